@@ -1,0 +1,205 @@
+"""CPU oracle for the Soft Anisotropic Diagrams hot path (numpy front end).
+
+TEST INFRASTRUCTURE ONLY.  This package wraps ``liboracle_sad.so`` (plain C, see
+``sad_oracle.c``).  Only ``tests/``, the smoke check in ``__graft_entry__`` and the
+CPU-baseline leg of ``bench.py`` may import it; the GPU library and its Python binding
+never do.
+
+Layouts follow the C file: ``sites`` float32[10, cap] (x, y, log_tau, r, c_r, c_g, c_b,
+u_x, u_y, a), ``lists`` uint32[H*W, K] (pixel-major), images [3, H, W].
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle_sad.so")
+_lib = None
+
+INVALID = 0xFFFFFFFF
+SCORE_F32, SCORE_F64 = 0, 1
+
+_f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+
+
+def _opt(ptype):
+    """ndpointer that also accepts None (a NULL pointer)."""
+    class _T(ptype):
+        @classmethod
+        def from_param(cls, obj):
+            if obj is None:
+                return None
+            return ptype.from_param(obj)
+    return _T
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"oracle library not built: {_LIB_PATH} (run oracle/build.py)")
+        L = C.CDLL(_LIB_PATH)
+        i64, i32, f32, f64, u64, u32 = C.c_int64, C.c_int, C.c_float, C.c_double, C.c_uint64, C.c_uint32
+        L.ora_site_derived.argtypes = [_f32p, i64, i64, f32, _f32p]
+        L.ora_score.argtypes = [_f32p, i64, i64, f32, f32, f32]
+        L.ora_score.restype = f32
+        L.ora_score_f64.argtypes = [_f32p, i64, i64, f64, f64, f64]
+        L.ora_score_f64.restype = f64
+        L.ora_brute_topk.argtypes = [i32, i32, i32, f32, _f32p, i64, i64, _opt(_i64p), i64, _u32p]
+        L.ora_seed.argtypes = [i32, i32, i32, f32, _f32p, i64, i64, _u32p]
+        L.ora_jump.argtypes = [i64, i32, i32]
+        L.ora_jump.restype = i32
+        L.ora_splitmix64.argtypes = [u64, u64]
+        L.ora_splitmix64.restype = u64
+        L.ora_inject_id.argtypes = [u64, u64, i64, i64, i32, i32, u32]
+        L.ora_inject_id.restype = u32
+        L.ora_prop_pass.argtypes = [i32, i32, i32, f32, _f32p, i64, i64, _u32p, _u32p, i32, i32,
+                                    u64, u64, _opt(_i64p), i64]
+        L.ora_render.argtypes = [i32, i32, i32, f32, _f32p, i64, i64, _u32p, i32, _f64p]
+        L.ora_query.argtypes = [i32, i32, i32, f32, _f32p, i64, i64, _u32p, _f32p, i64, _f64p]
+        L.ora_loss_grad.argtypes = [i32, i32, _f64p, _f32p, _opt(_f64p)]
+        L.ora_loss_grad.restype = f64
+        L.ora_render_bwd.argtypes = [i32, i32, i32, f32, _f32p, i64, i64, _u32p, _f64p,
+                                     _opt(_f32p), i32, _f64p, _opt(_f64p)]
+        L.ora_adam.argtypes = [i32, i32, _f64p, _f64p, _f64p, _f64p, i64, i64, _f64p, f64, f64,
+                               f64, i64]
+        L.ora_init_sites.argtypes = [i32, i32, _f32p, i64, f64, u64, f32, f32, _f32p, i64,
+                                     _opt(_f64p)]
+        L.ora_init_sites.restype = i64
+        _lib = L
+    return _lib
+
+
+def _sites(sites):
+    s = np.ascontiguousarray(sites, dtype=np.float32)
+    assert s.ndim == 2 and s.shape[0] == 10, s.shape
+    return s
+
+
+def _lists(lists, HW, K):
+    a = np.ascontiguousarray(lists, dtype=np.uint32).reshape(HW, K)
+    return a
+
+
+def default_scale(H, W):
+    """s = 1 / max(H, W) (Sec. 4.1), as a float32."""
+    return float(np.float32(1.0) / np.float32(max(H, W)))
+
+
+def site_derived(sites, n, s):
+    sites = _sites(sites)
+    out = np.zeros((n, 8), np.float32)
+    lib().ora_site_derived(sites, sites.shape[1], n, s, out)
+    return out
+
+
+def score(sites, i, s, X, Y):
+    sites = _sites(sites)
+    return float(lib().ora_score(sites, sites.shape[1], i, s, X, Y))
+
+
+def score_f64(sites, i, s, X, Y):
+    sites = _sites(sites)
+    return float(lib().ora_score_f64(sites, sites.shape[1], i, s, X, Y))
+
+
+def brute_topk(H, W, K, s, sites, n, pix=None):
+    sites = _sites(sites)
+    if pix is not None:
+        pix = np.ascontiguousarray(pix, dtype=np.int64)
+        npix = len(pix)
+    else:
+        npix = H * W
+    out = np.empty((npix, K), np.uint32)
+    lib().ora_brute_topk(H, W, K, s, sites, sites.shape[1], n, pix, npix, out)
+    return out
+
+
+def seed_lists(H, W, K, s, sites, n):
+    sites = _sites(sites)
+    out = np.empty((H * W, K), np.uint32)
+    lib().ora_seed(H, W, K, s, sites, sites.shape[1], n, out)
+    return out
+
+
+def jump(t, H, W):
+    return int(lib().ora_jump(t, H, W))
+
+
+def splitmix64(seed, k):
+    return int(lib().ora_splitmix64(seed, k))
+
+
+def inject_id(seed, t, P, p, J, j, n_slots):
+    return int(lib().ora_inject_id(seed, t, P, p, J, j, n_slots))
+
+
+def prop_pass(H, W, K, s, sites, n, lists, jump_, J, seed, t, pix=None):
+    sites = _sites(sites)
+    lin = _lists(lists, H * W, K)
+    if pix is not None:
+        pix = np.ascontiguousarray(pix, dtype=np.int64)
+        npix = len(pix)
+    else:
+        npix = H * W
+    out = np.empty((npix, K), np.uint32)
+    lib().ora_prop_pass(H, W, K, s, sites, sites.shape[1], n, lin, out, jump_, J, seed, t, pix, npix)
+    return out
+
+
+def render(H, W, K, s, sites, n, lists, mode=SCORE_F32):
+    sites = _sites(sites)
+    out = np.empty((3, H, W), np.float64)
+    lib().ora_render(H, W, K, s, sites, sites.shape[1], n, _lists(lists, H * W, K), mode, out)
+    return out
+
+
+def query(H, W, K, s, sites, n, lists, xy):
+    sites = _sites(sites)
+    xy = np.ascontiguousarray(xy, dtype=np.float32).reshape(-1, 2)
+    out = np.empty((len(xy), 3), np.float64)
+    lib().ora_query(H, W, K, s, sites, sites.shape[1], n, _lists(lists, H * W, K), xy, len(xy), out)
+    return out
+
+
+def loss_grad(img, target):
+    img = np.ascontiguousarray(img, dtype=np.float64)
+    target = np.ascontiguousarray(target, dtype=np.float32)
+    _, H, W = img.shape
+    g = np.empty_like(img)
+    L = lib().ora_loss_grad(H, W, img, target, g)
+    return float(L), g
+
+
+def render_bwd(H, W, K, s, sites, n, lists, grad_img, target=None, mode=SCORE_F32,
+               removal_delta=False):
+    sites = _sites(sites)
+    cap = sites.shape[1]
+    grad_img = np.ascontiguousarray(grad_img, dtype=np.float64)
+    grad = np.zeros((10, cap), np.float64)
+    rd = np.zeros(cap, np.float64) if removal_delta else None
+    tgt = np.ascontiguousarray(target, dtype=np.float32) if target is not None else None
+    lib().ora_render_bwd(H, W, K, s, sites, cap, n, _lists(lists, H * W, K), grad_img, tgt, mode,
+                         grad, rd)
+    return (grad, rd) if removal_delta else grad
+
+
+def adam(H, W, sites, grad, m, v, n, lr, b1, b2, eps, t):
+    """In place on float64 arrays sites/m/v [10, cap]."""
+    cap = sites.shape[1]
+    lr = np.ascontiguousarray(lr, dtype=np.float64)
+    lib().ora_adam(H, W, sites, np.ascontiguousarray(grad, np.float64), m, v, cap, n, lr,
+                   b1, b2, eps, t)
+
+
+def init_sites(target, N, lam, seed, log_tau0, r0, cap, return_keys=False):
+    target = np.ascontiguousarray(target, dtype=np.float32)
+    _, H, W = target.shape
+    sites = np.empty((10, cap), np.float32)
+    keys = np.empty(H * W, np.float64) if return_keys else None
+    k = lib().ora_init_sites(H, W, target, N, lam, seed, log_tau0, r0, sites, cap, keys)
+    return (sites, int(k), keys) if return_keys else (sites, int(k))

@@ -1,0 +1,607 @@
+/*
+ * sad_oracle.c -- plain, slow CPU oracle for the Soft Anisotropic Diagrams hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the reference the GPU library is checked
+ * against.  Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load it.  The GPU library never includes, links or calls anything here, and
+ * nothing here includes the GPU library's headers.
+ *
+ * Precision policy
+ *   - The per-site score l_i(x) is the quantity that decides integers (which sites
+ *     enter a top-K list).  The paper keeps sites in float32 (App. B.2, "Site
+ *     buffer"), so scores are evaluated in float32 in one fixed sequence of
+ *     correctly rounded operations (see score_f32 below); the two transcendentals
+ *     per site are evaluated in double and rounded once to float.
+ *   - Everything else (softmax blend, loss, gradients, removal delta, Adam,
+ *     initialisation keys) is evaluated in double.  Blend and gradients take the
+ *     float32 scores as their logits, so that the weights belong to the same scores
+ *     that chose the list; an all-double mode (SCORE_F64) exists for
+ *     finite-difference checks.
+ *
+ * Layouts (all host memory)
+ *   sites  : float[10][cap], parameter-major, order (x, y, log_tau, r, c_r, c_g, c_b,
+ *            u_x, u_y, a) as in App. B.2 "Site buffer".  A site is active iff x >= 0
+ *            and all ten values are finite.
+ *   lists  : uint32[H*W][K], pixel-major, one row of K site IDs per pixel (row-major
+ *            pixels, pixel id = i*W + j), 0xFFFFFFFF = empty slot.
+ *   images : double or float [3][H][W].
+ * Pixel (row i, column j) is evaluated at the point x = (j, i).
+ *
+ * Parity status of each function is stated in its comment; the pins live in tests/.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORA_INVALID 0xFFFFFFFFu
+enum { P_X, P_Y, P_LOGTAU, P_R, P_CR, P_CG, P_CB, P_UX, P_UY, P_A, NPARAM };
+
+/* ------------------------------------------------------------------------------ */
+/* Per-site quantities (Sec. 4.1, "Site Representation")                            */
+/* ------------------------------------------------------------------------------ */
+
+typedef struct {
+    int valid;
+    float x, y, log_tau, r, c[3], ux, uy, a;
+    /* float32 derived values (canonical) */
+    float tau, ep, em, kappa, g11, g12, g22;
+} site_t;
+
+static float prm(const float *sites, int64_t cap, int p, int64_t i) { return sites[(int64_t)p * cap + i]; }
+
+/* Sec. 4.1: G = e^a u u^T + e^-a v v^T with v the 90-degree rotation (-u_y, u_x) of u,
+ * so det G = |u|^4 and the eigenvalues along u and v are e^a |u|^2 and e^-a |u|^2.
+ * tau = exp(log_tau) (Sec. 4.1 list of parameters); kappa = tau * s folds the
+ * resolution scale s of d_mix into the temperature.  The three metric entries are
+ * formed in float32 in a fixed order. */
+static site_t site_load(const float *sites, int64_t cap, int64_t i, float s)
+{
+    site_t t;
+    memset(&t, 0, sizeof t);
+    t.x = prm(sites, cap, P_X, i);       t.y = prm(sites, cap, P_Y, i);
+    t.log_tau = prm(sites, cap, P_LOGTAU, i);
+    t.r = prm(sites, cap, P_R, i);
+    t.c[0] = prm(sites, cap, P_CR, i);   t.c[1] = prm(sites, cap, P_CG, i);
+    t.c[2] = prm(sites, cap, P_CB, i);
+    t.ux = prm(sites, cap, P_UX, i);     t.uy = prm(sites, cap, P_UY, i);
+    t.a = prm(sites, cap, P_A, i);
+    int finite = 1;
+    for (int p = 0; p < NPARAM; ++p) finite &= isfinite(prm(sites, cap, p, i)) ? 1 : 0;
+    /* App. B.2: an inactive site has x < 0, and every kernel skips it. */
+    t.valid = finite && t.x >= 0.0f;
+    if (!t.valid) return t;
+    t.tau = (float)exp((double)t.log_tau);
+    t.ep = (float)exp((double)t.a);
+    t.em = (float)exp(-(double)t.a);
+    t.kappa = t.tau * s;
+    float uxx = t.ux * t.ux, uyy = t.uy * t.uy, uxy = t.ux * t.uy;
+    t.g11 = fmaf(t.ep, uxx, t.em * uyy);
+    t.g22 = fmaf(t.ep, uyy, t.em * uxx);
+    t.g12 = (t.ep - t.em) * uxy;
+    if (!(t.kappa > 0.0f) || !isfinite(t.kappa) || !isfinite(t.g11) || !isfinite(t.g12) ||
+        !isfinite(t.g22))
+        t.valid = 0;
+    return t;
+}
+
+/* Exposed for pins: derived[i] = {valid, tau, e^a, e^-a, kappa, G11, G12, G22}. */
+void ora_site_derived(const float *sites, int64_t cap, int64_t n, float s, float *out)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        site_t t = site_load(sites, cap, i, s);
+        float *o = out + 8 * i;
+        o[0] = (float)t.valid; o[1] = t.tau; o[2] = t.ep; o[3] = t.em; o[4] = t.kappa;
+        o[5] = t.g11; o[6] = t.g12; o[7] = t.g22;
+    }
+}
+
+/* Sec. 4.1-4.2: l_i(x) = -tau_i d_mix(x,i) = tau_i s (r_i - ||x - p_i||_{G_i}).
+ * Canonical float32 sequence (every step correctly rounded, no contraction):
+ *   dx = X - p_x, dy = Y - p_y
+ *   t  = fma(2 G12, dy, G11 dx)          -> G11 dx + 2 G12 dy
+ *   q  = fma(t, dx, (G22 dy) dy)          -> d^T G d
+ *   q  = max(q, 0);  n = sqrt(q);  l = kappa (r - n);  l = l + 0  (signed zero -> +0)
+ * The list order is (l descending, ID ascending). */
+static float score_f32(const site_t *t, float X, float Y)
+{
+    float dx = X - t->x, dy = Y - t->y;
+    float tt = fmaf(2.0f * t->g12, dy, t->g11 * dx);
+    float q = fmaf(tt, dx, (t->g22 * dy) * dy);
+    if (!(q > 0.0f)) q = 0.0f;
+    float n = sqrtf(q);
+    float l = t->kappa * (t->r - n);
+    return l + 0.0f;
+}
+
+/* The same score entirely in double (finite-difference checks only). */
+static double score_f64(const site_t *t, double s, double X, double Y, double *n_out)
+{
+    double dx = X - (double)t->x, dy = Y - (double)t->y;
+    double ux = t->ux, uy = t->uy;
+    double ep = exp((double)t->a), em = exp(-(double)t->a);
+    double al = ux * dx + uy * dy;    /* u . d */
+    double be = -uy * dx + ux * dy;   /* v . d, v = (-u_y, u_x) */
+    double q = ep * al * al + em * be * be;
+    double n = sqrt(q > 0 ? q : 0);
+    if (n_out) *n_out = n;
+    return exp((double)t->log_tau) * s * ((double)t->r - n);
+}
+
+float ora_score(const float *sites, int64_t cap, int64_t id, float s, float X, float Y)
+{
+    site_t t = site_load(sites, cap, id, s);
+    return t.valid ? score_f32(&t, X, Y) : -INFINITY;
+}
+
+double ora_score_f64(const float *sites, int64_t cap, int64_t id, double s, double X, double Y)
+{
+    site_t t = site_load(sites, cap, id, (float)s);
+    return t.valid ? score_f64(&t, s, X, Y, NULL) : -INFINITY;
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Top-K selection (Sec. 4.3 update equation; storage Sec. 4.6)                     */
+/* ------------------------------------------------------------------------------ */
+
+typedef struct { float l; uint32_t id; } cand_t;
+
+/* (l descending, ID ascending): a strict total order on distinct IDs. */
+static int cand_cmp(const void *pa, const void *pb)
+{
+    const cand_t *a = (const cand_t *)pa, *b = (const cand_t *)pb;
+    if (a->l > b->l) return -1;
+    if (a->l < b->l) return 1;
+    if (a->id < b->id) return -1;
+    if (a->id > b->id) return 1;
+    return 0;
+}
+
+/* Sort candidates, drop repeated IDs (a set union in the update equation), keep the
+ * first K, pad with the empty sentinel. */
+static void select_topk(cand_t *c, int nc, int K, uint32_t *out)
+{
+    qsort(c, (size_t)nc, sizeof(cand_t), cand_cmp);
+    int k = 0;
+    for (int i = 0; i < nc && k < K; ++i) {
+        if (i > 0 && c[i].id == c[i - 1].id) continue;
+        out[k++] = c[i].id;
+    }
+    for (; k < K; ++k) out[k] = ORA_INVALID;
+}
+
+/* Exact top-K over every active site, for the pixels listed in pix (or all pixels if
+ * pix is NULL).  out: [npix][K].  Parity: pinned (k-d tree k-NN in the isotropic case,
+ * brute force by definition). */
+void ora_brute_topk(int H, int W, int K, float s, const float *sites, int64_t cap, int64_t n,
+                    const int64_t *pix, int64_t npix, uint32_t *out)
+{
+    site_t *st = (site_t *)malloc(sizeof(site_t) * (size_t)(n > 0 ? n : 1));
+    cand_t *c = (cand_t *)malloc(sizeof(cand_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) st[i] = site_load(sites, cap, i, s);
+    int64_t total = pix ? npix : (int64_t)H * W;
+    for (int64_t q = 0; q < total; ++q) {
+        int64_t p = pix ? pix[q] : q;
+        float X = (float)(p % W), Y = (float)(p / W);
+        int nc = 0;
+        for (int64_t i = 0; i < n; ++i)
+            if (st[i].valid) { c[nc].l = score_f32(&st[i], X, Y); c[nc].id = (uint32_t)i; ++nc; }
+        select_topk(c, nc, K, out + q * K);
+    }
+    free(st); free(c);
+}
+
+/* Initial lists (the seed pass of App. B.3): each active site is mapped to the pixel
+ * nearest its centre, (rint(p_y), rint(p_x)) clamped to the image, and each pixel's
+ * list is the top-K of the sites mapped to it.  Parity: pinned (brute force). */
+void ora_seed(int H, int W, int K, float s, const float *sites, int64_t cap, int64_t n,
+              uint32_t *lists)
+{
+    int64_t P = (int64_t)H * W;
+    for (int64_t p = 0; p < P * K; ++p) lists[p] = ORA_INVALID;
+    /* bucket sites by pixel (counting pass, then fill) */
+    int64_t *cnt = (int64_t *)calloc((size_t)P + 1, sizeof(int64_t));
+    int64_t *where = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    site_t *st = (site_t *)malloc(sizeof(site_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        st[i] = site_load(sites, cap, i, s);
+        where[i] = -1;
+        if (!st[i].valid) continue;
+        float fi = rintf(st[i].y), fj = rintf(st[i].x);
+        int64_t ii = fi < 0 ? 0 : (fi > (float)(H - 1) ? H - 1 : (int64_t)fi);
+        int64_t jj = fj < 0 ? 0 : (fj > (float)(W - 1) ? W - 1 : (int64_t)fj);
+        where[i] = ii * W + jj;
+        cnt[where[i]]++;
+    }
+    cand_t *c = (cand_t *)malloc(sizeof(cand_t) * (size_t)(n > 0 ? n : 1));
+    /* brute force per occupied pixel: gather its sites */
+    for (int64_t p = 0; p < P; ++p) {
+        if (!cnt[p]) continue;
+        float X = (float)(p % W), Y = (float)(p / W);
+        int nc = 0;
+        for (int64_t i = 0; i < n; ++i)
+            if (where[i] == p) { c[nc].l = score_f32(&st[i], X, Y); c[nc].id = (uint32_t)i; ++nc; }
+        select_topk(c, nc, K, lists + p * K);
+    }
+    free(cnt); free(where); free(st); free(c);
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Jump schedule and stochastic injection (Sec. 4.3; App. B.3 "Step encoding")      */
+/* ------------------------------------------------------------------------------ */
+
+/* Sec. 4.3: B = 2^ceil(log2 max(H,W)), s_t = max(1, B / 2^(min(t, log2 B - 1) + 1)). */
+int ora_jump(int64_t t, int H, int W)
+{
+    int m = H > W ? H : W;
+    int lb = 0;
+    while ((1LL << lb) < m) ++lb;               /* lb = ceil(log2 m) */
+    int64_t B = 1LL << lb;
+    int64_t e = t < (int64_t)(lb - 1) ? t : (int64_t)(lb - 1);
+    if (e < 0) e = 0;                           /* B = 1 (1x1 image): step 1 */
+    int64_t st = B >> (e + 1);
+    return (int)(st > 1 ? st : 1);
+}
+
+/* SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): output number k (0-based) of the stream
+ * seeded with `seed` is mix(seed + (k+1) * 0x9E3779B97F4A7C15), with the published
+ * finaliser mix(z) = z3 where z1 = (z ^ z>>30) * 0xBF58476D1CE4E5B9,
+ * z2 = (z1 ^ z1>>27) * 0x94D049BB133111EB, z3 = z2 ^ z2>>31. */
+uint64_t ora_splitmix64(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* Injected candidate j of pass t at pixel p: counter k = (t*P + p)*J + j, ID =
+ * floor(hi32 * n_slots / 2^32).  (The paper seeds an xorshift with step index and pixel
+ * ID; a stateless counter generator gives the same role with a reproducible stream.) */
+uint32_t ora_inject_id(uint64_t seed, uint64_t t, int64_t P, int64_t p, int J, int j,
+                       uint32_t n_slots)
+{
+    uint64_t k = ((uint64_t)t * (uint64_t)P + (uint64_t)p) * (uint64_t)J + (uint64_t)j;
+    uint64_t hi = ora_splitmix64(seed, k) >> 32;
+    return (uint32_t)((hi * (uint64_t)n_slots) >> 32);
+}
+
+/* One propagation pass (Sec. 4.3 update equation), Jacobi: every pixel reads the
+ * previous field `in` and writes `out`.  Candidates: the pixel's own list, the lists
+ * at (+-jump, 0) and (0, +-jump) that lie inside the image, and J injected IDs.  IDs
+ * that are empty, out of range or inactive are dropped; the rest are scored with the
+ * current sites and the top K of the set are kept.  If pix != NULL only those pixels
+ * are computed (out is then [npix][K]).  Parity: pinned by invariants
+ * (sortedness, uniqueness, monotonicity, convergence to brute force, dilation). */
+void ora_prop_pass(int H, int W, int K, float s, const float *sites, int64_t cap, int64_t n,
+                   const uint32_t *in, uint32_t *out, int jump, int J, uint64_t seed,
+                   uint64_t t, const int64_t *pix, int64_t npix)
+{
+    int64_t P = (int64_t)H * W;
+    site_t *st = (site_t *)malloc(sizeof(site_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) st[i] = site_load(sites, cap, i, s);
+    cand_t *c = (cand_t *)malloc(sizeof(cand_t) * (size_t)(5 * K + J + 1));
+    int64_t total = pix ? npix : P;
+    for (int64_t q = 0; q < total; ++q) {
+        int64_t p = pix ? pix[q] : q;
+        int64_t i = p / W, j = p % W;
+        float X = (float)j, Y = (float)i;
+        int64_t src[5]; int ns = 0;
+        src[ns++] = p;
+        if (j + jump < W) src[ns++] = p + jump;
+        if (j - jump >= 0) src[ns++] = p - jump;
+        if (i + jump < H) src[ns++] = p + (int64_t)jump * W;
+        if (i - jump >= 0) src[ns++] = p - (int64_t)jump * W;
+        int nc = 0;
+        for (int a = 0; a < ns; ++a)
+            for (int k = 0; k < K; ++k) {
+                uint32_t id = in[src[a] * K + k];
+                if (id == ORA_INVALID || (int64_t)id >= n || !st[id].valid) continue;
+                c[nc].l = score_f32(&st[id], X, Y); c[nc].id = id; ++nc;
+            }
+        for (int jj = 0; jj < J; ++jj) {
+            uint32_t id = n > 0 ? ora_inject_id(seed, t, P, p, J, jj, (uint32_t)n) : ORA_INVALID;
+            if (id == ORA_INVALID || (int64_t)id >= n || !st[id].valid) continue;
+            c[nc].l = score_f32(&st[id], X, Y); c[nc].id = id; ++nc;
+        }
+        select_topk(c, nc, K, out + q * K);
+    }
+    free(st); free(c);
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Soft blend (Sec. 4.2), loss (Sec. 6.1) and gradients (App. B.4)                   */
+/* ------------------------------------------------------------------------------ */
+
+enum { SCORE_F32 = 0, SCORE_F64 = 1 };
+
+typedef struct {
+    int nv;                 /* valid entries */
+    int idx[64];            /* site ids of the valid entries, list order */
+    double l[64], n[64];    /* logit and metric norm */
+    double w[64], e[64];    /* softmax weights, exp(l - max) */
+    double S, c[3];         /* sum of e, colour */
+} pix_t;
+
+/* Sec. 4.2: w_i = exp(l_i) / sum_j exp(l_j) over the valid entries of C(x) (computed
+ * with the maximum subtracted, App. B.4), c(x) = sum_i w_i c_i.  An empty list gives
+ * colour 0.  K <= 64. */
+static void blend_pixel(const site_t *st, int64_t n, const uint32_t *list, int K, double X,
+                        double Y, float s, int mode, pix_t *px)
+{
+    px->nv = 0; px->S = 0; px->c[0] = px->c[1] = px->c[2] = 0;
+    for (int k = 0; k < K; ++k) {
+        uint32_t id = list[k];
+        if (id == ORA_INVALID || (int64_t)id >= n || !st[id].valid) continue;
+        int v = px->nv++;
+        px->idx[v] = (int)id;
+        double nn;
+        double l64 = score_f64(&st[id], (double)s, X, Y, &nn);
+        px->n[v] = nn;
+        px->l[v] = mode == SCORE_F64 ? l64 : (double)score_f32(&st[id], (float)X, (float)Y);
+    }
+    if (!px->nv) return;
+    double m = px->l[0];
+    for (int v = 1; v < px->nv; ++v) if (px->l[v] > m) m = px->l[v];
+    for (int v = 0; v < px->nv; ++v) { px->e[v] = exp(px->l[v] - m); px->S += px->e[v]; }
+    for (int v = 0; v < px->nv; ++v) {
+        px->w[v] = px->e[v] / px->S;
+        for (int ch = 0; ch < 3; ++ch) px->c[ch] += px->w[v] * (double)st[px->idx[v]].c[ch];
+    }
+}
+
+/* Render every pixel from its list.  out: double[3][H][W].  Parity: pinned (partition
+ * of unity, convexity, K = N full softmax, hard Apollonius limit, scale invariance). */
+void ora_render(int H, int W, int K, float s, const float *sites, int64_t cap, int64_t n,
+                const uint32_t *lists, int mode, double *out)
+{
+    int64_t P = (int64_t)H * W;
+    site_t *st = (site_t *)malloc(sizeof(site_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) st[i] = site_load(sites, cap, i, s);
+    pix_t px;
+    for (int64_t p = 0; p < P; ++p) {
+        blend_pixel(st, n, lists + p * K, K, (double)(p % W), (double)(p / W), s, mode, &px);
+        for (int ch = 0; ch < 3; ++ch) out[ch * P + p] = px.c[ch];
+    }
+    free(st);
+}
+
+/* Sec. 4.2 evaluated at arbitrary points (random access, Sec. 6.6): the list is the
+ * one stored at the nearest pixel (rint, clamped), the scores are taken at the exact
+ * query point.  xy: float[M][2] in pixel units (x = column, y = row); out:
+ * double[M][3].  Parity: pinned (equals ora_render at integer points). */
+void ora_query(int H, int W, int K, float s, const float *sites, int64_t cap, int64_t n,
+               const uint32_t *lists, const float *xy, int64_t M, double *out)
+{
+    site_t *st = (site_t *)malloc(sizeof(site_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) st[i] = site_load(sites, cap, i, s);
+    pix_t px;
+    for (int64_t m = 0; m < M; ++m) {
+        float x = xy[2 * m], y = xy[2 * m + 1];
+        float fi = rintf(y), fj = rintf(x);
+        int64_t ii = !(fi > 0) ? 0 : (fi > (float)(H - 1) ? H - 1 : (int64_t)fi);
+        int64_t jj = !(fj > 0) ? 0 : (fj > (float)(W - 1) ? W - 1 : (int64_t)fj);
+        blend_pixel(st, n, lists + (ii * W + jj) * K, K, (double)x, (double)y, s, SCORE_F32, &px);
+        for (int ch = 0; ch < 3; ++ch) out[3 * m + ch] = px.c[ch];
+    }
+    free(st);
+}
+
+/* Sec. 6.1: L = E_x ||c(x) - I(x)||^2 = (1/P) sum_x sum_ch (c - I)^2 with P = H W;
+ * dL/dc(x) = (2/P)(c(x) - I(x)).  Returns L. */
+double ora_loss_grad(int H, int W, const double *img, const float *target, double *grad)
+{
+    int64_t P = (int64_t)H * W;
+    double L = 0;
+    for (int64_t i = 0; i < 3 * P; ++i) {
+        double d = img[i] - (double)target[i];
+        L += d * d;
+        if (grad) grad[i] = 2.0 * d / (double)P;
+    }
+    return L / (double)P;
+}
+
+/* Gradients of the loss w.r.t. every site parameter (App. B.4 lists position, log tau,
+ * r, colour, anisotropy direction and a; the formulas are derived here):
+ *   dL/dc_k        += w_k g
+ *   gamma_k         = w_k g . (c_k - c)            (= dL/dl_k)
+ *   dL/dlog_tau_k  += gamma_k l_k                   (dl/dlog_tau = l)
+ *   dL/dr_k        += gamma_k tau_k s
+ *   rho_k           = -gamma_k tau_k s / (2 n_k)   (= dL/dq_k), 0 if n_k = 0
+ *   with alpha = u.d, beta = v.d, d = x - p, v = (-u_y, u_x):
+ *   dL/dp          += -2 rho (e^a alpha u + e^-a beta v)
+ *   dL/da          += rho (e^a alpha^2 - e^-a beta^2)
+ *   dL/du_x        += 2 rho (e^a alpha d_x + e^-a beta d_y)
+ *   dL/du_y        += 2 rho (e^a alpha d_y - e^-a beta d_x)
+ * grad_img: double[3][H][W] = dL/dc(x).  grad: double[10][cap], accumulated (+=).
+ * If target and rdelta are non-NULL, also accumulates the removal delta of Sec. 4.5
+ * (see removal_delta below) divided by P into rdelta[cap].
+ * Parity: pinned (central finite differences in SCORE_F64 mode; shift and colour sum
+ * identities; removal delta against re-rendering without the site). */
+void ora_render_bwd(int H, int W, int K, float s, const float *sites, int64_t cap, int64_t n,
+                    const uint32_t *lists, const double *grad_img, const float *target,
+                    int mode, double *grad, double *rdelta)
+{
+    int64_t P = (int64_t)H * W;
+    site_t *st = (site_t *)malloc(sizeof(site_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) st[i] = site_load(sites, cap, i, s);
+    pix_t px;
+    for (int64_t p = 0; p < P; ++p) {
+        double X = (double)(p % W), Y = (double)(p / W);
+        blend_pixel(st, n, lists + p * K, K, X, Y, s, mode, &px);
+        if (!px.nv) continue;
+        double g[3];
+        for (int ch = 0; ch < 3; ++ch) g[ch] = grad_img[ch * P + p];
+        for (int v = 0; v < px.nv; ++v) {
+            const site_t *t = &st[px.idx[v]];
+            int64_t id = px.idx[v];
+            double w = px.w[v];
+            double gam = 0;
+            for (int ch = 0; ch < 3; ++ch) {
+                grad[(P_CR + ch) * cap + id] += w * g[ch];
+                gam += w * g[ch] * ((double)t->c[ch] - px.c[ch]);
+            }
+            double kap = exp((double)t->log_tau) * (double)s;
+            grad[P_LOGTAU * cap + id] += gam * px.l[v];
+            grad[P_R * cap + id] += gam * kap;
+            double nn = px.n[v];
+            if (nn > 0) {
+                double rho = -gam * kap / (2.0 * nn);
+                double ux = t->ux, uy = t->uy;
+                double dx = X - (double)t->x, dy = Y - (double)t->y;
+                double ep = exp((double)t->a), em = exp(-(double)t->a);
+                double al = ux * dx + uy * dy, be = -uy * dx + ux * dy;
+                grad[P_X * cap + id] += -2.0 * rho * (ep * al * ux + em * be * (-uy));
+                grad[P_Y * cap + id] += -2.0 * rho * (ep * al * uy + em * be * ux);
+                grad[P_A * cap + id] += rho * (ep * al * al - em * be * be);
+                grad[P_UX * cap + id] += 2.0 * rho * (ep * al * dx + em * be * dy);
+                grad[P_UY * cap + id] += 2.0 * rho * (ep * al * dy - em * be * dx);
+            }
+        }
+        if (target && rdelta) {
+            /* Sec. 4.5 removal delta: c' = colour with entry k removed and the remaining
+             * weights renormalised; Delta = ||c' - I||^2 - ||c - I||^2.  c' is formed
+             * as the softmax of the other entries (max of the others subtracted), which
+             * equals (c - w_k c_k) / (1 - w_k) but does not cancel when w_k -> 1.  With
+             * no other valid entry c' = 0 (an empty list renders 0). */
+            double base = 0;
+            for (int ch = 0; ch < 3; ++ch) {
+                double d = px.c[ch] - (double)target[ch * P + p];
+                base += d * d;
+            }
+            for (int v = 0; v < px.nv; ++v) {
+                double cp[3] = {0, 0, 0};
+                double m = -INFINITY;
+                for (int u = 0; u < px.nv; ++u) if (u != v && px.l[u] > m) m = px.l[u];
+                if (px.nv > 1) {
+                    double S = 0;
+                    for (int u = 0; u < px.nv; ++u) {
+                        if (u == v) continue;
+                        double e = exp(px.l[u] - m);
+                        S += e;
+                        for (int ch = 0; ch < 3; ++ch) cp[ch] += e * (double)st[px.idx[u]].c[ch];
+                    }
+                    for (int ch = 0; ch < 3; ++ch) cp[ch] /= S;
+                }
+                double rem = 0;
+                for (int ch = 0; ch < 3; ++ch) {
+                    double d = cp[ch] - (double)target[ch * P + p];
+                    rem += d * d;
+                }
+                rdelta[px.idx[v]] += (rem - base) / (double)P;
+            }
+        }
+    }
+    free(st);
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Adam with clamps (Sec. 5; Sec. 6.1 clamp ranges; Sec. 4.1 renormalisation of u)  */
+/* ------------------------------------------------------------------------------ */
+
+/* Textbook Adam (Kingma and Ba 2015), bias-corrected, per-parameter learning rates
+ * lr[10]; step t counts from 1.  Afterwards: x in [0, W-1], y in [0, H-1],
+ * log_tau in [2, 20], r in [1, 512], a in [-2, 2], colours in [0, 1], u renormalised
+ * (u = (1, 0) if |u| = 0).  Inactive sites are left untouched.  State in double.
+ * sites: double[10][cap] updated in place; m, v: double[10][cap]. */
+void ora_adam(int H, int W, double *sites, const double *grad, double *m, double *v,
+              int64_t cap, int64_t n, const double *lr, double b1, double b2, double eps,
+              int64_t t)
+{
+    double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(sites[P_X * cap + i] >= 0.0)) continue;
+        for (int p = 0; p < NPARAM; ++p) {
+            int64_t o = (int64_t)p * cap + i;
+            double g = grad[o];
+            m[o] = b1 * m[o] + (1.0 - b1) * g;
+            v[o] = b2 * v[o] + (1.0 - b2) * g * g;
+            double mh = m[o] / c1, vh = v[o] / c2;
+            sites[o] -= lr[p] * mh / (sqrt(vh) + eps);
+        }
+        double lo[NPARAM] = {0, 0, 2, 1, 0, 0, 0, -INFINITY, -INFINITY, -2};
+        double hi[NPARAM] = {(double)(W - 1), (double)(H - 1), 20, 512, 1, 1, 1, INFINITY,
+                             INFINITY, 2};
+        for (int p = 0; p < NPARAM; ++p) {
+            double *x = &sites[(int64_t)p * cap + i];
+            if (*x < lo[p]) *x = lo[p];
+            if (*x > hi[p]) *x = hi[p];
+        }
+        double ux = sites[P_UX * cap + i], uy = sites[P_UY * cap + i];
+        double nu = sqrt(ux * ux + uy * uy);
+        if (nu > 0) { sites[P_UX * cap + i] = ux / nu; sites[P_UY * cap + i] = uy / nu; }
+        else { sites[P_UX * cap + i] = 1; sites[P_UY * cap + i] = 0; }
+    }
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Gradient-weighted initialisation (Sec. 4.4)                                        */
+/* ------------------------------------------------------------------------------ */
+
+/* P_init(x) = (1 - lambda) |grad I(x)| / sum |grad I| + lambda / (H W), with
+ * |grad I| the Frobenius norm over RGB of central differences (edge-clamped).  N
+ * distinct pixels are drawn with probability proportional to P_init by the
+ * Efraimidis-Spirakis method (2006): pixel p gets key log(u_p) / P_init(p), u_p in
+ * (0,1) from SplitMix64 output number p of `seed`; the N largest keys win (ties to the
+ * lower pixel index).  Sites are written in increasing pixel order at the pixel
+ * centre, with the target colour there and the fixed defaults log_tau0, r0, u = (1,0),
+ * a = 0.  Slots n..cap-1 are set inactive (x = y = -1).  Returns the number of sites
+ * written.  keys_out (nullable) receives the H*W keys.  Parity: pinned (closed forms
+ * for the gradient map, N = H W, lambda = 1, selection without replacement). */
+static int key_cmp_desc(const void *pa, const void *pb)
+{
+    const double *a = (const double *)pa, *b = (const double *)pb;
+    if (a[0] > b[0]) return -1;
+    if (a[0] < b[0]) return 1;
+    return a[1] < b[1] ? -1 : (a[1] > b[1] ? 1 : 0);
+}
+
+int64_t ora_init_sites(int H, int W, const float *target, int64_t N, double lambda,
+                       uint64_t seed, float log_tau0, float r0, float *sites, int64_t cap,
+                       double *keys_out)
+{
+    int64_t P = (int64_t)H * W;
+    if (N > P) N = P;
+    if (N > cap) N = cap;
+    double *gm = (double *)malloc(sizeof(double) * (size_t)P);
+    double G = 0;
+    for (int64_t i = 0; i < H; ++i)
+        for (int64_t j = 0; j < W; ++j) {
+            int64_t jp = j + 1 < W ? j + 1 : W - 1, jm = j > 0 ? j - 1 : 0;
+            int64_t ip = i + 1 < H ? i + 1 : H - 1, im = i > 0 ? i - 1 : 0;
+            double acc = 0;
+            for (int ch = 0; ch < 3; ++ch) {
+                const float *I = target + ch * P;
+                double gx = 0.5 * ((double)I[i * W + jp] - (double)I[i * W + jm]);
+                double gy = 0.5 * ((double)I[ip * W + j] - (double)I[im * W + j]);
+                acc += gx * gx + gy * gy;
+            }
+            gm[i * W + j] = sqrt(acc);
+            G += gm[i * W + j];
+        }
+    double *kp = (double *)malloc(sizeof(double) * 2 * (size_t)P);
+    for (int64_t p = 0; p < P; ++p) {
+        double pr = lambda / (double)P + (G > 0 ? (1.0 - lambda) * gm[p] / G : 0.0);
+        double u = ((double)(ora_splitmix64(seed, (uint64_t)p) >> 32) + 0.5) / 4294967296.0;
+        double key = pr > 0 ? log(u) / pr : -INFINITY;
+        kp[2 * p] = key; kp[2 * p + 1] = (double)p;
+        if (keys_out) keys_out[p] = key;
+    }
+    qsort(kp, (size_t)P, 2 * sizeof(double), key_cmp_desc);
+    /* mark winners, then write them in raster order */
+    unsigned char *win = (unsigned char *)calloc((size_t)P, 1);
+    for (int64_t q = 0; q < N; ++q) win[(int64_t)kp[2 * q + 1]] = 1;
+    int64_t k = 0;
+    for (int64_t p = 0; p < P; ++p) {
+        if (!win[p]) continue;
+        float vals[NPARAM] = {(float)(p % W), (float)(p / W), log_tau0, r0,
+                              target[p], target[P + p], target[2 * P + p], 1.0f, 0.0f, 0.0f};
+        for (int q = 0; q < NPARAM; ++q) sites[(int64_t)q * cap + k] = vals[q];
+        ++k;
+    }
+    for (int64_t i = k; i < cap; ++i)
+        for (int q = 0; q < NPARAM; ++q)
+            sites[(int64_t)q * cap + i] = (q == P_X || q == P_Y) ? -1.0f : 0.0f;
+    free(gm); free(kp); free(win);
+    return k;
+}
