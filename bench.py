@@ -1,0 +1,206 @@
+"""Benchmark of the SAD hot path on one MI355X.
+
+One step = one training iteration of the 768x512 encode workload (N = 20 000 sites,
+K = 8, J = 4): propagation pass + forward blend + loss gradient + backward scatter +
+Adam, i.e. one ``sad_train_step``.  Steps run as replays of a recorded HIP graph (two
+iterations per graph; all counters live on the device).  Inputs are resident in HBM
+before the timed region.  Prints ONE JSON line.
+
+    python bench.py [--steps 100] [--warmup 10] [--gpus 1]
+"""
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+H, W, N_SITES, K, J = 512, 768, 20000, 8, 4
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(kernel, P, N, K):
+    """Bytes a kernel must move per launch, each unique byte once: list field reads and
+    writes, site records, images and gradients (neighbour-list re-reads and repeated
+    site gathers are cache traffic, not counted)."""
+    rec_prop, rec_fwd, rec_bwd = 32, 48, 64
+    if kernel == "prop":
+        return P * 8 * K + N * rec_prop
+    if kernel == "fwd_loss":
+        return P * (4 * K + 24) + N * rec_fwd
+    if kernel == "bwd":
+        return P * (4 * K + 12) + N * (rec_bwd + 40)
+    if kernel == "adam":
+        return N * (40 * 7 + 64)
+    return 0
+
+
+def cpu_baseline(target_np, sites_np, lists_np, budget_s):
+    """The CPU oracle (single thread) on whole steps of the same workload."""
+    import numpy as np
+
+    import oracle as O
+    s = O.default_scale(H, W)
+    lists = lists_np
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        lists = O.prop_pass(H, W, K, s, sites_np, N_SITES, lists, 1, J, 99, 1000 + steps)
+        img = O.render(H, W, K, s, sites_np, N_SITES, lists)
+        _, g = O.loss_grad(img, target_np)
+        O.render_bwd(H, W, K, s, sites_np, N_SITES, lists, g)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return H * W * steps / el / 1e6, steps, el
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-budget", type=float, default=12.0,
+                    help="seconds of single-thread oracle work for the CPU baseline (0: skip)")
+    ap.add_argument("--breakdown-steps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU design is described, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2604_21984_amd import _lib as S
+    from paper_2604_21984_amd.encode import EncodeConfig, Encoder
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    target_np = synth.image_encode(0, H, W)
+    target = torch.from_numpy(target_np).to(dev)
+    enc = Encoder(target, N_SITES, EncodeConfig(K=K, n_inject=J, seed=0))
+    # warm-up: eager iterations cover the long jumps of the schedule
+    for _ in range(max(args.warmup, 0)):
+        enc.step()
+    if enc.cur == 1:
+        enc.step()
+    torch.cuda.synchronize()
+    enc.capture()
+    enc.replay(2)
+    torch.cuda.synchronize()
+
+    # ---- timed region: K iterations = K/2 graph replays -----------------------------
+    pairs = max(1, (args.steps + 1) // 2)
+    steps = 2 * pairs
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    enc.replay(pairs)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    ms_per_step = ms / steps
+    mpix = H * W * steps / (ms / 1e3) / 1e6
+    loss = enc.loss.item()
+    psnr = enc.psnr()
+
+    # ---- per-kernel breakdown: the same kernels launched one by one, timed with events
+    # on their stream; a spin kernel first keeps the queue ahead of the host.
+    P = H * W
+    names = ["prop", "fwd_loss", "bwd", "adam"]
+    acc = {k: 0.0 for k in names}
+    nb = args.breakdown_steps
+    img = enc.img
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for _ in range(nb)]
+    st = enc.state.cpu()
+    torch.cuda.synchronize()
+    torch.cuda._sleep(int(2e8))
+    for it in range(nb):
+        a, b = enc.lists[enc.cur], enc.lists[1 - enc.cur]
+        t_pass = int(st[0]) + it
+        E = ev[it]
+        E[0].record(stream)
+        S.propagate_topk(img, enc.rec, a, b, S.jump_step(t_pass, H, W), J, 7, t_pass)
+        E[1].record(stream)
+        S.render_fwd_loss(img, enc.rec, b, enc.target, enc.grad_img, None, enc.loss)
+        E[2].record(stream)
+        S.render_bwd(img, enc.rec, b, enc.grad_img, enc.grad)
+        E[3].record(stream)
+        S.adam_step(img, enc.sites, enc.grad, enc.m, enc.v, enc.adam, int(st[1]) + it + 1, enc.rec,
+                    zero_grad=True)
+        E[4].record(stream)
+        enc.cur = 1 - enc.cur
+    torch.cuda.synchronize()
+    for it in range(nb):
+        for k, name in enumerate(names):
+            acc[name] += ev[it][k].elapsed_time(ev[it][k + 1])
+    per_kernel_us = {k: 1e3 * v / nb for k, v in acc.items()}
+    dom = max(per_kernel_us, key=per_kernel_us.get)
+    dom_bytes = algorithmic_bytes(dom, P, N_SITES, K)
+    achieved = dom_bytes / (per_kernel_us[dom] * 1e-6) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "algorithmic_bytes": dom_bytes}
+    step_bytes = sum(algorithmic_bytes(k, P, N_SITES, K) for k in names)
+
+    result = {
+        "metric": "Mpix/s fwd+bwd (topK prop+blend, K=8, 768x512)",
+        "value": round(mpix, 1),
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "encode 768x512, N=20000 sites, K=8, J=4, one propagation pass "
+                               "+ forward + MSE gradient + backward + Adam per step, HIP graph",
+                   "H": H, "W": W, "n_sites": N_SITES, "K": K, "J": J},
+        "roofline": roofline,
+        "per_kernel_us": {k: round(v, 2) for k, v in per_kernel_us.items()},
+        "step_algorithmic_bytes": step_bytes,
+        "step_hbm_frac": round(step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "loss": loss,
+        "psnr_db": round(psnr, 3),
+        "wall_s": round(wall, 4),
+    }
+
+    if args.cpu_budget > 0:
+        lists_np = enc.topk.cpu().numpy()
+        lists_np = (lists_np.astype(np.int64) & 0xFFFFFFFF).reshape(K // 4, P, 4)
+        lists_np = lists_np.transpose(1, 0, 2).reshape(P, K).astype(np.uint32)
+        sites_np = enc.sites.cpu().numpy()
+        v, n, el = cpu_baseline(target_np, sites_np, lists_np, args.cpu_budget)
+        cpu = "unknown"
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        cpu = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+        result["cpu_baseline"] = {"value": round(v, 3), "unit": "Mpix/s", "cores": 1,
+                                  "kind": "oracle",
+                                  "sample": f"{n} whole steps (pass + fwd + loss + bwd) of the "
+                                            f"same 768x512 workload in {el:.1f} s, single thread",
+                                  "cpu": cpu, "host_threads": os.cpu_count(),
+                                  "platform": platform.machine()}
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

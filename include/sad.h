@@ -1,0 +1,223 @@
+/*
+ * sad.h -- C ABI of the Soft Anisotropic Diagrams (SAD) hot path on AMD MI355X (gfx950).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers are DEVICE pointers unless marked "host".  The caller owns every buffer
+ *     (inputs, outputs and scratch); the library allocates nothing, never synchronises
+ *     and never reads device memory on the host, so every call may be recorded into a
+ *     HIP graph.  Work is enqueued on `stream` (a hipStream_t; NULL = default stream)
+ *     and the call returns.
+ *   - Arguments are validated on the host before anything is enqueued: a bad argument
+ *     returns SAD_ERR_INVALID_ARGUMENT or SAD_ERR_UNSUPPORTED and enqueues nothing.  A
+ *     launch failure returns SAD_ERR_DEVICE.  sad_last_error() returns a message for
+ *     the last failing call on the calling thread.  Faults inside a kernel surface at
+ *     the caller's next synchronisation.
+ *   - Site buffer `sites`: float[10][cap], parameter-major, in the order
+ *     (x, y, log_tau, r, c_r, c_g, c_b, u_x, u_y, a) of App. B.2 ("Site buffer").  Slot
+ *     i is site ID i.  A site is active iff x >= 0 and all ten values are finite
+ *     (inactive sites have x = y = -1); every kernel skips inactive sites.
+ *   - Derived-record buffer `rec`: float[n_slots][SAD_REC_FLOATS], written by
+ *     sad_prepare_sites from `sites`; every image-space call reads `rec`, so call
+ *     sad_prepare_sites after any change of `sites` (sad_adam_step can refresh it).
+ *   - Top-K list field `topk`: uint32[K/4][H*W][4] ("two 4-channel textures" for
+ *     K = 8, App. B.2): plane k/4, pixel p = i*W + j, lane k%4.  Each pixel's list is
+ *     sorted by (score descending, ID ascending) and padded with SAD_INVALID_ID.
+ *   - Images: float[3][H][W] (channel-major).  Pixel (row i, column j) is the point
+ *     (x, y) = (j, i).
+ *   - The score of site i at point x (Sec. 4.1-4.2) is
+ *        l_i(x) = tau_i s (r_i - ||x - p_i||_{G_i}),  G_i = e^a u u^T + e^-a v v^T,
+ *     v = (-u_y, u_x), tau = exp(log_tau), s = score scale; it is evaluated in float32
+ *     in one fixed sequence of correctly rounded operations, so the lists are
+ *     reproducible bit for bit.
+ */
+#ifndef SAD_H
+#define SAD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SAD_OK = 0,
+    SAD_ERR_INVALID_ARGUMENT = 1,
+    SAD_ERR_UNSUPPORTED = 2,
+    SAD_ERR_WORKSPACE = 3,
+    SAD_ERR_DEVICE = 4
+} sad_status;
+
+#define SAD_NPARAM 10
+#define SAD_REC_FLOATS 16
+#define SAD_INVALID_ID 0xFFFFFFFFu
+#define SAD_MAX_K 32
+
+/* One image and its site set.  K must be a multiple of 4 in [4, SAD_MAX_K].
+ * n_slots <= cap: site IDs are 0..n_slots-1 (injected IDs are drawn from this range).
+ * score_scale: s of Sec. 4.1; 0 selects 1/max(H, W). */
+typedef struct {
+    int32_t H, W;
+    int32_t K;
+    int32_t n_slots;
+    int64_t cap;
+    float score_scale;
+} sad_image;
+
+/* Adam hyper-parameters (Sec. 5: per-parameter base learning rates, fixed betas and
+ * epsilon).  lr[p] is the learning rate of parameter p in the site order above. */
+typedef struct {
+    float lr[SAD_NPARAM];
+    float beta1, beta2, eps;
+} sad_adam_params;
+
+/* ---- a0: per-site derived values (the "pack" kernel of App. B.2 / B.7) ----------
+ * rec[i] = {x, y, G11, 2*G12, G22, kappa, r, valid, c_r, c_g, c_b, u_x, u_y, e^a,
+ *           e^-a, tau} for every slot i < n_slots, with tau = f32(exp(double log_tau)),
+ * e^{+-a} = f32(exp(+-double a)), kappa = tau * s, G11 = fma(e^a, u_x^2, e^-a u_y^2),
+ * G22 = fma(e^a, u_y^2, e^-a u_x^2), G12 = (e^a - e^-a) u_x u_y; valid = 1 for an
+ * active site with finite kappa > 0 and finite G, else 0 (the record is then ignored).
+ * sites: [10][cap] (read); rec: [n_slots][16] (written). */
+sad_status sad_prepare_sites(const sad_image *img, const float *sites, float *rec, void *stream);
+
+/* ---- a2: list initialisation (the seed pass of App. B.3) --------------------------
+ * Clears every slot to SAD_INVALID_ID, then maps each valid site to the pixel
+ * (rint(y), rint(x)) clamped to the image; a pixel's list becomes the top K of the
+ * sites mapped to it.  Deterministic.  scratch: uint64[H*W] (contents undefined after;
+ * the K*4 bytes per pixel of a second list field are enough). */
+sad_status sad_seed_topk(const sad_image *img, const float *rec, uint32_t *topk,
+                         uint64_t *scratch, void *stream);
+
+/* ---- a3: one propagation pass (Sec. 4.3 update equation) --------------------------
+ * Jacobi: reads topk_in everywhere, writes topk_out (must not alias).  Candidate set of
+ * pixel p: its own list, the lists at (+-jump, 0) and (0, +-jump) that lie inside the
+ * image, and n_inject injected IDs; draw j is ID floor(hi32 * n_slots / 2^32) of
+ * SplitMix64 output number (pass_index * H*W + p) * n_inject + j of the stream seeded by
+ * `seed`.  Empty, out-of-range and invalid IDs are dropped, repeated IDs collapse, and
+ * the top K by (score descending, ID ascending) are written.  jump >= 1,
+ * 0 <= n_inject <= 16. */
+sad_status sad_propagate_topk(const sad_image *img, const float *rec, const uint32_t *topk_in,
+                              uint32_t *topk_out, int32_t jump, int32_t n_inject, uint64_t seed,
+                              uint64_t pass_index, void *stream);
+
+/* Jump step of refresh t (Sec. 4.3): B = 2^ceil(log2 max(H,W)),
+ * s_t = max(1, B / 2^(min(t, log2 B - 1) + 1)).  Host function. */
+int32_t sad_jump_step(int64_t t, int32_t H, int32_t W);
+
+/* ---- a4: forward blend (Sec. 4.2) -------------------------------------------------
+ * out[ch][i][j] = sum_k w_k c_k over the valid entries of the pixel's list, w = softmax
+ * of the scores with the maximum subtracted (App. B.4); an empty list gives 0.
+ * out: float[3][H][W] (written). */
+sad_status sad_render_fwd(const sad_image *img, const float *rec, const uint32_t *topk,
+                          float *out, void *stream);
+
+/* ---- a5: loss gradient (Sec. 6.1) -------------------------------------------------
+ * L = (1/P) sum_x ||c(x) - I(x)||^2 with P = H*W; grad = dL/dc = (2/P)(c - I).
+ * img, target: float[3][H][W]; grad: float[3][H][W] (written, may alias img);
+ * loss: nullable float scalar, L is ADDED to it (caller zeroes). */
+sad_status sad_loss_grad(const sad_image *img, const float *rendered, const float *target,
+                         float *grad, float *loss, void *stream);
+
+/* ---- a4 + a5 fused: forward blend and loss gradient in one pass ------------------
+ * As sad_render_fwd followed by sad_loss_grad, without storing the image unless
+ * rendered != NULL: grad_img = (2/P)(c - I); L is ADDED to *loss if loss != NULL.
+ * target, grad_img (written), rendered (nullable, written): float[3][H][W]. */
+sad_status sad_render_fwd_loss(const sad_image *img, const float *rec, const uint32_t *topk,
+                               const float *target, float *rendered, float *grad_img, float *loss,
+                               void *stream);
+
+/* ---- a6: backward scatter (App. B.4; Sec. 4.8 tiled pre-reduction) ---------------
+ * Recomputes the blend weights from rec and topk (nothing is stored by the forward)
+ * and ACCUMULATES (+=) dL/dsite into grad_sites[10][cap] (caller zeroes) for
+ * dL/dc = grad_img [3][H][W]:
+ *   dc_k += w_k g;  gamma_k = w_k g.(c_k - c);  dlog_tau_k += gamma_k l_k;
+ *   dr_k += gamma_k kappa_k;  with rho = -gamma kappa / (2 n) (0 when n = 0),
+ *   alpha = u.d, beta = v.d, d = x - p:  dp += -2 rho (e^a alpha u + e^-a beta v),
+ *   da += rho (e^a alpha^2 - e^-a beta^2), du_x += 2 rho (e^a alpha d_x + e^-a beta d_y),
+ *   du_y += 2 rho (e^a alpha d_y - e^-a beta d_x).
+ * If removal_delta != NULL (target then required) it also accumulates the removal
+ * delta of Sec. 4.5, (||c'_k - I||^2 - ||c - I||^2) / P with c'_k the blend without
+ * entry k, into removal_delta[cap].  Partial sums of a pixel tile are combined in LDS
+ * and flushed with one float atomic per (site, parameter, tile), so the order of
+ * additions -- and the last bits of the result -- vary from run to run. */
+sad_status sad_render_bwd(const sad_image *img, const float *rec, const uint32_t *topk,
+                          const float *grad_img, const float *target, float *grad_sites,
+                          float *removal_delta, void *stream);
+
+/* ---- a8: Adam step (Sec. 5; clamps of Sec. 6.1) ----------------------------------
+ * For every active slot: bias-corrected Adam on the ten parameters with gradient
+ * grad[10][cap], moments m, v [10][cap] (updated), step >= 1; then clamp x to
+ * [0, W-1], y to [0, H-1], log_tau to [2, 20], r to [1, 512], a to [-2, 2], colours to
+ * [0, 1] and renormalise u (u = (1, 0) if |u| = 0).  Inactive slots are untouched.  If
+ * rec != NULL the derived records of the updated sites are rewritten as by
+ * sad_prepare_sites.  With flags & SAD_ADAM_ZERO_GRAD the gradient is cleared after it
+ * has been read (the next backward accumulates into zeros).  params: host. */
+#define SAD_ADAM_ZERO_GRAD 1u
+sad_status sad_adam_step(const sad_image *img, float *sites, float *grad, float *m, float *v,
+                         const sad_adam_params *params, int64_t step, float *rec, uint32_t flags,
+                         void *stream);
+
+/* ---- a9: random access (Sec. 6.6: render from cached lists) -----------------------
+ * For each query point xy[q] = (x, y) (float32, pixel units, x = column): the list of
+ * the nearest pixel (rint, clamped to the image) blended with scores evaluated at the
+ * exact point.  xy: float[M][2]; out: float[M][3] (written). */
+sad_status sad_query_points(const sad_image *img, const float *rec, const uint32_t *topk,
+                            const float *xy, int64_t M, float *out, void *stream);
+
+/* ---- initialisation (Sec. 4.4) ----------------------------------------------------
+ * P_init(x) = (1 - lambda) |grad I(x)| / sum |grad I| + lambda / (H W), |grad I| the
+ * Frobenius norm over RGB of edge-clamped central differences.  Draws n_sites distinct
+ * pixels by Efraimidis-Spirakis keys log(u_p) / P_init(p) (u_p from SplitMix64 output p
+ * of `seed`, mapped to (0,1) as (hi32 + 0.5) / 2^32; the n_sites largest keys win, ties
+ * to the lower pixel) and writes them in raster order at the pixel centres, with the
+ * target colour there, log_tau = log_tau0, r = r0, u = (1, 0), a = 0.  Slots
+ * n_sites..cap-1 are made inactive.  Requires n_sites <= min(H*W, cap) and
+ * img->n_slots == cap is not required.  target: float[3][H][W]; sites: [10][cap]
+ * (written).  workspace: device scratch of *workspace_bytes; call with workspace =
+ * NULL to query the size. */
+sad_status sad_init_sites(const sad_image *img, const float *target, int32_t n_sites,
+                          float lambda, uint64_t seed, float log_tau0, float r0, float *sites,
+                          void *workspace, size_t *workspace_bytes, void *stream);
+
+/* ---- a8: one training iteration with device-resident counters ----------------------
+ * Counters live in device memory so that a recorded HIP graph replays correctly: every
+ * replay reads and advances them on the device. */
+typedef struct {
+    int64_t pass;      /* refresh counter t: jump s_t (Sec. 4.3) and injection stream */
+    int64_t adam_step; /* Adam steps taken so far */
+} sad_step_state;
+
+typedef struct {
+    int32_t n_inject;   /* J injected IDs per pixel and pass (Sec. 6.1: 4) */
+    int32_t fixed_jump; /* <= 0: the Sec. 4.3 schedule of state->pass; > 0: this jump */
+    uint64_t seed;      /* injection stream */
+    sad_adam_params adam;
+} sad_train_config;
+
+/* One iteration (Sec. 5: no host work inside the loop), enqueued as:
+ *   1. propagation pass topk_in -> topk_out with pass index state->pass;
+ *   2. forward blend with topk_out fused with the loss gradient: grad_img [3][H][W]
+ *      = dL/dc, the image itself into rendered [3][H][W] if rendered != NULL, L written
+ *      to *loss if loss != NULL;
+ *   3. the backward scatter into grad_sites [10][cap], which must be zero on entry;
+ *   4. Adam step number state->adam_step + 1 (clamps, renormalised u), rec refreshed,
+ *      grad_sites cleared again (ready for the next call);
+ *   5. state->pass += 1, state->adam_step += 1.
+ * rec must describe `sites` on entry (sad_prepare_sites); after the call topk_out holds
+ * the current list field (pass the two list buffers in swapped order next time).
+ * cfg: host; state: device. */
+sad_status sad_train_step(const sad_image *img, const sad_train_config *cfg, const float *target,
+                          float *sites, float *rec, const uint32_t *topk_in, uint32_t *topk_out,
+                          float *grad_sites, float *adam_m, float *adam_v, float *rendered,
+                          float *grad_img, float *loss, sad_step_state *state, void *stream);
+
+/* ---- diagnostics ------------------------------------------------------------------ */
+const char *sad_status_string(sad_status s);
+const char *sad_last_error(void);
+/* Library version string (host). */
+const char *sad_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SAD_H */

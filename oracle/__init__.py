@@ -64,7 +64,7 @@ def lib():
         L.ora_loss_grad.argtypes = [i32, i32, _f64p, _f32p, _opt(_f64p)]
         L.ora_loss_grad.restype = f64
         L.ora_render_bwd.argtypes = [i32, i32, i32, f32, _f32p, i64, i64, _u32p, _f64p,
-                                     _opt(_f32p), i32, _f64p, _opt(_f64p)]
+                                     _opt(_f32p), i32, _f64p, _opt(_f64p), _opt(_f64p)]
         L.ora_adam.argtypes = [i32, i32, _f64p, _f64p, _f64p, _f64p, i64, i64, _f64p, f64, f64,
                                f64, i64]
         L.ora_init_sites.argtypes = [i32, i32, _f32p, i64, f64, u64, f32, f32, _f32p, i64,
@@ -176,16 +176,24 @@ def loss_grad(img, target):
 
 
 def render_bwd(H, W, K, s, sites, n, lists, grad_img, target=None, mode=SCORE_F32,
-               removal_delta=False):
+               removal_delta=False, abs_sum=False):
+    """Gradient [10, cap]; with removal_delta=True also the removal delta [cap]; with
+    abs_sum=True also the sum of absolute per-pixel terms [10, cap] (returned last)."""
     sites = _sites(sites)
     cap = sites.shape[1]
     grad_img = np.ascontiguousarray(grad_img, dtype=np.float64)
     grad = np.zeros((10, cap), np.float64)
     rd = np.zeros(cap, np.float64) if removal_delta else None
+    ga = np.zeros((10, cap), np.float64) if abs_sum else None
     tgt = np.ascontiguousarray(target, dtype=np.float32) if target is not None else None
     lib().ora_render_bwd(H, W, K, s, sites, cap, n, _lists(lists, H * W, K), grad_img, tgt, mode,
-                         grad, rd)
-    return (grad, rd) if removal_delta else grad
+                         grad, rd, ga)
+    out = [grad]
+    if removal_delta:
+        out.append(rd)
+    if abs_sum:
+        out.append(ga)
+    return out[0] if len(out) == 1 else tuple(out)
 
 
 def adam(H, W, sites, grad, m, v, n, lr, b1, b2, eps, t):

@@ -415,12 +415,20 @@ double ora_loss_grad(int H, int W, const double *img, const float *target, doubl
  *   dL/du_y        += 2 rho (e^a alpha d_y - e^-a beta d_x)
  * grad_img: double[3][H][W] = dL/dc(x).  grad: double[10][cap], accumulated (+=).
  * If target and rdelta are non-NULL, also accumulates the removal delta of Sec. 4.5
- * (see removal_delta below) divided by P into rdelta[cap].
+ * (see removal_delta below) divided by P into rdelta[cap].  If gabs is non-NULL it
+ * accumulates the absolute values of the per-pixel terms of every sum ([10][cap]): the
+ * scale against which the rounding of a float32 evaluation of that sum is measured.
  * Parity: pinned (central finite differences in SCORE_F64 mode; shift and colour sum
  * identities; removal delta against re-rendering without the site). */
+static void acc2(double *grad, double *gabs, int64_t o, double v)
+{
+    grad[o] += v;
+    if (gabs) gabs[o] += fabs(v);
+}
+
 void ora_render_bwd(int H, int W, int K, float s, const float *sites, int64_t cap, int64_t n,
                     const uint32_t *lists, const double *grad_img, const float *target,
-                    int mode, double *grad, double *rdelta)
+                    int mode, double *grad, double *rdelta, double *gabs)
 {
     int64_t P = (int64_t)H * W;
     site_t *st = (site_t *)malloc(sizeof(site_t) * (size_t)(n > 0 ? n : 1));
@@ -438,12 +446,12 @@ void ora_render_bwd(int H, int W, int K, float s, const float *sites, int64_t ca
             double w = px.w[v];
             double gam = 0;
             for (int ch = 0; ch < 3; ++ch) {
-                grad[(P_CR + ch) * cap + id] += w * g[ch];
+                acc2(grad, gabs, (P_CR + ch) * cap + id, w * g[ch]);
                 gam += w * g[ch] * ((double)t->c[ch] - px.c[ch]);
             }
             double kap = exp((double)t->log_tau) * (double)s;
-            grad[P_LOGTAU * cap + id] += gam * px.l[v];
-            grad[P_R * cap + id] += gam * kap;
+            acc2(grad, gabs, P_LOGTAU * cap + id, gam * px.l[v]);
+            acc2(grad, gabs, P_R * cap + id, gam * kap);
             double nn = px.n[v];
             if (nn > 0) {
                 double rho = -gam * kap / (2.0 * nn);
@@ -451,11 +459,11 @@ void ora_render_bwd(int H, int W, int K, float s, const float *sites, int64_t ca
                 double dx = X - (double)t->x, dy = Y - (double)t->y;
                 double ep = exp((double)t->a), em = exp(-(double)t->a);
                 double al = ux * dx + uy * dy, be = -uy * dx + ux * dy;
-                grad[P_X * cap + id] += -2.0 * rho * (ep * al * ux + em * be * (-uy));
-                grad[P_Y * cap + id] += -2.0 * rho * (ep * al * uy + em * be * ux);
-                grad[P_A * cap + id] += rho * (ep * al * al - em * be * be);
-                grad[P_UX * cap + id] += 2.0 * rho * (ep * al * dx + em * be * dy);
-                grad[P_UY * cap + id] += 2.0 * rho * (ep * al * dy - em * be * dx);
+                acc2(grad, gabs, P_X * cap + id, -2.0 * rho * (ep * al * ux + em * be * (-uy)));
+                acc2(grad, gabs, P_Y * cap + id, -2.0 * rho * (ep * al * uy + em * be * ux));
+                acc2(grad, gabs, P_A * cap + id, rho * (ep * al * al - em * be * be));
+                acc2(grad, gabs, P_UX * cap + id, 2.0 * rho * (ep * al * dx + em * be * dy));
+                acc2(grad, gabs, P_UY * cap + id, 2.0 * rho * (ep * al * dy - em * be * dx));
             }
         }
         if (target && rdelta) {

@@ -1,0 +1,256 @@
+"""ctypes binding of ``libsad.so`` -- the C ABI declared in ``include/sad.h``.
+
+Argument marshalling only: every function takes torch tensors (device memory owned by
+the caller), checks dtype / device / size, and passes raw pointers, sizes and the
+current HIP stream to the entry point of the same name.  All computation happens in
+the library's kernels.  If the library is missing this module raises at import time:
+there is no fallback path.
+"""
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsad.so")
+
+NPARAM = 10
+REC_FLOATS = 16
+INVALID_ID = 0xFFFFFFFF
+MAX_K = 32
+
+
+class SadError(RuntimeError):
+    pass
+
+
+class SadImage(C.Structure):
+    _fields_ = [("H", C.c_int32), ("W", C.c_int32), ("K", C.c_int32), ("n_slots", C.c_int32),
+                ("cap", C.c_int64), ("score_scale", C.c_float)]
+
+
+class SadAdamParams(C.Structure):
+    _fields_ = [("lr", C.c_float * NPARAM), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float)]
+
+
+class SadTrainConfig(C.Structure):
+    _fields_ = [("n_inject", C.c_int32), ("fixed_jump", C.c_int32), ("seed", C.c_uint64),
+                ("adam", SadAdamParams)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    P, I32, I64, U64, F32, SZ = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_float, C.c_size_t
+    IMG = C.POINTER(SadImage)
+    sig = {
+        "sad_prepare_sites": [IMG, P, P, P],
+        "sad_seed_topk": [IMG, P, P, P, P],
+        "sad_propagate_topk": [IMG, P, P, P, I32, I32, U64, U64, P],
+        "sad_render_fwd": [IMG, P, P, P, P],
+        "sad_loss_grad": [IMG, P, P, P, P, P],
+        "sad_render_bwd": [IMG, P, P, P, P, P, P, P],
+        "sad_adam_step": [IMG, P, P, P, P, C.POINTER(SadAdamParams), I64, P, C.c_uint32, P],
+        "sad_render_fwd_loss": [IMG, P, P, P, P, P, P, P],
+        "sad_query_points": [IMG, P, P, P, I64, P, P],
+        "sad_init_sites": [IMG, P, I32, F32, U64, F32, F32, P, P, C.POINTER(SZ), P],
+        "sad_train_step": [IMG, C.POINTER(SadTrainConfig), P, P, P, P, P, P, P, P, P, P, P, P, P],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int
+    L.sad_jump_step.argtypes = [I64, I32, I32]
+    L.sad_jump_step.restype = I32
+    for name in ("sad_status_string",):
+        getattr(L, name).argtypes = [C.c_int]
+        getattr(L, name).restype = C.c_char_p
+    L.sad_last_error.argtypes = []
+    L.sad_last_error.restype = C.c_char_p
+    L.sad_version.argtypes = []
+    L.sad_version.restype = C.c_char_p
+    return L
+
+
+lib = _load()
+
+
+def _check(status, name):
+    if status != 0:
+        msg = lib.sad_last_error().decode(errors="replace")
+        raise SadError(f"{name}: {lib.sad_status_string(status).decode()} ({status}): {msg}")
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype, numel=None, name="tensor"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise TypeError(f"{name} must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name}: needs at least {numel} elements, has {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def image(H, W, K, n_slots, cap=None, score_scale=0.0):
+    """Image descriptor (sad_image)."""
+    return SadImage(int(H), int(W), int(K), int(n_slots), int(cap if cap is not None else n_slots),
+                    float(score_scale))
+
+
+def prepare_sites(img, sites, rec):
+    _check(lib.sad_prepare_sites(C.byref(img), _ptr(sites, torch.float32, NPARAM * img.cap, "sites"),
+                                 _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"), _stream()),
+           "sad_prepare_sites")
+
+
+def seed_topk(img, rec, topk, scratch):
+    P = img.H * img.W
+    if scratch.numel() * scratch.element_size() < 8 * P:
+        raise ValueError("seed_topk: scratch needs 8 bytes per pixel")
+    _check(lib.sad_seed_topk(C.byref(img), _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                             _ptr(topk, torch.int32, img.K * P, "topk"),
+                             _ptr(scratch, scratch.dtype, None, "scratch"), _stream()),
+           "sad_seed_topk")
+
+
+def propagate_topk(img, rec, topk_in, topk_out, jump, n_inject, seed, pass_index):
+    P = img.H * img.W
+    _check(lib.sad_propagate_topk(C.byref(img), _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                                  _ptr(topk_in, torch.int32, img.K * P, "topk_in"),
+                                  _ptr(topk_out, torch.int32, img.K * P, "topk_out"),
+                                  int(jump), int(n_inject), int(seed) & (2 ** 64 - 1),
+                                  int(pass_index), _stream()),
+           "sad_propagate_topk")
+
+
+def jump_step(t, H, W):
+    return int(lib.sad_jump_step(int(t), int(H), int(W)))
+
+
+def render_fwd(img, rec, topk, out):
+    P = img.H * img.W
+    _check(lib.sad_render_fwd(C.byref(img), _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                              _ptr(topk, torch.int32, img.K * P, "topk"),
+                              _ptr(out, torch.float32, 3 * P, "out"), _stream()),
+           "sad_render_fwd")
+
+
+def loss_grad(img, rendered, target, grad, loss=None):
+    P = img.H * img.W
+    _check(lib.sad_loss_grad(C.byref(img), _ptr(rendered, torch.float32, 3 * P, "rendered"),
+                             _ptr(target, torch.float32, 3 * P, "target"),
+                             _ptr(grad, torch.float32, 3 * P, "grad"),
+                             _ptr(loss, torch.float32, 1, "loss"), _stream()),
+           "sad_loss_grad")
+
+
+def render_bwd(img, rec, topk, grad_img, grad_sites, target=None, removal_delta=None):
+    P = img.H * img.W
+    _check(lib.sad_render_bwd(C.byref(img), _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                              _ptr(topk, torch.int32, img.K * P, "topk"),
+                              _ptr(grad_img, torch.float32, 3 * P, "grad_img"),
+                              _ptr(target, torch.float32, 3 * P, "target"),
+                              _ptr(grad_sites, torch.float32, NPARAM * img.cap, "grad_sites"),
+                              _ptr(removal_delta, torch.float32, img.cap, "removal_delta"), _stream()),
+           "sad_render_bwd")
+
+
+def adam_params(lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    p = SadAdamParams()
+    for i in range(NPARAM):
+        p.lr[i] = float(lr[i])
+    p.beta1, p.beta2, p.eps = float(beta1), float(beta2), float(eps)
+    return p
+
+
+ADAM_ZERO_GRAD = 1
+
+
+def adam_step(img, sites, grad, m, v, params, step, rec=None, zero_grad=False):
+    n = NPARAM * img.cap
+    _check(lib.sad_adam_step(C.byref(img), _ptr(sites, torch.float32, n, "sites"),
+                             _ptr(grad, torch.float32, n, "grad"), _ptr(m, torch.float32, n, "m"),
+                             _ptr(v, torch.float32, n, "v"), C.byref(params), int(step),
+                             _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                             ADAM_ZERO_GRAD if zero_grad else 0, _stream()),
+           "sad_adam_step")
+
+
+def render_fwd_loss(img, rec, topk, target, grad_img, rendered=None, loss=None):
+    P = img.H * img.W
+    _check(lib.sad_render_fwd_loss(C.byref(img), _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                                   _ptr(topk, torch.int32, img.K * P, "topk"),
+                                   _ptr(target, torch.float32, 3 * P, "target"),
+                                   _ptr(rendered, torch.float32, 3 * P, "rendered"),
+                                   _ptr(grad_img, torch.float32, 3 * P, "grad_img"),
+                                   _ptr(loss, torch.float32, 1, "loss"), _stream()),
+           "sad_render_fwd_loss")
+
+
+def query_points(img, rec, topk, xy, out):
+    M = xy.shape[0] if xy.dim() == 2 else xy.numel() // 2
+    P = img.H * img.W
+    _check(lib.sad_query_points(C.byref(img), _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                                _ptr(topk, torch.int32, img.K * P, "topk"),
+                                _ptr(xy, torch.float32, 2 * M, "xy"), int(M),
+                                _ptr(out, torch.float32, 3 * M, "out"), _stream()),
+           "sad_query_points")
+
+
+def init_workspace_bytes(img):
+    n = C.c_size_t(0)
+    _check(lib.sad_init_sites(C.byref(img), None, 0, 0.0, 0, 0.0, 0.0, None, None, C.byref(n), None),
+           "sad_init_sites")
+    return int(n.value)
+
+
+def init_sites(img, target, n_sites, lam, seed, log_tau0, r0, sites, workspace):
+    P = img.H * img.W
+    nbytes = C.c_size_t(workspace.numel() * workspace.element_size())
+    _check(lib.sad_init_sites(C.byref(img), _ptr(target, torch.float32, 3 * P, "target"), int(n_sites),
+                              float(lam), int(seed) & (2 ** 64 - 1), float(log_tau0), float(r0),
+                              _ptr(sites, torch.float32, NPARAM * img.cap, "sites"),
+                              _ptr(workspace, workspace.dtype, None, "workspace"), C.byref(nbytes),
+                              _stream()),
+           "sad_init_sites")
+
+
+def version():
+    return lib.sad_version().decode()
+
+
+def train_config(n_inject, seed, adam, fixed_jump=0):
+    c = SadTrainConfig()
+    c.n_inject, c.fixed_jump, c.seed, c.adam = int(n_inject), int(fixed_jump), int(seed) & (2 ** 64 - 1), adam
+    return c
+
+
+def train_step(img, cfg, target, sites, rec, topk_in, topk_out, grad, m, v, rendered, grad_img,
+               loss, state):
+    """One iteration (sad_train_step); state: int64 device tensor [pass, adam_step]."""
+    P = img.H * img.W
+    n = NPARAM * img.cap
+    _check(lib.sad_train_step(C.byref(img), C.byref(cfg), _ptr(target, torch.float32, 3 * P, "target"),
+                              _ptr(sites, torch.float32, n, "sites"),
+                              _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                              _ptr(topk_in, torch.int32, img.K * P, "topk_in"),
+                              _ptr(topk_out, torch.int32, img.K * P, "topk_out"),
+                              _ptr(grad, torch.float32, n, "grad"), _ptr(m, torch.float32, n, "m"),
+                              _ptr(v, torch.float32, n, "v"),
+                              _ptr(rendered, torch.float32, 3 * P, "rendered"),
+                              _ptr(grad_img, torch.float32, 3 * P, "grad_img"),
+                              _ptr(loss, torch.float32, 1, "loss"),
+                              _ptr(state, torch.int64, 2, "state"), _stream()),
+           "sad_train_step")

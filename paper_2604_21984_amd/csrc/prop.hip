@@ -1,0 +1,142 @@
+// prop.hip -- one Jacobi propagation pass of the per-pixel top-K list field (Sec. 4.3).
+#include "sad_device.h"
+#include "sad_host.h"
+#include "sad_internal.h"
+
+namespace sad {
+
+struct PropArgs {
+    int H, W, n_slots, jump, J, tiles_x, n_blocks;
+    uint64_t seed, pass;
+    const int64_t *pass_dev;  // device pass index (graph-replayable), or NULL
+};
+
+// One thread per pixel, 16x16 tiles (four 8x8 wave64 blocks).  Candidates: own list,
+// the four lists at +-jump (inside the image) and J injected IDs.  Each candidate is
+// scored and bubbled into a register-resident sorted key array (repeated IDs give equal
+// keys and are dropped).
+template <int K>
+__global__ __launch_bounds__(256) void k_prop(PropArgs a, const float4 *__restrict__ rec,
+                                              const uint4 *__restrict__ lin,
+                                              uint4 *__restrict__ lout) {
+    const int tile = xcd_tile(blockIdx.x, a.n_blocks);
+    const TilePix px = tile_pixel(tile, a.tiles_x);
+    if (px.i >= a.H || px.j >= a.W) return;
+    const int64_t P = (int64_t)a.H * a.W;
+    const int64_t p = (int64_t)px.i * a.W + px.j;
+    const float X = (float)px.j, Y = (float)px.i;
+    const uint32_t ns = (uint32_t)a.n_slots;
+    const uint64_t pass = a.pass_dev ? (uint64_t)*a.pass_dev : a.pass;
+    const int s = (a.pass_dev && a.jump <= 0) ? jump_of((int64_t)pass, a.H, a.W) : a.jump;
+
+    uint64_t keys[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) keys[k] = 0ull;
+
+    auto consider = [&](uint32_t id) {
+        const bool in_range = id < ns;
+        const uint32_t idc = in_range ? id : 0u;
+        const float4 q0 = rec[4 * (size_t)idc], q1 = rec[4 * (size_t)idc + 1];
+        uint64_t c = 0ull;
+        if (in_range && q1.w != 0.0f) c = make_key(score(q0, q1, X, Y), id);
+        insert_key<K>(keys, c);
+    };
+    auto consider_list = [&](int64_t q) {
+#pragma unroll
+        for (int g = 0; g < K / 4; ++g) {
+            const uint4 v = lin[(int64_t)g * P + q];
+            consider(v.x);
+            consider(v.y);
+            consider(v.z);
+            consider(v.w);
+        }
+    };
+
+    consider_list(p);
+    if (px.j + s < a.W) consider_list(p + s);
+    if (px.j - s >= 0) consider_list(p - s);
+    if (px.i + s < a.H) consider_list(p + (int64_t)s * a.W);
+    if (px.i - s >= 0) consider_list(p - (int64_t)s * a.W);
+    const uint64_t k0 = (pass * (uint64_t)P + (uint64_t)p) * (uint64_t)a.J;
+    for (int j = 0; j < a.J; ++j) {
+        const uint64_t hi = splitmix64(a.seed, k0 + (uint64_t)j) >> 32;
+        consider((uint32_t)((hi * (uint64_t)ns) >> 32));
+    }
+#pragma unroll
+    for (int g = 0; g < K / 4; ++g)
+        lout[(int64_t)g * P + p] = make_uint4(key_id(keys[4 * g]), key_id(keys[4 * g + 1]),
+                                              key_id(keys[4 * g + 2]), key_id(keys[4 * g + 3]));
+}
+
+template <int K>
+static void launch_prop(const PropArgs &a, const float4 *rec, const uint4 *lin, uint4 *lout,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_prop<K>, dim3(a.n_blocks), dim3(256), 0, st, a, rec, lin, lout);
+}
+
+__global__ __launch_bounds__(256) void k_fill_list(uint32_t *__restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = SAD_INVALID_ID;
+}
+
+}  // namespace sad
+
+using namespace sad;
+
+extern "C" int32_t sad_jump_step(int64_t t, int32_t H, int32_t W) { return jump_of(t, H, W); }
+
+void sad::launch_propagate(const sad_image *img, const float *rec, const uint32_t *in,
+                           uint32_t *out, int32_t jump, int32_t n_inject, uint64_t seed,
+                           uint64_t pass, const int64_t *pass_dev, hipStream_t st) {
+    const int64_t P = (int64_t)img->H * img->W;
+    if (img->n_slots == 0) {
+        const int64_t n = P * img->K;
+        hipLaunchKernelGGL(k_fill_list, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, out, n);
+        return;
+    }
+    PropArgs a;
+    a.H = img->H;
+    a.W = img->W;
+    a.n_slots = img->n_slots;
+    a.jump = jump;
+    a.J = n_inject;
+    a.tiles_x = tiles_x(img);
+    a.n_blocks = n_tiles(img);
+    a.seed = seed;
+    a.pass = pass;
+    a.pass_dev = pass_dev;
+    const float4 *r4 = reinterpret_cast<const float4 *>(rec);
+    const uint4 *li = reinterpret_cast<const uint4 *>(in);
+    uint4 *lo = reinterpret_cast<uint4 *>(out);
+    switch (img->K) {
+        case 4: launch_prop<4>(a, r4, li, lo, st); break;
+        case 8: launch_prop<8>(a, r4, li, lo, st); break;
+        case 12: launch_prop<12>(a, r4, li, lo, st); break;
+        case 16: launch_prop<16>(a, r4, li, lo, st); break;
+        case 20: launch_prop<20>(a, r4, li, lo, st); break;
+        case 24: launch_prop<24>(a, r4, li, lo, st); break;
+        case 28: launch_prop<28>(a, r4, li, lo, st); break;
+        case 32: launch_prop<32>(a, r4, li, lo, st); break;
+        default: break;
+    }
+}
+
+extern "C" sad_status sad_propagate_topk(const sad_image *img, const float *rec,
+                                         const uint32_t *topk_in, uint32_t *topk_out,
+                                         int32_t jump, int32_t n_inject, uint64_t seed,
+                                         uint64_t pass_index, void *stream) {
+    SAD_TRY(check_image(img, nullptr));
+    SAD_REQUIRE(topk_in && topk_out, SAD_ERR_INVALID_ARGUMENT, "sad_propagate_topk: NULL list");
+    SAD_REQUIRE(topk_in != topk_out, SAD_ERR_INVALID_ARGUMENT,
+                "sad_propagate_topk: topk_in and topk_out must not alias (Jacobi pass)");
+    SAD_REQUIRE(aligned16(topk_in) && aligned16(topk_out), SAD_ERR_INVALID_ARGUMENT,
+                "sad_propagate_topk: lists must be 16-byte aligned");
+    SAD_REQUIRE(jump >= 1, SAD_ERR_INVALID_ARGUMENT, "sad_propagate_topk: jump must be >= 1");
+    SAD_REQUIRE(n_inject >= 0 && n_inject <= 16, SAD_ERR_INVALID_ARGUMENT,
+                "sad_propagate_topk: n_inject must be in [0, 16]");
+    SAD_REQUIRE(img->n_slots == 0 || (rec && aligned16(rec)), SAD_ERR_INVALID_ARGUMENT,
+                "sad_propagate_topk: rec NULL or not 16-byte aligned");
+    launch_propagate(img, rec, topk_in, topk_out, jump, n_inject, seed, pass_index, nullptr,
+                     as_stream(stream));
+    return check_launch("sad_propagate_topk");
+}

@@ -1,0 +1,103 @@
+// sad_device.h -- device-side building blocks shared by the gfx950 kernels.
+//
+// Score (Sec. 4.1-4.2), list keys, the injection generator and tile mapping.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sad.h"
+
+namespace sad {
+
+// Derived record layout (SAD_REC_FLOATS = 16 floats = 64 bytes = four float4):
+//   q0 = {x, y, G11, 2*G12}   q1 = {G22, kappa, r, valid}
+//   q2 = {c_r, c_g, c_b, u_x} q3 = {u_y, e^a, e^-a, tau}
+// The propagation pass reads q0..q1, the forward q0..q2, the backward all four.
+constexpr int kRecQ = 4;
+
+// l = kappa (r - ||x - p||_G), evaluated in float32 as
+//   t = fma(2 G12, dy, G11 dx); q = fma(t, dx, (G22 dy) dy); q = max(q, 0);
+//   n = sqrt(q); l = kappa (r - n) + 0
+// with every operation correctly rounded (explicit _rn intrinsics; the TU is also
+// compiled without contraction).  The trailing "+ 0" maps -0 to +0.
+__device__ __forceinline__ float score(const float4 q0, const float4 q1, float X, float Y,
+                                       float *n_out = nullptr) {
+    const float dx = __fsub_rn(X, q0.x);
+    const float dy = __fsub_rn(Y, q0.y);
+    const float t = __fmaf_rn(q0.w, dy, __fmul_rn(q0.z, dx));
+    float q = __fmaf_rn(t, dx, __fmul_rn(__fmul_rn(q1.x, dy), dy));
+    q = fmaxf(q, 0.0f);
+    const float n = __fsqrt_rn(q);
+    if (n_out) *n_out = n;
+    return __fadd_rn(__fmul_rn(q1.y, __fsub_rn(q1.z, n)), 0.0f);
+}
+
+// Total order (score descending, ID ascending) as one unsigned 64-bit key: the high
+// word is the score's bits made monotone, the low word ~ID.  Key 0 is "empty" (no
+// finite or infinite score maps to 0) and ~0 of an empty key's low word is the
+// sentinel 0xFFFFFFFF.
+__device__ __forceinline__ uint64_t make_key(float l, uint32_t id) {
+    const uint32_t b = __float_as_uint(l);
+    const uint32_t o = b ^ ((uint32_t)((int32_t)b >> 31) | 0x80000000u);
+    return ((uint64_t)o << 32) | (uint32_t)(~id);
+}
+__device__ __forceinline__ uint32_t key_id(uint64_t k) { return ~(uint32_t)k; }
+__device__ __forceinline__ float key_score(uint64_t k) {
+    const uint32_t o = (uint32_t)(k >> 32);
+    const uint32_t b = (o & 0x80000000u) ? (o ^ 0x80000000u) : ~o;
+    return __uint_as_float(b);
+}
+
+// Insert candidate key c into keys[0..K-1] (descending, unique, 0 = empty): bubble it
+// down; an equal key is a repeated ID and is dropped.
+template <int K>
+__device__ __forceinline__ void insert_key(uint64_t (&keys)[K], uint64_t c) {
+    if (c > keys[K - 1]) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const uint64_t kj = keys[j];
+            const bool gt = c > kj;
+            const bool eq = c == kj;
+            keys[j] = gt ? c : kj;
+            c = gt ? kj : (eq ? 0ull : c);
+        }
+    }
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): output number k of the stream seeded by seed.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
+    uint64_t z = seed + (k + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Workgroups are handed to the eight XCDs round-robin (block b runs on XCD b % 8).
+// Remap so that each XCD works through one contiguous range of tiles: neighbouring
+// tiles then share that XCD's L2 (site records and neighbour lists).
+__device__ __forceinline__ int xcd_tile(int bid, int nblk) {
+    constexpr int X = 8;
+    const int q = nblk / X, r = nblk % X;
+    const int xcd = bid % X, k = bid / X;
+    const int base = xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q;
+    return base + k;
+}
+
+// 16x16-pixel tile of 256 threads: four wave64s, each an 8x8 block.
+struct TilePix {
+    int i, j;
+};
+__device__ __forceinline__ TilePix tile_pixel(int tile, int tiles_x) {
+    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    const int t = threadIdx.x;
+    const int w = t >> 6, l = t & 63;
+    TilePix p;
+    p.i = ty * 16 + (w >> 1) * 8 + (l >> 3);
+    p.j = tx * 16 + (w & 1) * 8 + (l & 7);
+    return p;
+}
+
+__device__ __forceinline__ void atomic_add_f32(float *p, float v) { unsafeAtomicAdd(p, v); }
+
+}  // namespace sad

@@ -1,0 +1,46 @@
+// sad_internal.h -- launchers shared between translation units (no validation here:
+// callers have checked their arguments).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sad.h"
+
+namespace sad {
+
+// One propagation pass.  If pass_dev != NULL the pass index is *pass_dev (device) and,
+// when jump <= 0, the jump is the schedule step of that index; otherwise pass / jump.
+void launch_propagate(const sad_image *img, const float *rec, const uint32_t *in, uint32_t *out,
+                      int32_t jump, int32_t n_inject, uint64_t seed, uint64_t pass,
+                      const int64_t *pass_dev, hipStream_t st);
+void launch_fwd(const sad_image *img, const float *rec, const uint32_t *topk, float *out,
+                hipStream_t st);
+void launch_loss_grad(const sad_image *img, const float *rendered, const float *target,
+                      float *grad, float *loss, hipStream_t st);
+// Forward blend fused with the loss gradient; rendered may be NULL.
+void launch_fwd_loss(const sad_image *img, const float *rec, const uint32_t *topk,
+                     const float *target, float *rendered, float *grad_img, float *loss,
+                     hipStream_t st);
+void launch_bwd(const sad_image *img, const float *rec, const uint32_t *topk, const float *grad_img,
+                const float *target, float *grad_sites, float *removal_delta, hipStream_t st);
+// Adam; if step_dev != NULL the step is *step_dev + 1 (device), else `step`.  If
+// zero_grad, the gradient is cleared after it has been read (ready for the next step).
+void launch_adam(const sad_image *img, float s, float *sites, float *grad, float *m, float *v,
+                 const sad_adam_params *p, int64_t step, const int64_t *step_dev, float *rec,
+                 bool zero_grad, hipStream_t st);
+void launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
+
+// Device-side jump schedule (Sec. 4.3), same formula as sad_jump_step.
+__host__ __device__ inline int32_t jump_of(int64_t t, int32_t H, int32_t W) {
+    const int m = H > W ? H : W;
+    int lb = 0;
+    while ((1LL << lb) < m) ++lb;
+    const int64_t B = 1LL << lb;
+    int64_t e = t < (int64_t)(lb - 1) ? t : (int64_t)(lb - 1);
+    if (e < 0) e = 0;
+    const int64_t s = B >> (e + 1);
+    return (int32_t)(s > 1 ? s : 1);
+}
+
+}  // namespace sad

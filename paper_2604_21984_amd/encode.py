@@ -1,0 +1,122 @@
+"""Single-image encoder: gradient-weighted initialisation, seed pass, then one
+propagation pass + forward + backward + Adam per iteration (Sec. 4.3-4.4, Sec. 5,
+Sec. 6.1), every step on the GPU.
+
+The iteration is one ``sad_train_step`` call whose counters live in device memory, so a
+pair of iterations (the list field ping-pongs between two buffers) can be recorded as
+a HIP graph once and replayed.
+"""
+import math
+from dataclasses import dataclass, field
+
+import torch
+
+from . import _lib as S
+
+# Per-parameter learning-rate multipliers over the base rate, order
+# (x, y, log_tau, r, c_r, c_g, c_b, u_x, u_y, a).  The paper states per-parameter base
+# rates without values; positions and radius move in pixels, the rest in their units.
+LR_MULT = (100.0, 100.0, 10.0, 100.0, 1.0, 1.0, 1.0, 10.0, 10.0, 10.0)
+
+
+@dataclass
+class EncodeConfig:
+    K: int = 8
+    n_inject: int = 4              # J (Sec. 6.1)
+    lr: float = 1e-3               # base learning rate
+    lr_mult: tuple = LR_MULT
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+    lam_init: float = 0.3          # lambda_init of Sec. 4.4
+    r0: float = 1.0                # initial radius (the clamp minimum)
+    log_tau0: float = None         # None: clamp(ln(2 max(H,W) / sqrt(HW/N)), 2, 20)
+    seed: int = 0
+    score_scale: float = 0.0       # 0: 1 / max(H, W)
+
+
+def default_log_tau(H, W, N):
+    """Initial log tau giving an adjacent-site logit gap of about 2 (kappa * spacing)."""
+    spacing = math.sqrt(H * W / max(N, 1))
+    return float(min(max(math.log(2.0 * max(H, W) / spacing), 2.0), 20.0))
+
+
+class Encoder:
+    """Device state of one image: sites, derived records, two list fields, Adam
+    moments, gradient, step counters."""
+
+    def __init__(self, target, n_sites, cfg=None, cap=None, device=None):
+        cfg = cfg or EncodeConfig()
+        self.cfg = cfg
+        self.device = device or target.device
+        self.target = target.contiguous().to(self.device, torch.float32)
+        _, H, W = self.target.shape
+        self.H, self.W = H, W
+        cap = int(cap or n_sites)
+        self.img = S.image(H, W, cfg.K, n_sites, cap, cfg.score_scale)
+        dev = self.device
+        f32 = dict(dtype=torch.float32, device=dev)
+        self.sites = torch.empty((S.NPARAM, cap), **f32)
+        self.rec = torch.empty(max(n_sites, 1) * S.REC_FLOATS, **f32)
+        self.lists = [torch.empty((cfg.K // 4, H, W, 4), dtype=torch.int32, device=dev)
+                      for _ in range(2)]
+        self.cur = 0
+        self.grad = torch.zeros((S.NPARAM, cap), **f32)
+        self.m = torch.zeros((S.NPARAM, cap), **f32)
+        self.v = torch.zeros((S.NPARAM, cap), **f32)
+        self.rendered = torch.empty((3, H, W), **f32)
+        self.grad_img = torch.empty((3, H, W), **f32)
+        self.loss = torch.zeros(1, **f32)
+        self.state = torch.zeros(2, dtype=torch.int64, device=dev)
+        lt0 = cfg.log_tau0 if cfg.log_tau0 is not None else default_log_tau(H, W, n_sites)
+        ws = torch.empty(S.init_workspace_bytes(self.img), dtype=torch.uint8, device=dev)
+        S.init_sites(self.img, self.target, n_sites, cfg.lam_init, cfg.seed, lt0, cfg.r0,
+                     self.sites, ws)
+        del ws
+        S.prepare_sites(self.img, self.sites, self.rec)
+        S.seed_topk(self.img, self.rec, self.lists[0], self.lists[1])
+        lr = [cfg.lr * mlt for mlt in cfg.lr_mult]
+        self.adam = S.adam_params(lr, cfg.beta1, cfg.beta2, cfg.eps)
+        self.train_cfg = S.train_config(cfg.n_inject, cfg.seed ^ 0x5AD5AD, self.adam)
+        self.graph = None
+        self.steps = 0
+
+    @property
+    def topk(self):
+        return self.lists[self.cur]
+
+    def step(self):
+        """One training iteration, enqueued on the current stream (no host sync)."""
+        a, b = self.lists[self.cur], self.lists[1 - self.cur]
+        S.train_step(self.img, self.train_cfg, self.target, self.sites, self.rec, a, b, self.grad,
+                     self.m, self.v, None, self.grad_img, self.loss, self.state)
+        self.cur = 1 - self.cur
+        self.steps += 1
+
+    def capture(self):
+        """Record two iterations (A -> B -> A) as one HIP graph."""
+        assert self.cur == 0, "capture from the first list buffer"
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step()
+            self.step()
+        self.steps -= 2  # recording does not execute
+        self.graph = g
+        return g
+
+    def replay(self, pairs=1):
+        for _ in range(pairs):
+            self.graph.replay()
+        self.steps += 2 * pairs
+
+    def render(self, out=None):
+        out = out if out is not None else torch.empty((3, self.H, self.W), dtype=torch.float32,
+                                                      device=self.device)
+        S.render_fwd(self.img, self.rec, self.topk, out)
+        return out
+
+    def psnr(self):
+        img = self.render().clamp(0, 1)
+        mse = torch.mean((img - self.target) ** 2).item()
+        return 10.0 * math.log10(1.0 / max(mse, 1e-20))

@@ -1,0 +1,286 @@
+"""GPU parity: every C-ABI call against the CPU oracle on the same seeded inputs.
+
+Lists: bit-exact.  Colours: max-abs <= 1e-5.  Gradients: per parameter group
+|d| <= 1e-4 (|g_ref| + 1e-3 max|g_ref|).  Derived site values: bit-exact.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from _helpers import GROUPS, grad_close, grad_report, planar_to_rows, rows_to_planar
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def S():
+    import paper_2604_21984_amd._lib as S
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return S
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+class Gpu:
+    """Device buffers of one image for direct C-ABI calls."""
+
+    def __init__(self, S, H, W, K, sites_np, n, s=0.0):
+        self.S, self.H, self.W, self.K = S, H, W, K
+        cap = sites_np.shape[1]
+        self.img = S.image(H, W, K, n, cap, s)
+        self.sites = _t(sites_np.astype(np.float32))
+        self.rec = torch.empty(max(n, 1) * 16, dtype=torch.float32, device=DEV)
+        S.prepare_sites(self.img, self.sites, self.rec)
+        self.A = torch.empty((K // 4, H, W, 4), dtype=torch.int32, device=DEV)
+        self.B = torch.empty_like(self.A)
+
+    def seed(self):
+        self.S.seed_topk(self.img, self.rec, self.A, self.B)
+
+    def set_lists(self, rows):
+        self.A.copy_(_t(rows_to_planar(rows, self.H, self.W, self.K)))
+
+    def prop(self, jump, J, seed, t):
+        self.S.propagate_topk(self.img, self.rec, self.A, self.B, jump, J, seed, t)
+        self.A, self.B = self.B, self.A
+
+    def lists(self):
+        torch.cuda.synchronize()
+        return planar_to_rows(self.A.cpu().numpy(), self.H, self.W, self.K)
+
+    def render(self):
+        out = torch.empty((3, self.H, self.W), dtype=torch.float32, device=DEV)
+        self.S.render_fwd(self.img, self.rec, self.A, out)
+        torch.cuda.synchronize()
+        return out.cpu().numpy()
+
+    def bwd(self, gimg, target=None, rd=False):
+        cap = self.img.cap
+        g = torch.zeros((10, cap), dtype=torch.float32, device=DEV)
+        r = torch.zeros(cap, dtype=torch.float32, device=DEV) if rd else None
+        self.S.render_bwd(self.img, self.rec, self.A, _t(gimg.astype(np.float32)), g,
+                          target=None if target is None else _t(target), removal_delta=r)
+        torch.cuda.synchronize()
+        return g.cpu().numpy(), (r.cpu().numpy() if rd else None)
+
+
+def _case_small():
+    """64x64, N = 256 isotropic sites (metric scale 1/8, r = 0, tau = 1), K = 4, J = 2,
+    jumps 32, 16, 8, 4."""
+    img = synth.image_small(0)
+    sites = synth.random_sites(100, 64, 64, 256)
+    return img, sites, 64, 64, 4, 256, 0.125
+
+
+def _case_aniso(H, W, N, K, seed, cap_extra=3):
+    img = synth.image_encode(seed, H, W, n_polygons=20, patch=32)
+    sites = synth.random_sites(seed + 7, H, W, N, cap=N + cap_extra, anisotropic=True,
+                               log_tau_range=(3.0, 7.0), r_range=(1.0, 4.0))
+    sites[0, 5] = -1.0                  # inactive slot
+    sites[2, 9] = np.nan                # non-finite parameter: never listed
+    sites[:, 12] = sites[:, N - 2]      # exact duplicate: tie broken by the lower ID
+    return img, sites, H, W, K, N, O.default_scale(H, W)
+
+
+CASES = {
+    "small_k4": _case_small,
+    "ragged_k8": lambda: _case_aniso(100, 150, 800, 8, 1),
+    "k16": lambda: _case_aniso(40, 56, 300, 16, 2),
+    "k32": lambda: _case_aniso(33, 47, 200, 32, 3),
+    "k12_tiny": lambda: _case_aniso(5, 9, 20, 12, 4),
+}
+
+
+def test_prepare_sites_bit_exact(S):
+    sites = synth.random_sites(5, 50, 70, 300, cap=310, anisotropic=True,
+                               log_tau_range=(-3, 25), r_range=(-2, 600), a_range=(-30, 30))
+    sites[0, 3] = -1.0
+    sites[9, 4] = np.inf
+    sites[2, 6] = 200.0                 # tau overflows to inf: invalid
+    sites[2, 7] = -200.0                # tau underflows to 0: invalid (kappa must be > 0)
+    g = Gpu(S, 50, 70, 8, sites, 300)
+    torch.cuda.synchronize()
+    rec = g.rec.cpu().numpy().reshape(300, 16)
+    ref = O.site_derived(sites, 300, O.default_scale(50, 70))
+    valid = ref[:, 0] == 1.0
+    np.testing.assert_array_equal(rec[:, 7], ref[:, 0])
+    for col_g, col_o, mul in [(15, 1, 1), (13, 2, 1), (14, 3, 1), (5, 4, 1), (2, 5, 1),
+                              (3, 6, 2), (4, 7, 1)]:
+        np.testing.assert_array_equal(rec[valid, col_g], ref[valid, col_o] * np.float32(mul))
+    np.testing.assert_array_equal(rec[:, 0], sites[0, :300])
+    np.testing.assert_array_equal(rec[:, 8:11], sites[4:7, :300].T)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_seed_and_propagation_lockstep_bit_exact(S, name):
+    img, sites, H, W, K, N, s = CASES[name]()
+    J = 2 if name == "small_k4" else 4
+    jumps = [32, 16, 8, 4] if name == "small_k4" else [O.jump(t, H, W) for t in range(8)]
+    g = Gpu(S, H, W, K, sites, N, s)
+    g.seed()
+    ref = O.seed_lists(H, W, K, s, sites, N)
+    got = g.lists()
+    assert np.array_equal(got, ref), f"seed: {np.sum(got != ref)} slots differ"
+    for t, jmp in enumerate(jumps):
+        # lockstep: both sides start the pass from the oracle's field
+        g.set_lists(ref)
+        g.prop(jmp, J, 1234, t)
+        ref = O.prop_pass(H, W, K, s, sites, N, ref, jmp, J, 1234, t)
+        got = g.lists()
+        bad = np.argwhere(np.any(got != ref, axis=1)).ravel()
+        assert bad.size == 0, f"pass {t} (jump {jmp}): {bad.size} pixels differ, first {bad[:5]}"
+
+
+def test_propagation_free_running_and_garbage_ids(S):
+    img, sites, H, W, K, N, s = CASES["ragged_k8"]()
+    rng = np.random.default_rng(9)
+    # garbage input field: random IDs including out-of-range and sentinel values
+    rows = rng.integers(0, N + 50, size=(H * W, K)).astype(np.uint32)
+    rows[rng.uniform(size=rows.shape) < 0.2] = 0xFFFFFFFF
+    g = Gpu(S, H, W, K, sites, N, s)
+    g.set_lists(rows)
+    ref = rows
+    for t in range(10):
+        jmp = O.jump(t, H, W)
+        g.prop(jmp, 4, 77, 100 + t)
+        ref = O.prop_pass(H, W, K, s, sites, N, ref, jmp, 4, 77, 100 + t)
+    assert np.array_equal(g.lists(), ref)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_forward_blend_within_1e5(S, name):
+    img, sites, H, W, K, N, s = CASES[name]()
+    g = Gpu(S, H, W, K, sites, N, s)
+    lists = O.brute_topk(H, W, K, s, sites, N)
+    g.set_lists(lists)
+    got = g.render()
+    ref = O.render(H, W, K, s, sites, N, lists)
+    err = np.abs(got - ref).max()
+    assert err <= 1e-5, err
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_backward_matches_oracle(S, name):
+    img, sites, H, W, K, N, s = CASES[name]()
+    g = Gpu(S, H, W, K, sites, N, s)
+    lists = O.brute_topk(H, W, K, s, sites, N)
+    g.set_lists(lists)
+    rng = np.random.default_rng(3)
+    gimg = rng.normal(0, 1e-3, (3, H, W)).astype(np.float32)
+    got, rd = g.bwd(gimg, target=img, rd=True)
+    ref, rdr, ab = O.render_bwd(H, W, K, s, sites, N, lists, gimg.astype(np.float64), target=img,
+                                removal_delta=True, abs_sum=True)
+    w, rep = grad_report(got, ref, ab)
+    assert w <= 1.0, f"gradient mismatch ratio {w}\n{rep}"
+    scale = 1e-4 * (np.abs(rdr) + 1e-3 * np.abs(rdr).max())
+    assert np.all(np.abs(rd - rdr) <= scale + 1e-12), np.max(np.abs(rd - rdr) / (scale + 1e-12))
+
+
+def test_loss_grad(S):
+    H, W = 37, 53
+    rng = np.random.default_rng(1)
+    a = rng.uniform(0, 1, (3, H, W)).astype(np.float32)
+    b = rng.uniform(0, 1, (3, H, W)).astype(np.float32)
+    img = S.image(H, W, 4, 1)
+    grad = torch.empty((3, H, W), dtype=torch.float32, device=DEV)
+    loss = torch.zeros(1, dtype=torch.float32, device=DEV)
+    S.loss_grad(img, _t(a), _t(b), grad, loss)
+    L, gref = O.loss_grad(a.astype(np.float64), b)
+    torch.cuda.synchronize()
+    assert abs(loss.item() - L) <= 1e-5 * L
+    np.testing.assert_allclose(grad.cpu().numpy(), gref, atol=1e-9, rtol=1e-5)
+
+
+def test_query_points(S):
+    img, sites, H, W, K, N, s = CASES["ragged_k8"]()
+    g = Gpu(S, H, W, K, sites, N, s)
+    lists = O.brute_topk(H, W, K, s, sites, N)
+    g.set_lists(lists)
+    rng = np.random.default_rng(4)
+    xy = np.stack([rng.uniform(-3, W + 2, 5000), rng.uniform(-3, H + 2, 5000)], 1).astype(np.float32)
+    xy[:10] = [[0, 0], [W - 1, H - 1], [0.5, 0.5], [1.5, 2.5], [-0.5, 3], [W - 0.5, 0],
+               [10, 10], [np.float32(7.49999), 3], [3, np.float32(8.5000005)], [2, 2]]
+    out = torch.empty((5000, 3), dtype=torch.float32, device=DEV)
+    S.query_points(g.img, g.rec, g.A, _t(xy), out)
+    torch.cuda.synchronize()
+    ref = O.query(H, W, K, s, sites, N, lists, xy)
+    assert np.abs(out.cpu().numpy() - ref).max() <= 1e-5
+
+
+def test_adam_matches_oracle(S):
+    H, W, N, cap = 40, 60, 500, 512
+    sites = synth.random_sites(8, H, W, N, cap=cap, anisotropic=True, log_tau=5.0, r=2.0)
+    sites[0, 7] = -1.0
+    lr = np.array([0.1, 0.1, 0.01, 0.1, 1e-3, 1e-3, 1e-3, 0.01, 0.01, 0.01])
+    img = S.image(H, W, 8, N, cap)
+    st = _t(sites)
+    m = torch.zeros_like(st)
+    v = torch.zeros_like(st)
+    rec = torch.empty(N * 16, dtype=torch.float32, device=DEV)
+    prm = S.adam_params(lr)
+    s64 = sites.astype(np.float64)
+    m64 = np.zeros_like(s64)
+    v64 = np.zeros_like(s64)
+    rng = np.random.default_rng(2)
+    for t in range(1, 5):
+        gr = (rng.normal(0, 1, (10, cap)) * 1e-3).astype(np.float32)
+        S.adam_step(img, st, _t(gr), m, v, prm, t, rec)
+        O.adam(H, W, s64, gr.astype(np.float64), m64, v64, N, lr, 0.9, 0.999, 1e-8, t)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(st.cpu().numpy(), s64, rtol=2e-6, atol=2e-6)
+    # the refreshed derived records equal a fresh prepare of the updated sites
+    rec2 = torch.empty_like(rec)
+    S.prepare_sites(img, st, rec2)
+    torch.cuda.synchronize()
+    assert torch.equal(rec, rec2)
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 256), (37, 91, 500), (512, 768, 20000)])
+def test_init_sites_bit_exact(S, shape):
+    H, W, N = shape
+    target = synth.image_encode(11, H, W, n_polygons=30 if H < 100 else 200)
+    cap = N + 5
+    ref, k = O.init_sites(target, N, 0.3, 42, 5.0, 1.0, cap)
+    img = S.image(H, W, 8, N, cap)
+    ws = torch.empty(S.init_workspace_bytes(img), dtype=torch.uint8, device=DEV)
+    sites = torch.full((10, cap), 7.0, dtype=torch.float32, device=DEV)
+    S.init_sites(img, _t(target), N, 0.3, 42, 5.0, 1.0, sites, ws)
+    torch.cuda.synchronize()
+    got = sites.cpu().numpy()
+    assert np.array_equal(got, ref), np.argwhere(got != ref)[:5]
+
+
+def test_encode_size_full_pipeline_parity(S):
+    """768x512, N = 20000 from the initialisation, K = 8, J = 4: seed + 10 free-running
+    passes bit-exact over the whole field, then forward and backward."""
+    H, W, N, K = 512, 768, 20000, 8
+    target = synth.image_encode(0, H, W)
+    s = O.default_scale(H, W)
+    lt0 = float(np.clip(math.log(2 * max(H, W) / math.sqrt(H * W / N)), 2, 20))
+    sites, _ = O.init_sites(target, N, 0.3, 1, lt0, 1.0, N)
+    g = Gpu(S, H, W, K, sites, N)
+    g.seed()
+    ref = O.seed_lists(H, W, K, s, sites, N)
+    for t in range(10):
+        jmp = O.jump(t, H, W)
+        g.prop(jmp, 4, 5, t)
+        ref = O.prop_pass(H, W, K, s, sites, N, ref, jmp, 4, 5, t)
+    got = g.lists()
+    assert np.array_equal(got, ref), f"{np.sum(np.any(got != ref, 1))} pixels differ"
+    col = g.render()
+    cref = O.render(H, W, K, s, sites, N, ref)
+    assert np.abs(col - cref).max() <= 1e-5
+    _, gimg = O.loss_grad(cref, target)
+    gg, _ = g.bwd(gimg.astype(np.float32))
+    gref, ab = O.render_bwd(H, W, K, s, sites, N, ref, gimg.astype(np.float32).astype(np.float64),
+                            abs_sum=True)
+    w, rep = grad_report(gg, gref, ab)
+    assert w <= 1.0, rep

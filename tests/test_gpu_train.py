@@ -1,0 +1,123 @@
+"""GPU: the training iteration (sad_train_step), its HIP-graph replay, and the
+autograd wrapper, against direct C-ABI calls and the CPU oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from _helpers import grad_close, planar_to_rows, rows_to_planar
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def mods():
+    from paper_2604_21984_amd import _lib as S
+    from paper_2604_21984_amd import autograd as A
+    from paper_2604_21984_amd import encode as E
+    return S, A, E
+
+
+def _enc(E, H=96, W=130, N=600, seed=0):
+    target = torch.from_numpy(synth.image_encode(seed, H, W, n_polygons=25, patch=24)).to(DEV)
+    return E.Encoder(target, N, E.EncodeConfig(K=8, n_inject=4, seed=seed))
+
+
+def test_train_step_equals_individual_calls(mods):
+    S, A, E = mods
+    enc = _enc(E)
+    # replica of the state, driven through the individual entry points
+    sites = enc.sites.clone()
+    rec = enc.rec.clone()
+    la, lb = enc.lists[0].clone(), enc.lists[1].clone()
+    m, v = enc.m.clone(), enc.v.clone()
+    grad = torch.zeros_like(enc.grad)
+    out = torch.empty_like(enc.rendered)
+    gimg = torch.empty_like(enc.grad_img)
+    loss = torch.zeros(1, dtype=torch.float32, device=DEV)
+    img = enc.img
+    for t in range(4):
+        enc.step()
+        S.propagate_topk(img, rec, la, lb, S.jump_step(t, enc.H, enc.W), 4,
+                         enc.train_cfg.seed, t)
+        S.render_fwd(img, rec, lb, out)
+        loss.zero_()
+        S.loss_grad(img, out, enc.target, gimg, loss)
+        gimg2 = torch.empty_like(gimg)
+        loss2 = torch.zeros(1, dtype=torch.float32, device=DEV)
+        out2 = torch.empty_like(out)
+        S.render_fwd_loss(img, rec, lb, enc.target, gimg2, out2, loss2)
+        assert torch.equal(out2, out) and torch.equal(gimg2, gimg)
+        assert abs(loss2.item() - loss.item()) <= 1e-6 * loss.item()
+        grad.zero_()
+        S.render_bwd(img, rec, lb, gimg, grad)
+        S.adam_step(img, sites, grad, m, v, enc.adam, t + 1, rec)
+        la, lb = lb, la
+        torch.cuda.synchronize()
+        if t == 0:
+            assert torch.equal(enc.topk, la)
+        assert abs(enc.loss.item() - loss.item()) <= 1e-6 * loss.item()
+    assert enc.state.tolist() == [4, 4]
+    torch.testing.assert_close(enc.sites, sites, rtol=1e-5, atol=1e-5)
+    agree = (enc.topk == la).float().mean().item()
+    assert agree > 0.999
+
+
+def test_graph_replay_matches_eager(mods):
+    S, A, E = mods
+    eager, graphed = _enc(E, seed=3), _enc(E, seed=3)
+    graphed.capture()
+    losses_e, losses_g = [], []
+    for r in range(4):
+        eager.step()
+        eager.step()
+        graphed.replay(1)
+        torch.cuda.synchronize()
+        losses_e.append(eager.loss.item())
+        losses_g.append(graphed.loss.item())
+        # eager host work and a synchronisation between replays
+        _ = graphed.render().sum().item()
+    np.testing.assert_allclose(losses_g, losses_e, rtol=1e-4)
+    assert graphed.state.tolist() == [8, 8]
+    torch.testing.assert_close(graphed.sites, eager.sites, rtol=1e-4, atol=1e-4)
+    assert (graphed.topk == eager.topk).float().mean().item() > 0.999
+
+
+def test_autograd_render_matches_oracle(mods):
+    S, A, E = mods
+    H, W, N, K = 40, 52, 150, 8
+    sites_np = synth.random_sites(4, H, W, N, cap=160, anisotropic=True,
+                                  log_tau_range=(3, 6), r_range=(1, 3))
+    s = O.default_scale(H, W)
+    lists = O.brute_topk(H, W, K, s, sites_np, N)
+    target_np = synth.image_encode(2, H, W, n_polygons=8, patch=16)
+    img = S.image(H, W, K, N, 160)
+    sites = torch.from_numpy(sites_np).to(DEV).requires_grad_(True)
+    topk = torch.from_numpy(rows_to_planar(lists, H, W, K)).to(DEV)
+    target = torch.from_numpy(target_np).to(DEV)
+    out = A.render(sites, topk, img)
+    loss = A.mse_loss(out, target, img)
+    loss.backward()
+    ref_img = O.render(H, W, K, s, sites_np, N, lists)
+    L, g = O.loss_grad(ref_img, target_np)
+    ref, ab = O.render_bwd(H, W, K, s, sites_np, N, lists, g, abs_sum=True)
+    assert abs(loss.item() - L) <= 1e-5 * L
+    assert np.abs(out.detach().cpu().numpy() - ref_img).max() <= 1e-5
+    assert grad_close(sites.grad.cpu().numpy(), ref, ab) <= 1.0
+    # torch's own MSE (scaled to the paper's normalisation) drives the same backward
+    sites.grad = None
+    out = A.render(sites, topk, img)
+    ((out - target) ** 2).sum(0).mean().backward()
+    assert grad_close(sites.grad.cpu().numpy(), ref, ab) <= 1.0
+
+
+def test_encode_improves_psnr(mods):
+    S, A, E = mods
+    enc = _enc(E, H=128, W=192, N=1500, seed=5)
+    p0 = enc.psnr()
+    for _ in range(100):
+        enc.step()
+    p1 = enc.psnr()
+    assert p1 > p0 + 3.0, (p0, p1)
