@@ -111,7 +111,7 @@ def main():
     ms = e0.elapsed_time(e1)
     ms_per_step = ms / steps
     mpix = H * W * steps / (ms / 1e3) / 1e6
-    loss = enc.loss.item()
+    loss = enc.loss_value()
     psnr = enc.psnr()
 
     # ---- per-kernel breakdown: the same kernels launched one by one, timed with events
@@ -122,7 +122,8 @@ def main():
     nb = args.breakdown_steps
     img = enc.img
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for _ in range(nb)]
-    st = enc.state.cpu()
+    st = enc.counters()
+    lacc = S.loss_acc(dev)
     torch.cuda.synchronize()
     torch.cuda._sleep(int(2e8))
     for it in range(nb):
@@ -132,7 +133,7 @@ def main():
         E[0].record(stream)
         S.propagate_topk(img, enc.rec, a, b, S.jump_step(t_pass, H, W), J, 7, t_pass)
         E[1].record(stream)
-        S.render_fwd_loss(img, enc.rec, b, enc.target, enc.grad_img, None, enc.loss)
+        S.render_fwd_loss(img, enc.rec, b, enc.target, enc.grad_img, None, lacc)
         E[2].record(stream)
         S.render_bwd(img, enc.rec, b, enc.grad_img, enc.grad)
         E[3].record(stream)

@@ -64,6 +64,16 @@ typedef struct {
     float score_scale;
 } sad_image;
 
+/* Device accumulator of the MSE loss.  A call that reports the loss adds L to `value`;
+ * part[] is scratch that every call leaves at zero (zero the whole struct once).  The
+ * loss is summed in per-block partials spread over SAD_LOSS_PARTS addresses and folded
+ * by a single-block pass, so no single address takes one atomic per block. */
+#define SAD_LOSS_PARTS 64
+typedef struct {
+    float value;
+    float part[SAD_LOSS_PARTS];
+} sad_loss_acc;
+
 /* Adam hyper-parameters (Sec. 5: per-parameter base learning rates, fixed betas and
  * epsilon).  lr[p] is the learning rate of parameter p in the site order above. */
 typedef struct {
@@ -114,17 +124,17 @@ sad_status sad_render_fwd(const sad_image *img, const float *rec, const uint32_t
 /* ---- a5: loss gradient (Sec. 6.1) -------------------------------------------------
  * L = (1/P) sum_x ||c(x) - I(x)||^2 with P = H*W; grad = dL/dc = (2/P)(c - I).
  * img, target: float[3][H][W]; grad: float[3][H][W] (written, may alias img);
- * loss: nullable float scalar, L is ADDED to it (caller zeroes). */
+ * loss: nullable device accumulator, L is added to loss->value. */
 sad_status sad_loss_grad(const sad_image *img, const float *rendered, const float *target,
-                         float *grad, float *loss, void *stream);
+                         float *grad, sad_loss_acc *loss, void *stream);
 
 /* ---- a4 + a5 fused: forward blend and loss gradient in one pass ------------------
  * As sad_render_fwd followed by sad_loss_grad, without storing the image unless
- * rendered != NULL: grad_img = (2/P)(c - I); L is ADDED to *loss if loss != NULL.
+ * rendered != NULL: grad_img = (2/P)(c - I); L is added to loss->value if loss != NULL.
  * target, grad_img (written), rendered (nullable, written): float[3][H][W]. */
 sad_status sad_render_fwd_loss(const sad_image *img, const float *rec, const uint32_t *topk,
-                               const float *target, float *rendered, float *grad_img, float *loss,
-                               void *stream);
+                               const float *target, float *rendered, float *grad_img,
+                               sad_loss_acc *loss, void *stream);
 
 /* ---- a6: backward scatter (App. B.4; Sec. 4.8 tiled pre-reduction) ---------------
  * Recomputes the blend weights from rec and topk (nothing is stored by the forward)
@@ -137,9 +147,12 @@ sad_status sad_render_fwd_loss(const sad_image *img, const float *rec, const uin
  *   du_y += 2 rho (e^a alpha d_y - e^-a beta d_x).
  * If removal_delta != NULL (target then required) it also accumulates the removal
  * delta of Sec. 4.5, (||c'_k - I||^2 - ||c - I||^2) / P with c'_k the blend without
- * entry k, into removal_delta[cap].  Partial sums of a pixel tile are combined in LDS
- * and flushed with one float atomic per (site, parameter, tile), so the order of
- * additions -- and the last bits of the result -- vary from run to run. */
+ * entry k, into removal_delta[cap].  Partial sums of a 16x16 pixel tile are combined in
+ * LDS in 64-bit fixed point (terms scaled by 2^40 * 2^(ceil(log2 P) - 1), i.e. exact
+ * integer adds with a resolution of 2^-40 of a term of size 1/P; a term too large for
+ * that range goes to a float atomic instead) and each tile flushes one float atomic per
+ * (site, parameter), so the order of the float additions across tiles -- and the last
+ * bits of the result -- vary from run to run. */
 sad_status sad_render_bwd(const sad_image *img, const float *rec, const uint32_t *topk,
                           const float *grad_img, const float *target, float *grad_sites,
                           float *removal_delta, void *stream);
@@ -185,6 +198,7 @@ sad_status sad_init_sites(const sad_image *img, const float *target, int32_t n_s
 typedef struct {
     int64_t pass;      /* refresh counter t: jump s_t (Sec. 4.3) and injection stream */
     int64_t adam_step; /* Adam steps taken so far */
+    sad_loss_acc loss; /* loss.value = L of the last step */
 } sad_step_state;
 
 typedef struct {
@@ -197,19 +211,19 @@ typedef struct {
 /* One iteration (Sec. 5: no host work inside the loop), enqueued as:
  *   1. propagation pass topk_in -> topk_out with pass index state->pass;
  *   2. forward blend with topk_out fused with the loss gradient: grad_img [3][H][W]
- *      = dL/dc, the image itself into rendered [3][H][W] if rendered != NULL, L written
- *      to *loss if loss != NULL;
+ *      = dL/dc, the image itself into rendered [3][H][W] if rendered != NULL, L into
+ *      state->loss.value;
  *   3. the backward scatter into grad_sites [10][cap], which must be zero on entry;
  *   4. Adam step number state->adam_step + 1 (clamps, renormalised u), rec refreshed,
  *      grad_sites cleared again (ready for the next call);
  *   5. state->pass += 1, state->adam_step += 1.
  * rec must describe `sites` on entry (sad_prepare_sites); after the call topk_out holds
  * the current list field (pass the two list buffers in swapped order next time).
- * cfg: host; state: device. */
+ * cfg: host; state: device (zero it before the first call). */
 sad_status sad_train_step(const sad_image *img, const sad_train_config *cfg, const float *target,
                           float *sites, float *rec, const uint32_t *topk_in, uint32_t *topk_out,
                           float *grad_sites, float *adam_m, float *adam_v, float *rendered,
-                          float *grad_img, float *loss, sad_step_state *state, void *stream);
+                          float *grad_img, sad_step_state *state, void *stream);
 
 /* ---- diagnostics ------------------------------------------------------------------ */
 const char *sad_status_string(sad_status s);

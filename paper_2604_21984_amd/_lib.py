@@ -16,6 +16,9 @@ LIB_PATH = os.path.join(_HERE, "libsad.so")
 
 NPARAM = 10
 REC_FLOATS = 16
+LOSS_PARTS = 64
+LOSS_ACC_FLOATS = 1 + LOSS_PARTS          # sad_loss_acc
+STEP_STATE_INT64 = (16 + 4 * LOSS_ACC_FLOATS + 7) // 8   # sad_step_state, 8-byte aligned
 INVALID_ID = 0xFFFFFFFF
 MAX_K = 32
 
@@ -56,7 +59,7 @@ def _load():
         "sad_render_fwd_loss": [IMG, P, P, P, P, P, P, P],
         "sad_query_points": [IMG, P, P, P, I64, P, P],
         "sad_init_sites": [IMG, P, I32, F32, U64, F32, F32, P, P, C.POINTER(SZ), P],
-        "sad_train_step": [IMG, C.POINTER(SadTrainConfig), P, P, P, P, P, P, P, P, P, P, P, P, P],
+        "sad_train_step": [IMG, C.POINTER(SadTrainConfig), P, P, P, P, P, P, P, P, P, P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -147,12 +150,32 @@ def render_fwd(img, rec, topk, out):
            "sad_render_fwd")
 
 
+def loss_acc(device="cuda"):
+    """A zeroed sad_loss_acc on the device (value = element 0)."""
+    return torch.zeros(LOSS_ACC_FLOATS, dtype=torch.float32, device=device)
+
+
+def step_state(device="cuda"):
+    """A zeroed sad_step_state on the device."""
+    return torch.zeros(STEP_STATE_INT64, dtype=torch.int64, device=device)
+
+
+def state_counters(state):
+    """(pass, adam_step) of a sad_step_state tensor (device tensor of 2 int64)."""
+    return state[:2]
+
+
+def state_loss(state):
+    """loss.value of a sad_step_state tensor (0-d device float tensor)."""
+    return state.view(torch.float32)[4]
+
+
 def loss_grad(img, rendered, target, grad, loss=None):
     P = img.H * img.W
     _check(lib.sad_loss_grad(C.byref(img), _ptr(rendered, torch.float32, 3 * P, "rendered"),
                              _ptr(target, torch.float32, 3 * P, "target"),
                              _ptr(grad, torch.float32, 3 * P, "grad"),
-                             _ptr(loss, torch.float32, 1, "loss"), _stream()),
+                             _ptr(loss, torch.float32, LOSS_ACC_FLOATS, "loss"), _stream()),
            "sad_loss_grad")
 
 
@@ -195,7 +218,7 @@ def render_fwd_loss(img, rec, topk, target, grad_img, rendered=None, loss=None):
                                    _ptr(target, torch.float32, 3 * P, "target"),
                                    _ptr(rendered, torch.float32, 3 * P, "rendered"),
                                    _ptr(grad_img, torch.float32, 3 * P, "grad_img"),
-                                   _ptr(loss, torch.float32, 1, "loss"), _stream()),
+                                   _ptr(loss, torch.float32, LOSS_ACC_FLOATS, "loss"), _stream()),
            "sad_render_fwd_loss")
 
 
@@ -238,8 +261,8 @@ def train_config(n_inject, seed, adam, fixed_jump=0):
 
 
 def train_step(img, cfg, target, sites, rec, topk_in, topk_out, grad, m, v, rendered, grad_img,
-               loss, state):
-    """One iteration (sad_train_step); state: int64 device tensor [pass, adam_step]."""
+               state):
+    """One iteration (sad_train_step); state: a sad_step_state tensor (step_state())."""
     P = img.H * img.W
     n = NPARAM * img.cap
     _check(lib.sad_train_step(C.byref(img), C.byref(cfg), _ptr(target, torch.float32, 3 * P, "target"),
@@ -251,6 +274,5 @@ def train_step(img, cfg, target, sites, rec, topk_in, topk_out, grad, m, v, rend
                               _ptr(v, torch.float32, n, "v"),
                               _ptr(rendered, torch.float32, 3 * P, "rendered"),
                               _ptr(grad_img, torch.float32, 3 * P, "grad_img"),
-                              _ptr(loss, torch.float32, 1, "loss"),
-                              _ptr(state, torch.int64, 2, "state"), _stream()),
+                              _ptr(state, torch.int64, STEP_STATE_INT64, "state"), _stream()),
            "sad_train_step")

@@ -35,11 +35,11 @@ class SADRender(torch.autograd.Function):
 class SADMSELoss(torch.autograd.Function):
     @staticmethod
     def forward(ctx, rendered, target, img):
-        loss = torch.zeros(1, dtype=torch.float32, device=rendered.device)
+        loss = S.loss_acc(rendered.device)
         grad = torch.empty_like(rendered)
         S.loss_grad(img, rendered.detach().contiguous(), target.contiguous(), grad, loss)
         ctx.save_for_backward(grad)
-        return loss[0]
+        return loss[0].clone()
 
     @staticmethod
     def backward(ctx, g):

@@ -1,5 +1,7 @@
 // render.hip -- forward blend (Sec. 4.2), loss gradient (Sec. 6.1), backward scatter
 // with per-tile LDS pre-reduction (App. B.4, Sec. 4.8), point queries (Sec. 6.6).
+#include <cmath>
+
 #include "sad_device.h"
 #include "sad_host.h"
 #include "sad_internal.h"
@@ -131,7 +133,7 @@ __device__ __forceinline__ float block_sum(float v) {
 __global__ __launch_bounds__(256) void k_loss_grad(const float *__restrict__ img,
                                                    const float *__restrict__ tgt,
                                                    float *__restrict__ grad, int64_t n3,
-                                                   float inv_P, float *__restrict__ loss) {
+                                                   float inv_P, sad_loss_acc *__restrict__ loss) {
     float sq = 0.f;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n3;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -141,7 +143,16 @@ __global__ __launch_bounds__(256) void k_loss_grad(const float *__restrict__ img
     }
     if (!loss) return;
     const float t = block_sum(sq);
-    if (threadIdx.x == 0) atomic_add_f32(loss, t * inv_P);
+    if (threadIdx.x == 0) atomic_add_f32(&loss->part[blockIdx.x % SAD_LOSS_PARTS], t * inv_P);
+}
+
+// Fold the partials into value (added, or written if `overwrite`) and clear them.
+__global__ __launch_bounds__(64) void k_loss_fold(sad_loss_acc *__restrict__ loss, int overwrite) {
+    const int i = threadIdx.x;
+    float v = i < SAD_LOSS_PARTS ? loss->part[i] : 0.f;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (i < SAD_LOSS_PARTS) loss->part[i] = 0.f;
+    if (i == 0) loss->value = overwrite ? v : loss->value + v;
 }
 
 // Forward blend fused with the loss gradient (training step): writes dL/dc and,
@@ -152,7 +163,7 @@ __global__ __launch_bounds__(256) void k_fwd_loss(ImgArgs a, const float4 *__res
                                                   const float *__restrict__ tgt,
                                                   float *__restrict__ out,
                                                   float *__restrict__ gimg,
-                                                  float *__restrict__ loss) {
+                                                  sad_loss_acc *__restrict__ loss) {
     const int tile = xcd_tile(blockIdx.x, a.n_blocks);
     const TilePix px = tile_pixel(tile, a.tiles_x);
     float sq = 0.f;
@@ -172,18 +183,41 @@ __global__ __launch_bounds__(256) void k_fwd_loss(ImgArgs a, const float4 *__res
     }
     if (!loss) return;
     const float t = block_sum(sq);
-    if (threadIdx.x == 0) atomic_add_f32(loss, t * a.inv_P);
+    if (threadIdx.x == 0) atomic_add_f32(&loss->part[blockIdx.x % SAD_LOSS_PARTS], t * a.inv_P);
 }
 
 // ---- backward ---------------------------------------------------------------------
 // Per-tile hash table in LDS keyed by site ID (multiplicative hash, linear probing of
-// at most 8 slots, CAS insert, as in Sec. 4.8 Alg. hash_grad); every (pixel, entry)
-// contribution is added into its slot with LDS float atomics; entries that find no
-// slot go straight to global atomics.  After the tile, each occupied slot is flushed
-// with one global atomic per parameter.
+// at most 8 slots, CAS insert; Sec. 4.8, Alg. hash_grad, App. B.4).  Each (pixel,
+// entry) contribution is added into its slot's accumulators.  On gfx950 LDS float
+// atomics are slow even without address conflicts while integer atomics are fast, so
+// the accumulators are 64-bit fixed point: a term v becomes rint(v * 2^40 * 2^e) with
+// 2^e ~ P/2 (every term carries the 1/P of dL/dc).  Terms with |v| 2^e >= 2^15 go to
+// a float global atomic instead, so a tile sum (<= 256 terms per slot) stays below
+// 2^63.  After the tile, each occupied slot is flushed with one float global atomic
+// per parameter.
 constexpr int kHashSlots = 256;
 constexpr int kProbes = 8;
 constexpr int kAcc = 11;  // 10 parameters + removal delta
+
+struct FixScale {
+    double to_fix;     // 2^(40 + e)
+    double from_fix;   // 2^-(40 + e)
+    float limit;       // |v| must be below 2^(15 - e)
+};
+
+__device__ __forceinline__ unsigned long long to_fixed(float v, double scale) {
+    const double x = rint((double)v * scale);
+    const double hi = floor(x * 0x1p-32);
+    const double lo = fma(hi, -0x1p32, x);  // exact, in [0, 2^32)
+    return ((unsigned long long)(uint32_t)(int32_t)hi << 32) | (uint32_t)lo;
+}
+
+__device__ __forceinline__ float from_fixed(unsigned long long u, double inv_scale) {
+    const double hi = (double)(int32_t)(uint32_t)(u >> 32);
+    const double lo = (double)(uint32_t)u;
+    return (float)(fma(hi, 0x1p32, lo) * inv_scale);
+}
 
 __device__ __forceinline__ int hash_slot(uint32_t *__restrict__ hkey, uint32_t id) {
     const uint32_t h = (id * 2654435761u) >> 24;
@@ -201,17 +235,17 @@ __device__ __forceinline__ int hash_slot(uint32_t *__restrict__ hkey, uint32_t i
 }
 
 template <int K, bool kRD>
-__global__ __launch_bounds__(256) void k_bwd(ImgArgs a, const float4 *__restrict__ rec,
+__global__ __launch_bounds__(256) void k_bwd(ImgArgs a, FixScale fx, const float4 *__restrict__ rec,
                                              const uint4 *__restrict__ topk,
                                              const float *__restrict__ gimg,
                                              const float *__restrict__ tgt,
                                              float *__restrict__ grad, float *__restrict__ rdel) {
     __shared__ uint32_t hkey[kHashSlots];
-    __shared__ float hacc[kAcc][kHashSlots];
+    __shared__ unsigned long long hacc[kAcc][kHashSlots];
     const int t = threadIdx.x;
     hkey[t] = SAD_INVALID_ID;
 #pragma unroll
-    for (int q = 0; q < kAcc; ++q) hacc[q][t] = 0.f;
+    for (int q = 0; q < kAcc; ++q) hacc[q][t] = 0ull;
     __syncthreads();
 
     const int tile = xcd_tile(blockIdx.x, a.n_blocks);
@@ -263,7 +297,6 @@ __global__ __launch_bounds__(256) void k_bwd(ImgArgs a, const float4 *__restrict
                 e1 = b.c[1] - tgt[P + p];
                 e2 = b.c[2] - tgt[2 * P + p];
                 if (b.nv > 1) {
-                    // blend of the others, with their own maximum subtracted
                     float m2 = -INFINITY;
 #pragma unroll
                     for (int k = 0; k < K; ++k)
@@ -295,8 +328,7 @@ __global__ __launch_bounds__(256) void k_bwd(ImgArgs a, const float4 *__restrict
                 const float4 q0 = rec[4 * (size_t)id], q1 = rec[4 * (size_t)id + 1];
                 const float4 q2 = rec[4 * (size_t)id + 2], q3 = rec[4 * (size_t)id + 3];
                 const float w = b.e[k] * invS;
-                // c_k - c
-                const float d0 = (col[k][0] - cr0) - dc0;
+                const float d0 = (col[k][0] - cr0) - dc0;  // c_k - c
                 const float d1 = (col[k][1] - cr1) - dc1;
                 const float d2 = (col[k][2] - cr2) - dc2;
                 float acc[kAcc];
@@ -337,14 +369,14 @@ __global__ __launch_bounds__(256) void k_bwd(ImgArgs a, const float4 *__restrict
                                p2 * (p2 + 2.0f * e2)) * a.inv_P;
                 }
                 const int slot = hash_slot(hkey, id);
-                if (slot >= 0) {
+                constexpr int nq = kRD ? kAcc : 10;
 #pragma unroll
-                    for (int q = 0; q < 10; ++q) atomicAdd(&hacc[q][slot], acc[q]);
-                    if (kRD) atomicAdd(&hacc[10][slot], acc[10]);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 10; ++q) atomic_add_f32(grad + q * a.cap + id, acc[q]);
-                    if (kRD) atomic_add_f32(rdel + id, acc[10]);
+                for (int q = 0; q < nq; ++q) {
+                    float *dst = q < 10 ? grad + q * a.cap + id : rdel + id;
+                    if (slot >= 0 && fabsf(acc[q]) < fx.limit)
+                        atomicAdd(&hacc[q][slot], to_fixed(acc[q], fx.to_fix));
+                    else if (acc[q] != 0.0f)
+                        atomic_add_f32(dst, acc[q]);
                 }
             }
         }
@@ -352,9 +384,13 @@ __global__ __launch_bounds__(256) void k_bwd(ImgArgs a, const float4 *__restrict
     __syncthreads();
     const uint32_t id = hkey[t];
     if (id != SAD_INVALID_ID) {
+        constexpr int nq = kRD ? kAcc : 10;
 #pragma unroll
-        for (int q = 0; q < 10; ++q) atomic_add_f32(grad + q * a.cap + id, hacc[q][t]);
-        if (kRD) atomic_add_f32(rdel + id, hacc[10][t]);
+        for (int q = 0; q < nq; ++q) {
+            const unsigned long long u = hacc[q][t];
+            if (u) atomic_add_f32(q < 10 ? grad + q * a.cap + id : rdel + id,
+                                  from_fixed(u, fx.from_fix));
+        }
     }
 }
 
@@ -426,23 +462,28 @@ void sad::launch_fwd(const sad_image *img, const float *rec, const uint32_t *top
                                             l4, out));
 }
 
+void sad::launch_loss_fold(sad_loss_acc *loss, bool overwrite, hipStream_t st) {
+    hipLaunchKernelGGL(k_loss_fold, dim3(1), dim3(64), 0, st, loss, overwrite ? 1 : 0);
+}
+
 void sad::launch_loss_grad(const sad_image *img, const float *rendered, const float *target,
-                           float *grad, float *loss, hipStream_t st) {
+                           float *grad, sad_loss_acc *loss, bool overwrite, hipStream_t st) {
     const int64_t n3 = 3ll * img->H * img->W;
     int64_t nb = (n3 + 256 * 8 - 1) / (256 * 8);
     if (nb > 512) nb = 512;
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(k_loss_grad, dim3((unsigned)nb), dim3(256), 0, st, rendered, target, grad, n3,
                        (float)(1.0 / ((double)img->H * img->W)), loss);
+    if (loss) launch_loss_fold(loss, overwrite, st);
 }
 
 void sad::launch_fwd_loss(const sad_image *img, const float *rec, const uint32_t *topk,
-                          const float *target, float *rendered, float *grad_img, float *loss,
-                          hipStream_t st) {
-    if (img->n_slots == 0) {
+                          const float *target, float *rendered, float *grad_img,
+                          sad_loss_acc *loss, bool overwrite, hipStream_t st) {
+    if (img->n_slots == 0) {  // colour 0 everywhere; the loss kernel reads the zeros in place
         if (rendered) launch_fill_f32(rendered, 3ll * img->H * img->W, 0.0f, st);
         launch_fill_f32(grad_img, 3ll * img->H * img->W, 0.0f, st);
-        launch_loss_grad(img, grad_img, target, grad_img, loss, st);
+        launch_loss_grad(img, grad_img, target, grad_img, loss, overwrite, st);
         return;
     }
     const ImgArgs a = img_args(img);
@@ -450,6 +491,7 @@ void sad::launch_fwd_loss(const sad_image *img, const float *rec, const uint32_t
     const uint4 *l4 = reinterpret_cast<const uint4 *>(topk);
     SAD_K_SWITCH(img->K, hipLaunchKernelGGL(k_fwd_loss<KK>, dim3(a.n_blocks), dim3(256), 0, st, a,
                                             r4, l4, target, rendered, grad_img, loss));
+    if (loss) launch_loss_fold(loss, overwrite, st);
 }
 
 void sad::launch_bwd(const sad_image *img, const float *rec, const uint32_t *topk,
@@ -457,15 +499,22 @@ void sad::launch_bwd(const sad_image *img, const float *rec, const uint32_t *top
                      float *removal_delta, hipStream_t st) {
     if (img->n_slots == 0) return;
     const ImgArgs a = img_args(img);
+    const int64_t P = (int64_t)img->H * img->W;
+    int e = 0;
+    while ((int64_t)1 << (e + 1) < P) ++e;  // 2^e ~ P / 2
+    FixScale fx;
+    fx.to_fix = std::ldexp(1.0, 40 + e);
+    fx.from_fix = std::ldexp(1.0, -(40 + e));
+    fx.limit = (float)std::ldexp(1.0, 15 - e);
     const float4 *r4 = reinterpret_cast<const float4 *>(rec);
     const uint4 *l4 = reinterpret_cast<const uint4 *>(topk);
     if (removal_delta) {
         SAD_K_SWITCH(img->K, hipLaunchKernelGGL((k_bwd<KK, true>), dim3(a.n_blocks), dim3(256), 0,
-                                                st, a, r4, l4, grad_img, target, grad_sites,
+                                                st, a, fx, r4, l4, grad_img, target, grad_sites,
                                                 removal_delta));
     } else {
         SAD_K_SWITCH(img->K, hipLaunchKernelGGL((k_bwd<KK, false>), dim3(a.n_blocks), dim3(256), 0,
-                                                st, a, r4, l4, grad_img, target, grad_sites,
+                                                st, a, fx, r4, l4, grad_img, target, grad_sites,
                                                 removal_delta));
     }
 }
@@ -487,16 +536,17 @@ extern "C" sad_status sad_render_fwd(const sad_image *img, const float *rec, con
 }
 
 extern "C" sad_status sad_loss_grad(const sad_image *img, const float *rendered,
-                                    const float *target, float *grad, float *loss, void *stream) {
+                                    const float *target, float *grad, sad_loss_acc *loss,
+                                    void *stream) {
     SAD_TRY(check_image(img, nullptr));
     SAD_REQUIRE(rendered && target && grad, SAD_ERR_INVALID_ARGUMENT, "sad_loss_grad: NULL pointer");
-    launch_loss_grad(img, rendered, target, grad, loss, as_stream(stream));
+    launch_loss_grad(img, rendered, target, grad, loss, false, as_stream(stream));
     return check_launch("sad_loss_grad");
 }
 
 extern "C" sad_status sad_render_fwd_loss(const sad_image *img, const float *rec,
                                           const uint32_t *topk, const float *target,
-                                          float *rendered, float *grad_img, float *loss,
+                                          float *rendered, float *grad_img, sad_loss_acc *loss,
                                           void *stream) {
     SAD_TRY(check_image(img, nullptr));
     SAD_REQUIRE(topk && target && grad_img, SAD_ERR_INVALID_ARGUMENT,
@@ -505,7 +555,7 @@ extern "C" sad_status sad_render_fwd_loss(const sad_image *img, const float *rec
                 "sad_render_fwd_loss: topk not 16-byte aligned");
     SAD_REQUIRE(img->n_slots == 0 || (rec && aligned16(rec)), SAD_ERR_INVALID_ARGUMENT,
                 "sad_render_fwd_loss: bad rec");
-    launch_fwd_loss(img, rec, topk, target, rendered, grad_img, loss, as_stream(stream));
+    launch_fwd_loss(img, rec, topk, target, rendered, grad_img, loss, false, as_stream(stream));
     return check_launch("sad_render_fwd_loss");
 }
 

@@ -16,6 +16,14 @@ namespace sad {
 // The propagation pass reads q0..q1, the forward q0..q2, the backward all four.
 constexpr int kRecQ = 4;
 
+// Quadratic form q = d^T G d of the score (first half of score()).
+__device__ __forceinline__ float quad(const float4 q0, const float4 q1, float X, float Y) {
+    const float dx = __fsub_rn(X, q0.x);
+    const float dy = __fsub_rn(Y, q0.y);
+    const float t = __fmaf_rn(q0.w, dy, __fmul_rn(q0.z, dx));
+    return fmaxf(__fmaf_rn(t, dx, __fmul_rn(__fmul_rn(q1.x, dy), dy)), 0.0f);
+}
+
 // l = kappa (r - ||x - p||_G), evaluated in float32 as
 //   t = fma(2 G12, dy, G11 dx); q = fma(t, dx, (G22 dy) dy); q = max(q, 0);
 //   n = sqrt(q); l = kappa (r - n) + 0
@@ -63,6 +71,41 @@ __device__ __forceinline__ void insert_key(uint64_t (&keys)[K], uint64_t c) {
             c = gt ? kj : (eq ? 0ull : c);
         }
     }
+}
+
+// Sort keys[] descending with Batcher's odd-even merge network (Knuth TAOCP vol. 3,
+// 5.3.4); K is padded to the next power of two with empty (zero) keys.
+template <int K>
+struct Pow2 {
+    static constexpr int v = K <= 4 ? 4 : K <= 8 ? 8 : K <= 16 ? 16 : 32;
+};
+
+template <int N>
+__device__ __forceinline__ void ce_desc(uint64_t (&a)[N], int x, int y) {
+    const uint64_t ax = a[x], ay = a[y];
+    const bool sw = ax < ay;
+    a[x] = sw ? ay : ax;
+    a[y] = sw ? ax : ay;
+}
+
+template <int K>
+__device__ __forceinline__ void sort_keys_desc(uint64_t (&keys)[K]) {
+    constexpr int N = Pow2<K>::v;
+    uint64_t a[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) a[i] = i < K ? keys[i] : 0ull;
+#pragma unroll
+    for (int p = 1; p < N; p <<= 1)
+#pragma unroll
+        for (int k = p; k >= 1; k >>= 1)
+#pragma unroll
+            for (int j = k % p; j + k < N; j += 2 * k)
+#pragma unroll
+                for (int i = 0; i < k; ++i)
+                    if (i < N - j - k && (i + j) / (2 * p) == (i + j + k) / (2 * p))
+                        ce_desc<N>(a, i + j, i + j + k);
+#pragma unroll
+    for (int i = 0; i < K; ++i) keys[i] = a[i];
 }
 
 // SplitMix64 (Steele, Lea, Flood 2014): output number k of the stream seeded by seed.

@@ -17,11 +17,13 @@ void launch_propagate(const sad_image *img, const float *rec, const uint32_t *in
 void launch_fwd(const sad_image *img, const float *rec, const uint32_t *topk, float *out,
                 hipStream_t st);
 void launch_loss_grad(const sad_image *img, const float *rendered, const float *target,
-                      float *grad, float *loss, hipStream_t st);
+                      float *grad, sad_loss_acc *loss, bool overwrite, hipStream_t st);
+// Fold loss->part into loss->value (added, or written if overwrite) and clear part[].
+void launch_loss_fold(sad_loss_acc *loss, bool overwrite, hipStream_t st);
 // Forward blend fused with the loss gradient; rendered may be NULL.
 void launch_fwd_loss(const sad_image *img, const float *rec, const uint32_t *topk,
-                     const float *target, float *rendered, float *grad_img, float *loss,
-                     hipStream_t st);
+                     const float *target, float *rendered, float *grad_img, sad_loss_acc *loss,
+                     bool overwrite, hipStream_t st);
 void launch_bwd(const sad_image *img, const float *rec, const uint32_t *topk, const float *grad_img,
                 const float *target, float *grad_sites, float *removal_delta, hipStream_t st);
 // Adam; if step_dev != NULL the step is *step_dev + 1 (device), else `step`.  If

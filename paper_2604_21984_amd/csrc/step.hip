@@ -20,7 +20,7 @@ extern "C" sad_status sad_train_step(const sad_image *img, const sad_train_confi
                                      const float *target, float *sites, float *rec,
                                      const uint32_t *topk_in, uint32_t *topk_out, float *grad_sites,
                                      float *adam_m, float *adam_v, float *rendered, float *grad_img,
-                                     float *loss, sad_step_state *state, void *stream) {
+                                     sad_step_state *state, void *stream) {
     float s;
     SAD_TRY(check_image(img, &s));
     SAD_REQUIRE(cfg && state, SAD_ERR_INVALID_ARGUMENT, "sad_train_step: cfg / state is NULL");
@@ -36,8 +36,7 @@ extern "C" sad_status sad_train_step(const sad_image *img, const sad_train_confi
     hipStream_t st = as_stream(stream);
     launch_propagate(img, rec, topk_in, topk_out, cfg->fixed_jump > 0 ? cfg->fixed_jump : 0,
                      cfg->n_inject, cfg->seed, 0, &state->pass, st);
-    if (loss) launch_fill_f32(loss, 1, 0.0f, st);
-    launch_fwd_loss(img, rec, topk_out, target, rendered, grad_img, loss, st);
+    launch_fwd_loss(img, rec, topk_out, target, rendered, grad_img, &state->loss, true, st);
     launch_bwd(img, rec, topk_out, grad_img, nullptr, grad_sites, nullptr, st);
     launch_adam(img, s, sites, grad_sites, adam_m, adam_v, &cfg->adam, 1, &state->adam_step, rec,
                 true, st);

@@ -66,8 +66,7 @@ class Encoder:
         self.v = torch.zeros((S.NPARAM, cap), **f32)
         self.rendered = torch.empty((3, H, W), **f32)
         self.grad_img = torch.empty((3, H, W), **f32)
-        self.loss = torch.zeros(1, **f32)
-        self.state = torch.zeros(2, dtype=torch.int64, device=dev)
+        self.state = S.step_state(dev)
         lt0 = cfg.log_tau0 if cfg.log_tau0 is not None else default_log_tau(H, W, n_sites)
         ws = torch.empty(S.init_workspace_bytes(self.img), dtype=torch.uint8, device=dev)
         S.init_sites(self.img, self.target, n_sites, cfg.lam_init, cfg.seed, lt0, cfg.r0,
@@ -81,6 +80,14 @@ class Encoder:
         self.graph = None
         self.steps = 0
 
+    def loss_value(self):
+        """L of the last iteration (synchronises)."""
+        return float(S.state_loss(self.state).item())
+
+    def counters(self):
+        """(pass, adam_step) device counters (synchronises)."""
+        return [int(v) for v in S.state_counters(self.state).tolist()]
+
     @property
     def topk(self):
         return self.lists[self.cur]
@@ -89,7 +96,7 @@ class Encoder:
         """One training iteration, enqueued on the current stream (no host sync)."""
         a, b = self.lists[self.cur], self.lists[1 - self.cur]
         S.train_step(self.img, self.train_cfg, self.target, self.sites, self.rec, a, b, self.grad,
-                     self.m, self.v, None, self.grad_img, self.loss, self.state)
+                     self.m, self.v, None, self.grad_img, self.state)
         self.cur = 1 - self.cur
         self.steps += 1
 

@@ -191,11 +191,13 @@ def test_loss_grad(S):
     b = rng.uniform(0, 1, (3, H, W)).astype(np.float32)
     img = S.image(H, W, 4, 1)
     grad = torch.empty((3, H, W), dtype=torch.float32, device=DEV)
-    loss = torch.zeros(1, dtype=torch.float32, device=DEV)
+    loss = S.loss_acc(DEV)
     S.loss_grad(img, _t(a), _t(b), grad, loss)
+    S.loss_grad(img, _t(a), _t(b), grad, loss)        # adds: value = 2 L, parts left at 0
     L, gref = O.loss_grad(a.astype(np.float64), b)
     torch.cuda.synchronize()
-    assert abs(loss.item() - L) <= 1e-5 * L
+    assert abs(loss[0].item() - 2 * L) <= 2e-5 * L
+    assert torch.all(loss[1:] == 0)
     np.testing.assert_allclose(grad.cpu().numpy(), gref, atol=1e-9, rtol=1e-5)
 
 
