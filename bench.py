@@ -28,15 +28,13 @@ def algorithmic_bytes(kernel, P, N, K):
     """Bytes a kernel must move per launch, each unique byte once: list field reads and
     writes, site records, images and gradients (neighbour-list re-reads and repeated
     site gathers are cache traffic, not counted)."""
-    rec_prop, rec_fwd, rec_bwd = 32, 48, 64
-    if kernel == "prop":
-        return P * 8 * K + N * rec_prop
-    if kernel == "fwd_loss":
-        return P * (4 * K + 24) + N * rec_fwd
-    if kernel == "bwd":
-        return P * (4 * K + 12) + N * (rec_bwd + 40)
+    if kernel == "train_pass":
+        # read the previous list, write the new one, read the target; per site one
+        # derived record in, one gradient row out
+        return P * (8 * K + 12) + N * (64 + 40)
     if kernel == "adam":
-        return N * (40 * 7 + 64)
+        # sites, m, v read + written, gradient read + cleared, derived record written
+        return N * (40 * 8 + 64)
     return 0
 
 
@@ -114,32 +112,27 @@ def main():
     loss = enc.loss_value()
     psnr = enc.psnr()
 
-    # ---- per-kernel breakdown: the same kernels launched one by one, timed with events
-    # on their stream; a spin kernel first keeps the queue ahead of the host.
+    # ---- per-kernel breakdown: the kernels of the step launched one by one, timed with
+    # events on their stream; a spin kernel first keeps the queue ahead of the host.
     P = H * W
-    names = ["prop", "fwd_loss", "bwd", "adam"]
+    names = ["train_pass", "adam"]
     acc = {k: 0.0 for k in names}
     nb = args.breakdown_steps
     img = enc.img
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(len(names) + 1)] for _ in range(nb)]
     st = enc.counters()
-    lacc = S.loss_acc(dev)
     torch.cuda.synchronize()
     torch.cuda._sleep(int(2e8))
     for it in range(nb):
         a, b = enc.lists[enc.cur], enc.lists[1 - enc.cur]
-        t_pass = int(st[0]) + it
         E = ev[it]
         E[0].record(stream)
-        S.propagate_topk(img, enc.rec, a, b, S.jump_step(t_pass, H, W), J, 7, t_pass)
+        S.train_image_pass(img, enc.train_cfg, enc.target, enc.rec, a, b, enc.grad, None, None,
+                           enc.state)
         E[1].record(stream)
-        S.render_fwd_loss(img, enc.rec, b, enc.target, enc.grad_img, None, lacc)
-        E[2].record(stream)
-        S.render_bwd(img, enc.rec, b, enc.grad_img, enc.grad)
-        E[3].record(stream)
-        S.adam_step(img, enc.sites, enc.grad, enc.m, enc.v, enc.adam, int(st[1]) + it + 1, enc.rec,
+        S.adam_step(img, enc.sites, enc.grad, enc.m, enc.v, enc.adam, st[1] + it + 1, enc.rec,
                     zero_grad=True)
-        E[4].record(stream)
+        E[2].record(stream)
         enc.cur = 1 - enc.cur
     torch.cuda.synchronize()
     for it in range(nb):

@@ -177,6 +177,25 @@ sad_status sad_adam_step(const sad_image *img, float *sites, float *grad, float 
 sad_status sad_query_points(const sad_image *img, const float *rec, const uint32_t *topk,
                             const float *xy, int64_t M, float *out, void *stream);
 
+/* Point queries of many requests against many resident site sets in one launch (the
+ * serving path).  Job j answers M_j points of one set: the same computation as
+ * sad_query_points, so a result does not depend on the other jobs of the launch.
+ * All sets of one call share K.  jobs: DEVICE array [n_jobs] with q0 (the first
+ * global point index of the job) increasing; total = sum of M_j. */
+typedef struct {
+    const float *rec;       /* derived records of the set */
+    const uint32_t *topk;   /* its list field */
+    const float *xy;        /* [M][2] query points */
+    float *out;             /* [M][3] colours */
+    int64_t M;
+    int64_t q0;
+    int32_t H, W, n_slots;
+    int32_t pad;
+} sad_query_job;
+
+sad_status sad_query_batch(const sad_query_job *jobs, int32_t n_jobs, int64_t total, int32_t K,
+                           void *stream);
+
 /* ---- initialisation (Sec. 4.4) ----------------------------------------------------
  * P_init(x) = (1 - lambda) |grad I(x)| / sum |grad I| + lambda / (H W), |grad I| the
  * Frobenius norm over RGB of edge-clamped central differences.  Draws n_sites distinct
@@ -210,10 +229,11 @@ typedef struct {
 
 /* One iteration (Sec. 5: no host work inside the loop), enqueued as:
  *   1. propagation pass topk_in -> topk_out with pass index state->pass;
- *   2. forward blend with topk_out fused with the loss gradient: grad_img [3][H][W]
- *      = dL/dc, the image itself into rendered [3][H][W] if rendered != NULL, L into
- *      state->loss.value;
+ *   2. the forward blend of topk_out and the loss gradient dL/dc, written to grad_img
+ *      [3][H][W] if grad_img != NULL, the image to rendered [3][H][W] if rendered !=
+ *      NULL, L to state->loss.value;
  *   3. the backward scatter into grad_sites [10][cap], which must be zero on entry;
+ *   (1-3 are one kernel: the new keys of a pixel carry the scores its blend needs.)
  *   4. Adam step number state->adam_step + 1 (clamps, renormalised u), rec refreshed,
  *      grad_sites cleared again (ready for the next call);
  *   5. state->pass += 1, state->adam_step += 1.
@@ -224,6 +244,57 @@ sad_status sad_train_step(const sad_image *img, const sad_train_config *cfg, con
                           float *sites, float *rec, const uint32_t *topk_in, uint32_t *topk_out,
                           float *grad_sites, float *adam_m, float *adam_v, float *rendered,
                           float *grad_img, sad_step_state *state, void *stream);
+
+/* Steps 1-3 of sad_train_step alone (rows a3-a6 as one kernel): the propagation pass
+ * with pass index state->pass (not advanced), the blend, the loss gradient (L added to
+ * state->loss.value) and the backward into grad_sites (accumulated, +=).  Same argument
+ * meaning as sad_train_step. */
+sad_status sad_train_image_pass(const sad_image *img, const sad_train_config *cfg,
+                                const float *target, const float *rec, const uint32_t *topk_in,
+                                uint32_t *topk_out, float *grad_sites, float *rendered,
+                                float *grad_img, sad_step_state *state, void *stream);
+
+/* ---- a8: batched training of many images in one persistent launch ----------------
+ * Images of uneven size and site budget share pooled buffers.  Image b's blocks start
+ * at fixed offsets: pixel pools (target [3][P_b] at 3*px0 floats, each list field
+ * [K/4][P_b][4] at K*px0 words, optional rendered / grad_img [3][P_b] at 3*px0 floats)
+ * and site pools (sites, grad, m, v [10][cap_b] at 10*site0 floats, derived records
+ * [cap_b][16] at 16*site0 floats).  All images use the batch's K. */
+typedef struct {
+    int32_t H, W;
+    int32_t n_slots;
+    int32_t tile0;      /* first work item (16x16 tile) of this image; items are
+                           numbered image by image in raster order of tiles */
+    int64_t cap;
+    int64_t px0;        /* pixels of the images before this one */
+    int64_t site0;      /* site slots (sum of cap) of the images before this one */
+    float score_scale;  /* 0 => 1 / max(H, W) */
+    int32_t pad;
+} sad_batch_image;
+
+typedef struct {
+    int32_t n_images;
+    int32_t K;
+    int32_t n_items;           /* total 16x16 tiles of all images */
+    int32_t grid;              /* persistent workgroups; 0 => one per tile */
+    int32_t chunked;           /* 0: item i goes to workgroup i mod grid; 1: each
+                                  workgroup takes a contiguous run of items (its XCD's
+                                  L2 then holds neighbouring tiles) */
+    int32_t pad;
+    int64_t n_site_slots;      /* sum of cap over the images */
+    const sad_batch_image *images;  /* DEVICE array [n_images], tile0 increasing */
+} sad_batch;
+
+/* One training iteration of every image of the batch (sad_train_step semantics per
+ * image; image b uses states[b]): one persistent image-space kernel over all tiles of
+ * all images, then per-image loss folds, one Adam kernel over all site slots and one
+ * state update, whatever the number of images.  batch: host struct whose `images`
+ * points to device memory; states: device [n_images]; rendered, grad_img nullable. */
+sad_status sad_batch_train_step(const sad_batch *batch, const sad_train_config *cfg,
+                                const float *target, float *sites, float *rec,
+                                const uint32_t *topk_in, uint32_t *topk_out, float *grad_sites,
+                                float *adam_m, float *adam_v, float *rendered, float *grad_img,
+                                sad_step_state *states, void *stream);
 
 /* ---- diagnostics ------------------------------------------------------------------ */
 const char *sad_status_string(sad_status s);

@@ -42,6 +42,24 @@ class SadTrainConfig(C.Structure):
                 ("adam", SadAdamParams)]
 
 
+class SadBatchImage(C.Structure):
+    _fields_ = [("H", C.c_int32), ("W", C.c_int32), ("n_slots", C.c_int32), ("tile0", C.c_int32),
+                ("cap", C.c_int64), ("px0", C.c_int64), ("site0", C.c_int64),
+                ("score_scale", C.c_float), ("pad", C.c_int32)]
+
+
+class SadBatch(C.Structure):
+    _fields_ = [("n_images", C.c_int32), ("K", C.c_int32), ("n_items", C.c_int32),
+                ("grid", C.c_int32), ("chunked", C.c_int32), ("pad", C.c_int32),
+                ("n_site_slots", C.c_int64), ("images", C.c_void_p)]
+
+
+class SadQueryJob(C.Structure):
+    _fields_ = [("rec", C.c_void_p), ("topk", C.c_void_p), ("xy", C.c_void_p), ("out", C.c_void_p),
+                ("M", C.c_int64), ("q0", C.c_int64), ("H", C.c_int32), ("W", C.c_int32),
+                ("n_slots", C.c_int32), ("pad", C.c_int32)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
@@ -60,6 +78,10 @@ def _load():
         "sad_query_points": [IMG, P, P, P, I64, P, P],
         "sad_init_sites": [IMG, P, I32, F32, U64, F32, F32, P, P, C.POINTER(SZ), P],
         "sad_train_step": [IMG, C.POINTER(SadTrainConfig), P, P, P, P, P, P, P, P, P, P, P, P],
+        "sad_train_image_pass": [IMG, C.POINTER(SadTrainConfig), P, P, P, P, P, P, P, P, P],
+        "sad_query_batch": [P, I32, I64, I32, P],
+        "sad_batch_train_step": [C.POINTER(SadBatch), C.POINTER(SadTrainConfig), P, P, P, P, P, P,
+                                 P, P, P, P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -276,3 +298,44 @@ def train_step(img, cfg, target, sites, rec, topk_in, topk_out, grad, m, v, rend
                               _ptr(grad_img, torch.float32, 3 * P, "grad_img"),
                               _ptr(state, torch.int64, STEP_STATE_INT64, "state"), _stream()),
            "sad_train_step")
+
+
+def train_image_pass(img, cfg, target, rec, topk_in, topk_out, grad, rendered, grad_img, state):
+    """Rows a3-a6 of one iteration as one kernel (sad_train_image_pass)."""
+    P = img.H * img.W
+    _check(lib.sad_train_image_pass(C.byref(img), C.byref(cfg), _ptr(target, torch.float32, 3 * P, "target"),
+                                    _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                                    _ptr(topk_in, torch.int32, img.K * P, "topk_in"),
+                                    _ptr(topk_out, torch.int32, img.K * P, "topk_out"),
+                                    _ptr(grad, torch.float32, NPARAM * img.cap, "grad"),
+                                    _ptr(rendered, torch.float32, 3 * P, "rendered"),
+                                    _ptr(grad_img, torch.float32, 3 * P, "grad_img"),
+                                    _ptr(state, torch.int64, STEP_STATE_INT64, "state"), _stream()),
+           "sad_train_image_pass")
+
+
+def batch_train_step(batch, cfg, target, sites, rec, topk_in, topk_out, grad, m, v, rendered,
+                     grad_img, states):
+    """One iteration of every image of a batch (sad_batch_train_step).  Buffers are the
+    pooled tensors; states: int64 tensor of n_images sad_step_state records."""
+    n = NPARAM * batch.n_site_slots
+    _check(lib.sad_batch_train_step(C.byref(batch), C.byref(cfg), _ptr(target, torch.float32, None, "target"),
+                                    _ptr(sites, torch.float32, n, "sites"),
+                                    _ptr(rec, torch.float32, REC_FLOATS * batch.n_site_slots, "rec"),
+                                    _ptr(topk_in, torch.int32, None, "topk_in"),
+                                    _ptr(topk_out, torch.int32, None, "topk_out"),
+                                    _ptr(grad, torch.float32, n, "grad"), _ptr(m, torch.float32, n, "m"),
+                                    _ptr(v, torch.float32, n, "v"),
+                                    _ptr(rendered, torch.float32, None, "rendered"),
+                                    _ptr(grad_img, torch.float32, None, "grad_img"),
+                                    _ptr(states, torch.int64, STEP_STATE_INT64 * batch.n_images, "states"),
+                                    _stream()),
+           "sad_batch_train_step")
+
+
+def query_batch(jobs_dev, n_jobs, total, K):
+    """Point queries of many jobs (sad_query_batch); jobs_dev: device uint8 tensor holding
+    n_jobs SadQueryJob records."""
+    _check(lib.sad_query_batch(C.c_void_p(jobs_dev.data_ptr()), int(n_jobs), int(total), int(K),
+                               _stream()),
+           "sad_query_batch")

@@ -1,0 +1,71 @@
+"""Autotuner for the batched persistent launch.
+
+Picks the persistent grid size (workgroups per compute unit) and the work assignment
+(contiguous runs of tiles per workgroup, which keeps neighbouring tiles in one XCD's L2,
+or round robin) by timing graph-replayed iterations of the actual batch.  The batch's
+state is restored after the trials, so tuning does not change the encode.  Results are
+cached per workload signature (image shapes, site counts, K) in memory and optionally
+in a JSON file.
+"""
+import json
+import os
+
+import torch
+
+
+def _signature(enc):
+    return f"K{enc.K}|" + ";".join(f"{h}x{w}:{n}" for (h, w), n in zip(enc.shapes, enc.n_sites))
+
+
+def candidates(n_items, n_cu):
+    out = [(0, 0)]  # one workgroup per tile
+    for per_cu in (2, 3, 4, 6, 8):
+        g = per_cu * n_cu
+        if g < n_items:
+            out += [(g, 1), (g, 0)]
+    return out
+
+
+class Autotuner:
+    def __init__(self, cache_path=None):
+        self.cache_path = cache_path
+        self.cache = {}
+        if cache_path and os.path.exists(cache_path):
+            with open(cache_path) as f:
+                self.cache = json.load(f)
+
+    def tune(self, enc, pairs=3, reps=2):
+        """Return (grid, chunked, timings) for a BatchEncoder and apply the best."""
+        sig = _signature(enc)
+        if sig in self.cache:
+            grid, chunked = self.cache[sig]["best"]
+            enc.set_launch(grid, chunked)
+            return grid, chunked, self.cache[sig]["timings"]
+        n_cu = torch.cuda.get_device_properties(enc.device).multi_processor_count
+        snap = enc.snapshot()
+        timings = {}
+        for grid, chunked in candidates(enc.T_tot, n_cu):
+            enc.restore(snap)
+            enc.set_launch(grid, chunked)
+            enc.capture()
+            enc.replay(1)
+            torch.cuda.synchronize()
+            best = float("inf")
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                enc.replay(pairs)
+                e1.record()
+                torch.cuda.synchronize()
+                best = min(best, e0.elapsed_time(e1) / (2 * pairs))
+            timings[f"{grid}/{chunked}"] = best
+        enc.restore(snap)
+        key = min(timings, key=timings.get)
+        grid, chunked = (int(x) for x in key.split("/"))
+        enc.set_launch(grid, chunked)
+        self.cache[sig] = {"best": [grid, chunked], "timings": timings}
+        if self.cache_path:
+            with open(self.cache_path, "w") as f:
+                json.dump(self.cache, f, indent=1)
+        return grid, chunked, timings

@@ -1,0 +1,514 @@
+// sad_kernels.h -- per-pixel device routines shared by the kernels: propagation of one
+// pixel's list (Sec. 4.3), the soft blend (Sec. 4.2) and the backward contributions
+// with the per-tile fixed-point LDS table (App. B.4, Sec. 4.8).
+#pragma once
+
+#include <cmath>
+
+#include "sad_device.h"
+#include "sad_internal.h"
+
+namespace sad {
+
+struct ImgArgs {
+    int H, W, n_slots, tiles_x, n_blocks;
+    int64_t cap;
+    float inv_P;
+};
+
+// Valid entries of one pixel's list with their scores (K registers each).
+template <int K>
+struct PixelBlend {
+    uint32_t id[K];
+    float l[K];
+    float e[K];
+    bool ok[K];
+    float S, c[3];
+    int nv;
+};
+
+// Gather and score the list of pixel p at point (X, Y); max-subtracted softmax; colour.
+// Rotate ids[] left by `rot` (0 <= rot < 8) with three conditional stages.  Used by the
+// backward so that neighbouring lanes work on different ranks of their (similar) lists
+// in the same instruction, which spreads their LDS atomics over different sites.
+template <int K>
+__device__ __forceinline__ void rotate_ids(uint32_t (&ids)[K], int rot) {
+#pragma unroll
+    for (int st = 1; st < 8 && st < K; st <<= 1) {
+        const bool c = (rot & st) != 0;
+        uint32_t t[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) t[j] = c ? ids[(j + st) % K] : ids[j];
+#pragma unroll
+        for (int j = 0; j < K; ++j) ids[j] = t[j];
+    }
+}
+
+template <int K, bool kNeedN>
+__device__ __forceinline__ void blend(const float4 *__restrict__ rec, uint32_t ns,
+                                      const uint4 *__restrict__ topk, int64_t P, int64_t p,
+                                      float X, float Y, PixelBlend<K> &b, float (*col)[3],
+                                      float *nrm, int rot = 0) {
+    float m = -INFINITY;
+    b.nv = 0;
+    uint32_t ids[K];
+#pragma unroll
+    for (int g = 0; g < K / 4; ++g) {
+        const uint4 v = topk[(int64_t)g * P + p];
+        ids[4 * g] = v.x;
+        ids[4 * g + 1] = v.y;
+        ids[4 * g + 2] = v.z;
+        ids[4 * g + 3] = v.w;
+    }
+    if (rot) rotate_ids<K>(ids, rot);
+#pragma unroll
+    for (int g = 0; g < K / 4; ++g) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = 4 * g + t;
+            const uint32_t id = ids[k];
+            const bool in_range = id < ns;
+            const uint32_t idc = in_range ? id : 0u;
+            const float4 q0 = rec[4 * (size_t)idc], q1 = rec[4 * (size_t)idc + 1];
+            const float4 q2 = rec[4 * (size_t)idc + 2];
+            b.id[k] = idc;
+            b.ok[k] = in_range && q1.w != 0.0f;
+            float n;
+            b.l[k] = score(q0, q1, X, Y, &n);
+            if (kNeedN) nrm[k] = n;
+            col[k][0] = q2.x;
+            col[k][1] = q2.y;
+            col[k][2] = q2.z;
+            if (b.ok[k]) {
+                m = fmaxf(m, b.l[k]);
+                ++b.nv;
+            }
+        }
+    }
+    b.S = 0.f;
+    b.c[0] = b.c[1] = b.c[2] = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        b.e[k] = b.ok[k] ? __expf(b.l[k] - m) : 0.0f;
+        b.S += b.e[k];
+        b.c[0] = fmaf(b.e[k], col[k][0], b.c[0]);
+        b.c[1] = fmaf(b.e[k], col[k][1], b.c[1]);
+        b.c[2] = fmaf(b.e[k], col[k][2], b.c[2]);
+    }
+    if (b.nv) {
+        const float inv = __builtin_amdgcn_rcpf(b.S);
+        b.c[0] *= inv;
+        b.c[1] *= inv;
+        b.c[2] *= inv;
+    }
+}
+
+// The blend of a pixel from its freshly propagated keys (sorted descending, so entry 0
+// holds the maximum score): the scores are the keys' own exact float32 scores; the
+// norms are recomputed for the backward.
+template <int K, bool kNeedN>
+__device__ __forceinline__ void blend_keys(const float4 *__restrict__ rec, const uint64_t (&keys)[K],
+                                           float X, float Y, PixelBlend<K> &b, float (*col)[3],
+                                           float *nrm) {
+    b.nv = 0;
+    const float m = keys[0] ? key_score(keys[0]) : 0.0f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        b.ok[k] = keys[k] != 0ull;
+        const uint32_t id = b.ok[k] ? key_id(keys[k]) : 0u;
+        b.id[k] = id;
+        b.l[k] = b.ok[k] ? key_score(keys[k]) : 0.0f;
+        const float4 q2 = rec[4 * (size_t)id + 2];
+        col[k][0] = q2.x;
+        col[k][1] = q2.y;
+        col[k][2] = q2.z;
+        if (kNeedN) {
+            const float4 q0 = rec[4 * (size_t)id], q1 = rec[4 * (size_t)id + 1];
+            nrm[k] = __fsqrt_rn(quad(q0, q1, X, Y));
+        }
+        b.nv += b.ok[k] ? 1 : 0;
+    }
+    b.S = 0.f;
+    b.c[0] = b.c[1] = b.c[2] = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        b.e[k] = b.ok[k] ? __expf(b.l[k] - m) : 0.0f;
+        b.S += b.e[k];
+        b.c[0] = fmaf(b.e[k], col[k][0], b.c[0]);
+        b.c[1] = fmaf(b.e[k], col[k][1], b.c[1]);
+        b.c[2] = fmaf(b.e[k], col[k][2], b.c[2]);
+    }
+    if (b.nv) {
+        const float inv = __builtin_amdgcn_rcpf(b.S);
+        b.c[0] *= inv;
+        b.c[1] *= inv;
+        b.c[2] *= inv;
+    }
+}
+
+__device__ __forceinline__ float block_sum(float v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __shared__ float part[4];
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const float r = (part[0] + part[1]) + (part[2] + part[3]);
+    __syncthreads();
+    return r;
+}
+
+// ---- propagation ------------------------------------------------------------------
+struct PropArgs {
+    int H, W, n_slots, jump, J, tiles_x, n_blocks;
+    uint64_t seed, pass;
+    const int64_t *pass_dev;  // device pass index (graph-replayable), or NULL
+};
+
+// One thread per pixel, 16x16 tiles (four 8x8 wave64 blocks).
+//  1. The pixel's own list is scored exactly and sorted (Batcher network); the K-th
+//     key is the admission threshold.
+//  2. Every other candidate (the four lists at +-jump inside the image, then the J
+//     injected IDs) is first screened cheaply: an ID already kept is a repeat (equal
+//     key, never inserted); otherwise the score is estimated with the hardware square
+//     root (<= 1 ulp) and rejected if it is below the threshold by more than a bound on
+//     the estimate's error.  The bound: with |n_a - n| <= 2^-22 n, the float32 score
+//     differs from the exact sequence by at most 2^-21 (kappa (|r| + n) + |l|); the
+//     test uses 2^-19 of that sum.
+//  3. Survivors are queued in LDS and scored exactly before the queue could overflow
+//     and at the end, then bubbled into the sorted key array.
+// A candidate is only ever discarded when its exact key is below the K-th key, so the
+// result is the exact top K of the candidate set, as in the plain definition.
+template <int K>
+struct QueueDepth {
+    static constexpr int v = K + 8;  // room for one whole list (or 4 injections) after a check
+};
+
+// The new list of pixel (px.i, px.j) into keys[] (sorted, 0 = empty).  Lanes of pixels
+// outside the image must not call it (it votes across the wave, so call it from a
+// branch that those lanes skip).  queue: the kernel's LDS queue, Q x 256 words.
+template <int K>
+__device__ __forceinline__ void prop_pixel(const PropArgs &a, const float4 *__restrict__ rec,
+                                           const uint4 *__restrict__ lin, TilePix px,
+                                           uint32_t (*queue)[256], uint64_t (&keys)[K]) {
+    constexpr int Q = QueueDepth<K>::v;
+    const int tid = threadIdx.x;
+    const int64_t P = (int64_t)a.H * a.W;
+    const int64_t p = (int64_t)px.i * a.W + px.j;
+    const float X = (float)px.j, Y = (float)px.i;
+    const uint32_t ns = (uint32_t)a.n_slots;
+    const uint64_t pass = a.pass_dev ? (uint64_t)*a.pass_dev : a.pass;
+    const int s = (a.pass_dev && a.jump <= 0) ? jump_of((int64_t)pass, a.H, a.W) : a.jump;
+
+    auto exact_key = [&](uint32_t id) __attribute__((always_inline)) -> uint64_t {
+        const bool in_range = id < ns;
+        const uint32_t idc = in_range ? id : 0u;
+        const float4 q0 = rec[4 * (size_t)idc], q1 = rec[4 * (size_t)idc + 1];
+        return (in_range && q1.w != 0.0f) ? make_key(score(q0, q1, X, Y), id) : 0ull;
+    };
+
+    // 1. own list
+#pragma unroll
+    for (int g = 0; g < K / 4; ++g) {
+        const uint4 v = lin[(int64_t)g * P + p];
+        keys[4 * g] = exact_key(v.x);
+        keys[4 * g + 1] = exact_key(v.y);
+        keys[4 * g + 2] = exact_key(v.z);
+        keys[4 * g + 3] = exact_key(v.w);
+    }
+    sort_keys_desc<K>(keys);
+    bool rep = false;
+#pragma unroll
+    for (int k = 1; k < K; ++k) rep = rep || (keys[k] != 0ull && keys[k] == keys[k - 1]);
+    if (rep) {  // a repeated ID in the input list: rebuild as a set
+        uint64_t t[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            t[k] = keys[k];
+            keys[k] = 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) insert_key<K>(keys, t[k]);
+    }
+    float kth = keys[K - 1] ? key_score(keys[K - 1]) : -INFINITY;
+    int qn = 0;
+
+    auto screen = [&](uint32_t id) __attribute__((always_inline)) {
+        const bool in_range = id < ns;
+        const uint32_t idc = in_range ? id : 0u;
+        const float4 q0 = rec[4 * (size_t)idc], q1 = rec[4 * (size_t)idc + 1];
+        const uint32_t nid = ~id;
+        bool kept = false;
+#pragma unroll
+        for (int k = 0; k < K; ++k) kept = kept || ((uint32_t)keys[k] == nid);
+        const float na = __builtin_amdgcn_sqrtf(quad(q0, q1, X, Y));
+        const float la = q1.y * (q1.z - na);
+        const float bound = fmaf(q1.y, fabsf(q1.z) + na, fabsf(la)) * 0x1p-19f;
+        const bool maybe = in_range && q1.w != 0.0f && !kept &&
+                           (keys[K - 1] == 0ull || la + bound >= kth);
+        if (maybe) queue[qn++][tid] = id;
+    };
+    auto drain_if = [&](int room) __attribute__((always_inline)) {
+        if (__any(qn > Q - room)) {
+            for (int i = 0; i < Q; ++i) {
+                if (!__any(i < qn)) break;
+                if (i < qn) insert_key<K>(keys, exact_key(queue[i][tid]));
+            }
+            qn = 0;
+            kth = keys[K - 1] ? key_score(keys[K - 1]) : -INFINITY;
+        }
+    };
+
+    // 2. screen the other candidates: the four lists at +-jump, then the injections
+#pragma unroll 1
+    for (int nb = 0; nb < 4; ++nb) {
+        const int di = nb == 2 ? s : (nb == 3 ? -s : 0);
+        const int dj = nb == 0 ? s : (nb == 1 ? -s : 0);
+        const int ii = px.i + di, jj = px.j + dj;
+        drain_if(K);
+        if (ii >= 0 && ii < a.H && jj >= 0 && jj < a.W) {
+            const int64_t q = (int64_t)ii * a.W + jj;
+#pragma unroll
+            for (int g = 0; g < K / 4; ++g) {
+                const uint4 v = lin[(int64_t)g * P + q];
+                screen(v.x);
+                screen(v.y);
+                screen(v.z);
+                screen(v.w);
+            }
+        }
+    }
+    const uint64_t k0 = (pass * (uint64_t)P + (uint64_t)p) * (uint64_t)a.J;
+#pragma unroll 1
+    for (int j = 0; j < a.J; j += 4) {
+        drain_if(4);
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj)
+            if (j + jj < a.J) {
+                const uint64_t hi = splitmix64(a.seed, k0 + (uint64_t)(j + jj)) >> 32;
+                screen((uint32_t)((hi * (uint64_t)ns) >> 32));
+            }
+    }
+    // 3. remaining survivors
+    drain_if(Q + 1);
+}
+
+
+// ---- backward ---------------------------------------------------------------------
+// Per-tile hash table in LDS keyed by site ID (multiplicative hash, linear probing of
+// at most 8 slots, CAS insert; Sec. 4.8, Alg. hash_grad, App. B.4).  Each (pixel,
+// entry) contribution is added into its slot's accumulators.  On gfx950 LDS float
+// atomics are slow even without address conflicts while integer atomics are fast, so
+// the accumulators are 64-bit fixed point: a term v becomes rint(v * 2^40 * 2^e) with
+// 2^e ~ P/2 (every term carries the 1/P of dL/dc).  Terms with |v| 2^e >= 2^15 go to
+// a float global atomic instead, so a tile sum (<= 256 terms per slot) stays below
+// 2^63.  After the tile, each occupied slot is flushed with one float global atomic
+// per parameter.
+constexpr int kHashSlots = 256;
+constexpr int kProbes = 8;
+constexpr int kAcc = 11;  // 10 parameters + removal delta
+
+struct FixScale {
+    double to_fix;     // 2^(40 + e)
+    double from_fix;   // 2^-(40 + e)
+    float limit;       // |v| must be below 2^(15 - e)
+};
+
+__device__ __forceinline__ unsigned long long to_fixed(float v, double scale) {
+    const double x = rint((double)v * scale);
+    const double hi = floor(x * 0x1p-32);
+    const double lo = fma(hi, -0x1p32, x);  // exact, in [0, 2^32)
+    return ((unsigned long long)(uint32_t)(int32_t)hi << 32) | (uint32_t)lo;
+}
+
+__device__ __forceinline__ float from_fixed(unsigned long long u, double inv_scale) {
+    const double hi = (double)(int32_t)(uint32_t)(u >> 32);
+    const double lo = (double)(uint32_t)u;
+    return (float)(fma(hi, 0x1p32, lo) * inv_scale);
+}
+
+__device__ __forceinline__ int hash_slot(uint32_t *__restrict__ hkey, uint32_t id) {
+    const uint32_t h = (id * 2654435761u) >> 24;
+#pragma unroll 1
+    for (int pr = 0; pr < kProbes; ++pr) {
+        const uint32_t s = (h + pr) & (kHashSlots - 1);
+        uint32_t k = hkey[s];
+        if (k == id) return (int)s;
+        if (k == SAD_INVALID_ID) {
+            k = atomicCAS(&hkey[s], SAD_INVALID_ID, id);
+            if (k == SAD_INVALID_ID || k == id) return (int)s;
+        }
+    }
+    return -1;
+}
+
+// Contributions of one pixel (its blend b, colours col, norms nrm) to the site
+// gradients for dL/dc = (g0, g1, g2), added into the tile table (hkey, hacc) or, if
+// the table is full or a term is out of fixed-point range, straight to global memory.
+// With kRD also the removal delta against the target colour (I0, I1, I2).
+template <int K, bool kRD>
+__device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const PixelBlend<K> &b,
+                                          const float (*col)[3], const float *nrm, float X,
+                                          float Y, float g0, float g1, float g2, float I0,
+                                          float I1, float I2, uint32_t *__restrict__ hkey,
+                                          unsigned long long (*hacc)[kHashSlots],
+                                          const FixScale &fx, float inv_P, int64_t cap,
+                                          float *__restrict__ grad, float *__restrict__ rdel) {
+    if (b.nv) {
+        const float invS = __builtin_amdgcn_rcpf(b.S);
+        // Reference entry r: the largest score (e_r = 1).  Differences are formed
+        // relative to it, so that nothing cancels when one weight is close to 1:
+        //   c_k - c = (c_k - c_r) - dc_r,  dc_r = sum_j w_j (c_j - c_r).
+        int r = 0;
+        float mx = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (b.ok[k] && b.l[k] > mx) {
+                mx = b.l[k];
+                r = k;
+            }
+        float cr0 = 0.f, cr1 = 0.f, cr2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (k == r) {
+                cr0 = col[k][0];
+                cr1 = col[k][1];
+                cr2 = col[k][2];
+            }
+        float dc0 = 0.f, dc1 = 0.f, dc2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const float w = b.e[k] * invS;  // 0 for invalid entries
+            dc0 = fmaf(w, col[k][0] - cr0, dc0);
+            dc1 = fmaf(w, col[k][1] - cr1, dc1);
+            dc2 = fmaf(w, col[k][2] - cr2, dc2);
+        }
+        // removal delta (Sec. 4.5): Delta = (c' - c) . ((c' - c) + 2 (c - I))
+        float e0 = 0.f, e1 = 0.f, e2 = 0.f;      // c - I
+        float dr0 = 0.f, dr1 = 0.f, dr2 = 0.f;   // c'_r - c for the reference entry
+        if (kRD) {
+            e0 = b.c[0] - I0;
+            e1 = b.c[1] - I1;
+            e2 = b.c[2] - I2;
+            if (b.nv > 1) {
+                float m2 = -INFINITY;
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+                    if (b.ok[k] && k != r) m2 = fmaxf(m2, b.l[k]);
+                float S2 = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    if (!b.ok[k] || k == r) continue;
+                    const float ee = __expf(b.l[k] - m2);
+                    S2 += ee;
+                    n0 = fmaf(ee, col[k][0] - cr0, n0);
+                    n1 = fmaf(ee, col[k][1] - cr1, n1);
+                    n2 = fmaf(ee, col[k][2] - cr2, n2);
+                }
+                const float inv2 = __builtin_amdgcn_rcpf(S2);
+                dr0 = n0 * inv2 - dc0;
+                dr1 = n1 * inv2 - dc1;
+                dr2 = n2 * inv2 - dc2;
+            } else {  // no other entry: the pixel would render 0
+                dr0 = -b.c[0];
+                dr1 = -b.c[1];
+                dr2 = -b.c[2];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (!b.ok[k]) continue;
+            const uint32_t id = b.id[k];
+            const float4 q0 = rec[4 * (size_t)id], q1 = rec[4 * (size_t)id + 1];
+            const float4 q2 = rec[4 * (size_t)id + 2], q3 = rec[4 * (size_t)id + 3];
+            const float w = b.e[k] * invS;
+            const float d0 = (col[k][0] - cr0) - dc0;  // c_k - c
+            const float d1 = (col[k][1] - cr1) - dc1;
+            const float d2 = (col[k][2] - cr2) - dc2;
+            float acc[kAcc];
+            acc[4] = w * g0;
+            acc[5] = w * g1;
+            acc[6] = w * g2;
+            const float gam = w * (g0 * d0 + g1 * d1 + g2 * d2);
+            acc[2] = gam * b.l[k];
+            acc[3] = gam * q1.y;
+            const float n = nrm[k];
+            acc[0] = acc[1] = acc[7] = acc[8] = acc[9] = 0.f;
+            if (n > 0.f) {
+                const float rho = -0.5f * gam * q1.y * __builtin_amdgcn_rcpf(n);
+                const float ux = q2.w, uy = q3.x, ep = q3.y, em = q3.z;
+                const float dx = X - q0.x, dy = Y - q0.y;
+                const float al = ux * dx + uy * dy, be = ux * dy - uy * dx;
+                const float A = ep * al, B = em * be;
+                acc[0] = -2.0f * rho * (A * ux - B * uy);
+                acc[1] = -2.0f * rho * (A * uy + B * ux);
+                acc[9] = rho * (A * al - B * be);
+                acc[7] = 2.0f * rho * (A * dx + B * dy);
+                acc[8] = 2.0f * rho * (A * dy - B * dx);
+            }
+            acc[10] = 0.f;
+            if (kRD) {
+                float p0, p1, p2;  // c'_k - c
+                if (k == r) {
+                    p0 = dr0;
+                    p1 = dr1;
+                    p2 = dr2;
+                } else {  // c' - c = -w / (1 - w) (c_k - c), with w <= 1/2 here
+                    const float f = -w * __builtin_amdgcn_rcpf(1.0f - w);
+                    p0 = f * d0;
+                    p1 = f * d1;
+                    p2 = f * d2;
+                }
+                acc[10] = (p0 * (p0 + 2.0f * e0) + p1 * (p1 + 2.0f * e1) +
+                           p2 * (p2 + 2.0f * e2)) * inv_P;
+            }
+            const int slot = hash_slot(hkey, id);
+            constexpr int nq = kRD ? kAcc : 10;
+#pragma unroll
+            for (int q = 0; q < nq; ++q) {
+                float *dst = q < 10 ? grad + q * cap + id : rdel + id;
+                if (slot >= 0 && fabsf(acc[q]) < fx.limit)
+                    atomicAdd(&hacc[q][slot], to_fixed(acc[q], fx.to_fix));
+                else if (acc[q] != 0.0f)
+                    atomic_add_f32(dst, acc[q]);
+            }
+        }
+    }
+}
+
+// Clear the tile table (one slot per thread of a 256-thread block).
+__device__ __forceinline__ void bwd_tile_init(uint32_t *__restrict__ hkey,
+                                              unsigned long long (*hacc)[kHashSlots]) {
+    const int t = threadIdx.x;
+    hkey[t] = SAD_INVALID_ID;
+#pragma unroll
+    for (int q = 0; q < kAcc; ++q) hacc[q][t] = 0ull;
+}
+
+// Flush the tile table: one float global atomic per occupied (site, parameter).
+template <bool kRD>
+__device__ __forceinline__ void bwd_flush(const uint32_t *__restrict__ hkey,
+                                          unsigned long long (*hacc)[kHashSlots],
+                                          const FixScale &fx, int64_t cap,
+                                          float *__restrict__ grad, float *__restrict__ rdel) {
+    const int t = threadIdx.x;
+    const uint32_t id = hkey[t];
+    if (id == SAD_INVALID_ID) return;
+    constexpr int nq = kRD ? kAcc : 10;
+#pragma unroll
+    for (int q = 0; q < nq; ++q) {
+        const unsigned long long u = hacc[q][t];
+        if (u) atomic_add_f32(q < 10 ? grad + q * cap + id : rdel + id, from_fixed(u, fx.from_fix));
+    }
+}
+
+// Fixed-point scale for an image of P pixels: 2^(40 + e) with 2^e ~ P / 2.
+inline FixScale fix_scale(int64_t P) {
+    int e = 0;
+    while ((int64_t)1 << (e + 1) < P) ++e;
+    FixScale fx;
+    fx.to_fix = std::ldexp(1.0, 40 + e);
+    fx.from_fix = std::ldexp(1.0, -(40 + e));
+    fx.limit = (float)std::ldexp(1.0, 15 - e);
+    return fx;
+}
+
+}  // namespace sad

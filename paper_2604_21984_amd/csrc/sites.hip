@@ -4,49 +4,9 @@
 #include "sad_device.h"
 #include "sad_host.h"
 #include "sad_internal.h"
+#include "sad_sites.h"
 
 namespace sad {
-
-// Derived record of slot i (Sec. 4.1: G = e^a u u^T + e^-a v v^T, v = (-u_y, u_x);
-// tau = exp(log_tau); kappa = tau * s).  Transcendentals in double, rounded once.
-__device__ __forceinline__ void write_record(const float *__restrict__ sites, int64_t cap,
-                                             int64_t i, float s, float4 *__restrict__ rec) {
-    float v[SAD_NPARAM];
-    bool finite = true;
-#pragma unroll
-    for (int p = 0; p < SAD_NPARAM; ++p) {
-        v[p] = sites[p * cap + i];
-        finite = finite && isfinite(v[p]);
-    }
-    const float x = v[0], y = v[1], lt = v[2], r = v[3], ux = v[7], uy = v[8], a = v[9];
-    float4 q0 = make_float4(x, y, 0.f, 0.f), q1 = make_float4(0.f, 0.f, r, 0.f);
-    float4 q2 = make_float4(v[4], v[5], v[6], ux), q3 = make_float4(uy, 0.f, 0.f, 0.f);
-    if (finite && x >= 0.0f) {
-        const float tau = (float)exp((double)lt);
-        const float ep = (float)exp((double)a);
-        const float em = (float)exp(-(double)a);
-        const float kappa = __fmul_rn(tau, s);
-        const float uxx = __fmul_rn(ux, ux), uyy = __fmul_rn(uy, uy), uxy = __fmul_rn(ux, uy);
-        const float g11 = __fmaf_rn(ep, uxx, __fmul_rn(em, uyy));
-        const float g22 = __fmaf_rn(ep, uyy, __fmul_rn(em, uxx));
-        const float g12 = __fmul_rn(__fsub_rn(ep, em), uxy);
-        const float g12x2 = __fmul_rn(2.0f, g12);
-        const bool ok = kappa > 0.0f && isfinite(kappa) && isfinite(g11) && isfinite(g22) &&
-                        isfinite(g12x2);
-        q0.z = g11;
-        q0.w = g12x2;
-        q1.x = g22;
-        q1.y = kappa;
-        q1.w = ok ? 1.0f : 0.0f;
-        q3.y = ep;
-        q3.z = em;
-        q3.w = tau;
-    }
-    rec[4 * i + 0] = q0;
-    rec[4 * i + 1] = q1;
-    rec[4 * i + 2] = q2;
-    rec[4 * i + 3] = q3;
-}
 
 __global__ __launch_bounds__(256) void k_prepare(const float *__restrict__ sites, int64_t cap,
                                                  int n, float s, float4 *__restrict__ rec) {
@@ -115,62 +75,15 @@ __global__ __launch_bounds__(256) void k_seed_take(const float4 *__restrict__ re
     }
 }
 
-// ---- Adam (Sec. 5; clamps of Sec. 6.1) ----------------------------------------------
-struct AdamArgs {
-    float lr[SAD_NPARAM];
-    float b1, b2, eps, c1, c2;  // c1 = 1 - b1^t, c2 = 1 - b2^t (host step)
-    const int64_t *step_dev;    // if set: t = *step_dev + 1, corrections formed on device
-    int zero_grad;              // clear the gradient after reading it
-};
-
 __global__ __launch_bounds__(256) void k_adam(float *__restrict__ sites,
                                               float *__restrict__ grad,
                                               float *__restrict__ m, float *__restrict__ v,
                                               int64_t cap, int n, int H, int W, AdamArgs A,
-                                              float s, float4 *__restrict__ rec) {
+                                              const int64_t *step_dev, float s,
+                                              float4 *__restrict__ rec) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    if (!(sites[i] >= 0.0f)) {  // inactive slot: parameters untouched
-        if (A.zero_grad)
-            for (int p = 0; p < SAD_NPARAM; ++p) grad[p * cap + i] = 0.0f;
-        if (rec) write_record(sites, cap, i, s, rec);
-        return;
-    }
-    float c1 = A.c1, c2 = A.c2;
-    if (A.step_dev) {
-        const double t = (double)(*A.step_dev + 1);
-        c1 = (float)(1.0 - pow((double)A.b1, t));
-        c2 = (float)(1.0 - pow((double)A.b2, t));
-    }
-    const float lo[SAD_NPARAM] = {0.f, 0.f, 2.f, 1.f, 0.f, 0.f, 0.f, -INFINITY, -INFINITY, -2.f};
-    const float hi[SAD_NPARAM] = {(float)(W - 1), (float)(H - 1), 20.f, 512.f, 1.f, 1.f, 1.f,
-                                  INFINITY, INFINITY, 2.f};
-    float th[SAD_NPARAM];
-#pragma unroll
-    for (int p = 0; p < SAD_NPARAM; ++p) {
-        const int64_t o = p * cap + i;
-        const float g = grad[o];
-        if (A.zero_grad) grad[o] = 0.0f;
-        const float mm = A.b1 * m[o] + (1.0f - A.b1) * g;
-        const float vv = A.b2 * v[o] + (1.0f - A.b2) * g * g;
-        m[o] = mm;
-        v[o] = vv;
-        const float mh = mm / c1, vh = vv / c2;
-        float x = sites[o] - A.lr[p] * mh / (sqrtf(vh) + A.eps);
-        x = fminf(fmaxf(x, lo[p]), hi[p]);
-        th[p] = x;
-    }
-    const float nu = sqrtf(th[7] * th[7] + th[8] * th[8]);
-    if (nu > 0.f) {
-        th[7] /= nu;
-        th[8] /= nu;
-    } else {
-        th[7] = 1.f;
-        th[8] = 0.f;
-    }
-#pragma unroll
-    for (int p = 0; p < SAD_NPARAM; ++p) sites[p * cap + i] = th[p];
-    if (rec) write_record(sites, cap, i, s, rec);
+    adam_site(sites, grad, m, v, cap, i, H, W, A, step_dev, s, rec);
 }
 
 }  // namespace sad
@@ -230,11 +143,10 @@ void sad::launch_adam(const sad_image *img, float s, float *sites, float *grad, 
     A.eps = params->eps;
     A.c1 = (float)(1.0 - std::pow((double)params->beta1, (double)step));
     A.c2 = (float)(1.0 - std::pow((double)params->beta2, (double)step));
-    A.step_dev = step_dev;
     A.zero_grad = zero_grad ? 1 : 0;
     const int n = img->n_slots;
     hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, st, sites, grad, m, v, img->cap,
-                       n, img->H, img->W, A, s, reinterpret_cast<float4 *>(rec));
+                       n, img->H, img->W, A, step_dev, s, reinterpret_cast<float4 *>(rec));
 }
 
 extern "C" sad_status sad_adam_step(const sad_image *img, float *sites, float *grad, float *m,

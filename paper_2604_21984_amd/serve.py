@@ -1,0 +1,329 @@
+"""Serving loop for encoded images (random-access decode, Sec. 6.6: rendering from
+cached top-K lists is the fast path).
+
+* Resident sets: encoded site sets (derived records + list field) kept on the device.
+* Requests: point queries (M points of one set) and full renders (one set).
+* Admission by memory: a request is admitted when the device bytes it needs (its
+  inputs and outputs) fit in what the budget has left; bytes return when it completes.
+  A request that could never fit is rejected.
+* Continuous batching: every scheduler turn launches whatever has been admitted since
+  the last turn -- point queries of many requests across many sets as one
+  ``sad_query_batch`` launch, renders as their own launches -- on a pool of streams,
+  without waiting for earlier launches; completions are found by polling events.
+  Requests that arrive while others run are admitted as memory frees up and their work
+  overlaps on the device with the work already there.
+* A failing launch fails only the requests in it.
+* Latency is arrival -> completion; p50 / p99 and throughput are reported.
+
+The scheduler talks to a backend (``GpuBackend`` here; tests also drive it with a fake
+backend with a simulated clock, memory and errors).
+"""
+import collections
+import math
+import threading
+import time
+from dataclasses import dataclass
+
+QUERY, RENDER = "query", "render"
+
+
+@dataclass
+class Request:
+    rid: int
+    set_id: int
+    kind: str
+    xy: object = None            # [M, 2] float32 device tensor (queries)
+    M: int = 0
+    t_arrival: float = 0.0
+    t_admit: float = None
+    t_launch: float = None
+    t_done: float = None
+    result: object = None
+    error: str = None
+    nbytes: int = 0
+
+    @property
+    def latency(self):
+        return None if self.t_done is None else self.t_done - self.t_arrival
+
+
+class ResidentSet:
+    """One encoded image kept on the device."""
+
+    def __init__(self, set_id, H, W, K, n_slots, rec, topk, score_scale=0.0):
+        self.set_id, self.H, self.W, self.K, self.n_slots = set_id, H, W, K, n_slots
+        self.rec, self.topk, self.score_scale = rec, topk, score_scale
+
+    @classmethod
+    def from_encoder(cls, set_id, enc):
+        return cls(set_id, enc.H, enc.W, enc.cfg.K, enc.img.n_slots, enc.rec.clone(),
+                   enc.topk.clone(), enc.cfg.score_scale)
+
+    @classmethod
+    def from_batch(cls, set_id, benc, b):
+        H, W = benc.shapes[b]
+        return cls(set_id, H, W, benc.K, benc.n_sites[b], benc.view_rec(b).clone(),
+                   benc.view_list(benc.cur, b).clone(), benc.cfg.score_scale)
+
+    def nbytes(self):
+        return self.rec.numel() * 4 + self.topk.numel() * 4
+
+
+def request_bytes(req, rset):
+    """Device bytes a request holds while admitted: inputs and outputs."""
+    if req.kind == QUERY:
+        return req.M * (8 + 12)
+    return 12 * rset.H * rset.W
+
+
+class GpuBackend:
+    """Launches on a pool of default-priority HIP streams; completion via events."""
+
+    def __init__(self, device=None, n_streams=4):
+        import torch
+
+        from . import _lib as S
+        self.torch, self.S = torch, S
+        self.device = torch.device(device or "cuda")
+        self.streams = [torch.cuda.Stream(self.device) for _ in range(n_streams)]
+        self._next = 0
+
+    def now(self):
+        return time.perf_counter()
+
+    def free_bytes(self):
+        free, _ = self.torch.cuda.mem_get_info(self.device)
+        return free
+
+    def _stream(self):
+        s = self.streams[self._next % len(self.streams)]
+        self._next += 1
+        return s
+
+    def launch_queries(self, reqs, sets):
+        torch, S = self.torch, self.S
+        K = sets[reqs[0].set_id].K
+        n = len(reqs)
+        arr = (S.SadQueryJob * n)()
+        outs = []
+        q0 = 0
+        for j, r in enumerate(reqs):
+            rs = sets[r.set_id]
+            out = torch.empty((r.M, 3), dtype=torch.float32, device=self.device)
+            outs.append(out)
+            arr[j] = S.SadQueryJob(rs.rec.data_ptr(), rs.topk.data_ptr(), r.xy.data_ptr(),
+                                   out.data_ptr(), r.M, q0, rs.H, rs.W, rs.n_slots, 0)
+            q0 += r.M
+        st = self._stream()
+        with torch.cuda.stream(st):
+            host = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).pin_memory()
+            jobs = host.to(self.device, non_blocking=True)
+            S.query_batch(jobs, n, q0, K)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        return {"event": ev, "reqs": reqs, "outs": outs, "keep": (host, jobs)}
+
+    def launch_render(self, req, rset):
+        torch, S = self.torch, self.S
+        st = self._stream()
+        with torch.cuda.stream(st):
+            img = S.image(rset.H, rset.W, rset.K, rset.n_slots, rset.n_slots, rset.score_scale)
+            out = torch.empty((3, rset.H, rset.W), dtype=torch.float32, device=self.device)
+            S.render_fwd(img, rset.rec, rset.topk, out)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        return {"event": ev, "reqs": [req], "outs": [out], "keep": ()}
+
+    def done(self, h):
+        return h["event"].query()
+
+    def results(self, h):
+        return list(zip(h["reqs"], h["outs"]))
+
+
+class Server:
+    def __init__(self, backend, sets, mem_budget=None, max_batch_points=1 << 22, max_inflight=8,
+                 reserve_frac=0.5):
+        self.backend = backend
+        self.sets = {s.set_id: s for s in sets}
+        if mem_budget is None:
+            mem_budget = int(backend.free_bytes() * reserve_frac)
+        self.budget = int(mem_budget)
+        self.reserved = 0
+        self.max_batch_points = int(max_batch_points)
+        self.max_inflight = int(max_inflight)
+        self._lock = threading.Lock()
+        self._arrivals = collections.deque()
+        self.pending = collections.deque()
+        self.admitted = collections.deque()
+        self.inflight = []
+        self.completed = []
+        self.launches = []       # (time, number of requests, number of sets) per launch
+        self.peak_reserved = 0
+
+    # ---- intake -------------------------------------------------------------------
+    def submit(self, req):
+        if req.t_arrival == 0.0:
+            req.t_arrival = self.backend.now()
+        with self._lock:
+            self._arrivals.append(req)
+
+    # ---- one scheduler turn -----------------------------------------------------------
+    def step(self):
+        with self._lock:
+            while self._arrivals:
+                self.pending.append(self._arrivals.popleft())
+        self._poll()
+        self._admit()
+        self._launch()
+        return bool(self.pending or self.admitted or self.inflight)
+
+    def _admit(self):
+        while self.pending:
+            r = self.pending[0]
+            rs = self.sets.get(r.set_id)
+            if rs is None:
+                self.pending.popleft()
+                self._fail(r, f"unknown set {r.set_id}")
+                continue
+            need = request_bytes(r, rs)
+            if need > self.budget:
+                self.pending.popleft()
+                self._fail(r, f"needs {need} bytes, budget {self.budget}")
+                continue
+            if self.reserved + need > self.budget:
+                break  # FIFO: wait until memory frees up
+            self.pending.popleft()
+            r.nbytes = need
+            r.t_admit = self.backend.now()
+            self.reserved += need
+            self.peak_reserved = max(self.peak_reserved, self.reserved)
+            self.admitted.append(r)
+
+    def _launch(self):
+        while self.admitted and len(self.inflight) < self.max_inflight:
+            head = self.admitted[0]
+            if head.kind == RENDER:
+                self.admitted.popleft()
+                self._start([head], lambda rs=self.sets[head.set_id], r=head:
+                             self.backend.launch_render(r, rs))
+                continue
+            # gather admitted point queries with the head's K, up to the point budget
+            K = self.sets[head.set_id].K
+            batch, keep, total = [], collections.deque(), 0
+            while self.admitted:
+                r = self.admitted.popleft()
+                if (r.kind == QUERY and self.sets[r.set_id].K == K and
+                        (not batch or total + r.M <= self.max_batch_points)):
+                    batch.append(r)
+                    total += r.M
+                else:
+                    keep.append(r)
+            self.admitted = keep
+            self._start(batch, lambda b=batch: self.backend.launch_queries(b, self.sets))
+
+    def _start(self, reqs, fn):
+        t = self.backend.now()
+        for r in reqs:
+            r.t_launch = t
+        try:
+            h = fn()
+        except Exception as e:
+            if len(reqs) > 1:  # find the failing request(s): launch each alone
+                for r in reqs:
+                    self._start([r], lambda r=r: self.backend.launch_queries([r], self.sets))
+                return
+            for r in reqs:
+                self._release(r)
+                self._fail(r, f"launch failed: {e}")
+            return
+        self.inflight.append(h)
+        self.launches.append((t, len(reqs), len({r.set_id for r in reqs})))
+
+    def _poll(self):
+        still = []
+        for h in self.inflight:
+            if self.backend.done(h):
+                t = self.backend.now()
+                for r, out in self.backend.results(h):
+                    r.result = out
+                    r.t_done = t
+                    self._release(r)
+                    self.completed.append(r)
+            else:
+                still.append(h)
+        self.inflight = still
+
+    def _release(self, r):
+        self.reserved -= r.nbytes
+        r.nbytes = 0
+
+    def _fail(self, r, msg):
+        r.error = msg
+        r.t_done = self.backend.now()
+        self.completed.append(r)
+
+    # ---- driving ----------------------------------------------------------------------
+    def drain(self, timeout=60.0, idle_sleep=0.0):
+        t_end = time.perf_counter() + timeout
+        while self.step():
+            if time.perf_counter() > t_end:
+                raise TimeoutError("server did not drain")
+            if idle_sleep:
+                time.sleep(idle_sleep)
+
+    def stats(self):
+        ok = [r for r in self.completed if r.error is None]
+        lat = sorted(r.latency for r in ok)
+        if not ok:
+            return {"completed": 0, "failed": len(self.completed)}
+        t0 = min(r.t_arrival for r in ok)
+        t1 = max(r.t_done for r in ok)
+        pts = sum(r.M for r in ok if r.kind == QUERY)
+        px = sum(self.sets[r.set_id].H * self.sets[r.set_id].W for r in ok if r.kind == RENDER)
+
+        def pct(q):
+            return lat[min(len(lat) - 1, max(0, math.ceil(q * len(lat)) - 1))]
+
+        span = max(t1 - t0, 1e-9)
+        multi = [n for _, n, _ in self.launches]
+        return {"completed": len(ok), "failed": len(self.completed) - len(ok),
+                "p50_ms": 1e3 * pct(0.50), "p99_ms": 1e3 * pct(0.99),
+                "mean_ms": 1e3 * sum(lat) / len(lat), "throughput_rps": len(ok) / span,
+                "points_per_s": pts / span, "render_px_per_s": px / span,
+                "launches": len(self.launches),
+                "mean_requests_per_launch": sum(multi) / max(len(multi), 1),
+                "peak_reserved_bytes": self.peak_reserved, "budget_bytes": self.budget}
+
+
+def poisson_arrivals(rate, duration, rng):
+    """Arrival times of a Poisson process of the given rate on [0, duration)."""
+    t, out = 0.0, []
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t >= duration:
+            return out
+        out.append(t)
+
+
+def run_open_loop(server, requests, times, poll_sleep=0.0):
+    """Submit requests at their arrival times (seconds from now) from a feeder thread
+    while this thread runs the scheduler; returns when every request has completed."""
+    t_start = time.perf_counter()
+
+    def feed():
+        for r, t in zip(requests, times):
+            dt = t_start + t - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            r.t_arrival = time.perf_counter()
+            server.submit(r)
+
+    th = threading.Thread(target=feed, daemon=True)
+    th.start()
+    n = len(requests)
+    while th.is_alive() or len(server.completed) < n:
+        server.step()
+        if poll_sleep:
+            time.sleep(poll_sleep)
+    th.join()

@@ -1,0 +1,112 @@
+"""GPU: the serving loop.  A request answered inside a mixed, continuously batched
+launch equals the same request answered alone, bit for bit; point queries match the
+oracle; renders equal sad_render_fwd."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from _helpers import planar_to_rows
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def sets():
+    from paper_2604_21984_amd import encode as E
+    from paper_2604_21984_amd import serve as V
+    out, encs = [], []
+    for i, (H, W, N) in enumerate([(48, 64, 150), (40, 30, 90), (70, 33, 120)]):
+        tg = torch.from_numpy(synth.image_encode(20 + i, H, W, n_polygons=10, patch=12)).to(DEV)
+        enc = E.Encoder(tg, N, E.EncodeConfig(K=8, n_inject=4, seed=7 + i))
+        for _ in range(6):
+            enc.step()
+        torch.cuda.synchronize()
+        out.append(V.ResidentSet.from_encoder(i, enc))
+        encs.append(enc)
+    return out, encs
+
+
+def _alone(S, rs, xy):
+    img = S.image(rs.H, rs.W, rs.K, rs.n_slots, rs.n_slots, rs.score_scale)
+    out = torch.empty((xy.shape[0], 3), dtype=torch.float32, device=DEV)
+    S.query_points(img, rs.rec, rs.topk, xy, out)
+    torch.cuda.synchronize()
+    return out
+
+
+def test_mixed_batches_equal_alone_and_oracle(sets):
+    from paper_2604_21984_amd import _lib as S
+    from paper_2604_21984_amd import serve as V
+    rsets, encs = sets
+    rng = np.random.default_rng(4)
+    srv = V.Server(V.GpuBackend(), rsets, mem_budget=64 << 20, max_inflight=4)
+    reqs = []
+    for rid in range(24):
+        sid = int(rng.integers(0, len(rsets)))
+        rs = rsets[sid]
+        if rid % 7 == 3:
+            reqs.append(V.Request(rid, sid, V.RENDER))
+            continue
+        M = int(rng.integers(1, 700))
+        pts = np.stack([rng.uniform(-2, rs.W + 1, M), rng.uniform(-2, rs.H + 1, M)], 1)
+        xy = torch.from_numpy(pts.astype(np.float32)).to(DEV)
+        reqs.append(V.Request(rid, sid, V.QUERY, xy=xy, M=M))
+    for r in reqs[:10]:
+        srv.submit(r)
+    srv.step()
+    for r in reqs[10:]:          # arrive while the first launches run
+        srv.submit(r)
+    srv.drain(timeout=60)
+    torch.cuda.synchronize()
+    assert len(srv.completed) == len(reqs)
+    assert all(r.error is None for r in srv.completed)
+    assert any(n > 1 and k > 1 for _, n, k in srv.launches)  # some launch mixed sets
+    for r in reqs:
+        rs = rsets[r.set_id]
+        if r.kind == V.RENDER:
+            ref = torch.empty((3, rs.H, rs.W), dtype=torch.float32, device=DEV)
+            img = S.image(rs.H, rs.W, rs.K, rs.n_slots, rs.n_slots, rs.score_scale)
+            S.render_fwd(img, rs.rec, rs.topk, ref)
+            torch.cuda.synchronize()
+            assert torch.equal(r.result, ref), r.rid
+        else:
+            assert torch.equal(r.result, _alone(S, rs, r.xy)), r.rid
+    # oracle on one query request per set
+    for sid, rs in enumerate(rsets):
+        r = next(q for q in reqs if q.kind == V.QUERY and q.set_id == sid)
+        enc = encs[sid]
+        sites = enc.sites.cpu().numpy()
+        lists = planar_to_rows(enc.topk.cpu().numpy(), rs.H, rs.W, rs.K)
+        s = oracle.default_scale(rs.H, rs.W)
+        ref = oracle.query(rs.H, rs.W, rs.K, s, sites, rs.n_slots, lists, r.xy.cpu().numpy())
+        assert np.abs(r.result.cpu().numpy() - ref).max() <= 1e-5
+
+
+def test_query_batch_direct_with_empty_jobs(sets):
+    from paper_2604_21984_amd import _lib as S
+    rsets, _ = sets
+    rng = np.random.default_rng(8)
+    Ms = [5, 0, 300, 1, 0, 257]
+    arr = (S.SadQueryJob * len(Ms))()
+    xs, outs, q0 = [], [], 0
+    for j, M in enumerate(Ms):
+        rs = rsets[j % len(rsets)]
+        pts = np.stack([rng.uniform(0, rs.W, M), rng.uniform(0, rs.H, M)], 1).astype(np.float32)
+        xy = torch.from_numpy(pts.reshape(M, 2)).to(DEV)
+        out = torch.full((max(M, 1), 3), -7.0, dtype=torch.float32, device=DEV)
+        xs.append(xy)
+        outs.append(out)
+        arr[j] = S.SadQueryJob(rs.rec.data_ptr(), rs.topk.data_ptr(), xy.data_ptr(), out.data_ptr(),
+                               M, q0, rs.H, rs.W, rs.n_slots, 0)
+        q0 += M
+    jobs = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).to(DEV)
+    S.query_batch(jobs, len(Ms), q0, 8)
+    torch.cuda.synchronize()
+    for j, M in enumerate(Ms):
+        if M == 0:
+            assert (outs[j] == -7.0).all()       # untouched
+        else:
+            assert torch.equal(outs[j], _alone(S, rsets[j % len(rsets)], xs[j])), j

@@ -121,3 +121,31 @@ def test_encode_improves_psnr(mods):
         enc.step()
     p1 = enc.psnr()
     assert p1 > p0 + 3.0, (p0, p1)
+
+
+def test_fused_image_pass_equals_separate_kernels(mods):
+    S, A, E = mods
+    enc = _enc(E, H=100, W=150, N=900, seed=7)
+    for _ in range(12):
+        enc.step()
+    torch.cuda.synchronize()
+    img = enc.img
+    a = enc.topk
+    t = enc.counters()[0]
+    # fused pass (pass index from the device state; the state is not advanced)
+    lf = torch.empty_like(a)
+    gf = torch.zeros_like(enc.grad)
+    gif = torch.empty_like(enc.grad_img)
+    S.train_image_pass(img, enc.train_cfg, enc.target, enc.rec, a, lf, gf, None, gif, enc.state)
+    # the same work through the separate entry points
+    ls = torch.empty_like(a)
+    S.propagate_topk(img, enc.rec, a, ls, S.jump_step(t, enc.H, enc.W), 4, enc.train_cfg.seed, t)
+    gis = torch.empty_like(enc.grad_img)
+    S.render_fwd_loss(img, enc.rec, ls, enc.target, gis)
+    gs = torch.zeros_like(enc.grad)
+    S.render_bwd(img, enc.rec, ls, gis, gs)
+    torch.cuda.synchronize()
+    assert torch.equal(lf, ls)
+    assert torch.equal(gif, gis)
+    scale = gs.abs().amax(dim=1, keepdim=True) + 1e-30
+    assert ((gf - gs).abs() / scale).max().item() < 1e-5
