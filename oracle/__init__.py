@@ -70,6 +70,10 @@ def lib():
         L.ora_init_sites.argtypes = [i32, i32, _f32p, i64, f64, u64, f32, f32, _f32p, i64,
                                      _opt(_f64p)]
         L.ora_init_sites.restype = i64
+        L.ora_site_stats.argtypes = [i32, i32, i32, f32, _f32p, i64, i64, _u32p, _f32p, _f64p]
+        L.ora_densify_prune.argtypes = [i32, i32, i32, _f32p, _f32p, i64, _opt(_f32p),
+                                        _opt(_f32p), _f32p, f64, f64, f64, f64, f64, i32,
+                                        _opt(_u32p), _i64p]
         _lib = L
     return _lib
 
@@ -211,3 +215,38 @@ def init_sites(target, N, lam, seed, log_tau0, r0, cap, return_keys=False):
     keys = np.empty(H * W, np.float64) if return_keys else None
     k = lib().ora_init_sites(H, W, target, N, lam, seed, log_tau0, r0, sites, cap, keys)
     return (sites, int(k), keys) if return_keys else (sites, int(k))
+
+
+NSTAT = 8
+DP_PRUNE, DP_SPLIT, DP_SEED = 1, 2, 4
+
+
+def site_stats(H, W, K, s, sites, n, lists, target):
+    """Statistics [8, cap] (m, E, S_x, S_y, S_xx, S_xy, S_yy, removal delta)."""
+    L = lib()
+    sites = _sites(sites)
+    cap = sites.shape[1]
+    out = np.zeros((NSTAT, cap), np.float64)
+    L.ora_site_stats(H, W, K, s, sites, cap, n, _lists(lists, H * W, K),
+                     np.ascontiguousarray(target, dtype=np.float32), out)
+    return out
+
+
+def densify_prune(target, sites, stats, p_prune, p_split, flags, K=8, adam_m=None, adam_v=None,
+                  lists=None, alpha=0.7, eps=1e-8, min_mass=1.0):
+    """One budget step, in place on float32 sites [10, cap] (and adam_m / adam_v, lists
+    [H*W, K] if given).  Returns counts (n_active, n_pruned, n_split, n_after, high
+    water, candidates)."""
+    L = lib()
+    target = np.ascontiguousarray(target, dtype=np.float32)
+    _, H, W = target.shape
+    assert sites.dtype == np.float32 and sites.flags.c_contiguous
+    cap = sites.shape[1]
+    st = np.ascontiguousarray(stats, dtype=np.float32)
+    assert st.shape == (NSTAT, cap)
+    counts = np.zeros(6, np.int64)
+    if lists is not None:
+        assert lists.dtype == np.uint32 and lists.flags.c_contiguous
+    L.ora_densify_prune(H, W, K, target, sites, cap, adam_m, adam_v, st, p_prune, p_split, alpha,
+                        eps, min_mass, flags, lists, counts)
+    return [int(c) for c in counts]

@@ -426,6 +426,42 @@ static void acc2(double *grad, double *gabs, int64_t o, double v)
     if (gabs) gabs[o] += fabs(v);
 }
 
+/* Sec. 4.5 removal delta of every entry of one blended pixel: c' = the colour with
+ * entry v removed and the remaining weights renormalised, Delta_v = ||c' - I||^2 -
+ * ||c - I||^2.  c' is formed as the softmax of the other entries (their maximum
+ * subtracted), which equals (c - w_v c_v) / (1 - w_v) but does not cancel when w_v -> 1.
+ * With no other valid entry c' = 0 (an empty list renders 0). */
+static void removal_delta_pixel(const pix_t *px, const site_t *st, const float *target,
+                                int64_t P, int64_t p, double *out)
+{
+    double base = 0;
+    for (int ch = 0; ch < 3; ++ch) {
+        double d = px->c[ch] - (double)target[ch * P + p];
+        base += d * d;
+    }
+    for (int v = 0; v < px->nv; ++v) {
+        double cp[3] = {0, 0, 0};
+        double m = -INFINITY;
+        for (int u = 0; u < px->nv; ++u) if (u != v && px->l[u] > m) m = px->l[u];
+        if (px->nv > 1) {
+            double S = 0;
+            for (int u = 0; u < px->nv; ++u) {
+                if (u == v) continue;
+                double e = exp(px->l[u] - m);
+                S += e;
+                for (int ch = 0; ch < 3; ++ch) cp[ch] += e * (double)st[px->idx[u]].c[ch];
+            }
+            for (int ch = 0; ch < 3; ++ch) cp[ch] /= S;
+        }
+        double rem = 0;
+        for (int ch = 0; ch < 3; ++ch) {
+            double d = cp[ch] - (double)target[ch * P + p];
+            rem += d * d;
+        }
+        out[v] = rem - base;
+    }
+}
+
 void ora_render_bwd(int H, int W, int K, float s, const float *sites, int64_t cap, int64_t n,
                     const uint32_t *lists, const double *grad_img, const float *target,
                     int mode, double *grad, double *rdelta, double *gabs)
@@ -467,37 +503,9 @@ void ora_render_bwd(int H, int W, int K, float s, const float *sites, int64_t ca
             }
         }
         if (target && rdelta) {
-            /* Sec. 4.5 removal delta: c' = colour with entry k removed and the remaining
-             * weights renormalised; Delta = ||c' - I||^2 - ||c - I||^2.  c' is formed
-             * as the softmax of the other entries (max of the others subtracted), which
-             * equals (c - w_k c_k) / (1 - w_k) but does not cancel when w_k -> 1.  With
-             * no other valid entry c' = 0 (an empty list renders 0). */
-            double base = 0;
-            for (int ch = 0; ch < 3; ++ch) {
-                double d = px.c[ch] - (double)target[ch * P + p];
-                base += d * d;
-            }
-            for (int v = 0; v < px.nv; ++v) {
-                double cp[3] = {0, 0, 0};
-                double m = -INFINITY;
-                for (int u = 0; u < px.nv; ++u) if (u != v && px.l[u] > m) m = px.l[u];
-                if (px.nv > 1) {
-                    double S = 0;
-                    for (int u = 0; u < px.nv; ++u) {
-                        if (u == v) continue;
-                        double e = exp(px.l[u] - m);
-                        S += e;
-                        for (int ch = 0; ch < 3; ++ch) cp[ch] += e * (double)st[px.idx[u]].c[ch];
-                    }
-                    for (int ch = 0; ch < 3; ++ch) cp[ch] /= S;
-                }
-                double rem = 0;
-                for (int ch = 0; ch < 3; ++ch) {
-                    double d = cp[ch] - (double)target[ch * P + p];
-                    rem += d * d;
-                }
-                rdelta[px.idx[v]] += (rem - base) / (double)P;
-            }
+            double dl[64];
+            removal_delta_pixel(&px, st, target, P, p, dl);
+            for (int v = 0; v < px.nv; ++v) rdelta[px.idx[v]] += dl[v] / (double)P;
         }
     }
     free(st);
@@ -612,4 +620,300 @@ int64_t ora_init_sites(int H, int W, const float *target, int64_t N, double lamb
             sites[(int64_t)q * cap + i] = (q == P_X || q == P_Y) ? -1.0f : 0.0f;
     free(gm); free(kp); free(win);
     return k;
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Adaptive budget: statistics, densify, prune (Sec. 4.5; App. B.5)                  */
+/* ------------------------------------------------------------------------------ */
+
+enum { ST_M, ST_E, ST_SX, ST_SY, ST_SXX, ST_SXY, ST_SYY, ST_RD, NSTAT };
+
+/* Statistics pass (App. B.5 "Densification scores"; Sec. 4.5 responsibilities).  For
+ * every pixel x with a non-empty list, blended as in ora_render (weights w from the
+ * float32 scores), with residual e(x) = ||c(x) - I(x)||^2, and every valid entry i:
+ *   m_i  += w_i(x)                       soft mass
+ *   E_i  += w_i(x) e(x)                  energy
+ *   with omega = w_i(x) e(x) and d = x - p_i:
+ *   S_x  += omega d_x      S_y  += omega d_y
+ *   S_xx += omega d_x^2    S_xy += omega d_x d_y    S_yy += omega d_y^2
+ *   R_i  += Delta_i(x) / P               removal delta, as in ora_render_bwd
+ * The moments are weighted by the residual (the split uses a residual-weighted
+ * centroid and covariance) and taken about the site centre p_i; the covariance does
+ * not depend on that origin.  stats: double[8][cap] in the order (m, E, S_x, S_y,
+ * S_xx, S_xy, S_yy, R), accumulated (+=).  Parity: pinned (mass is a partition of
+ * unity, energy sums to the loss, one-site moments against a weighted covariance
+ * from a library routine, removal delta against ora_render_bwd). */
+void ora_site_stats(int H, int W, int K, float s, const float *sites, int64_t cap, int64_t n,
+                    const uint32_t *lists, const float *target, double *stats)
+{
+    int64_t P = (int64_t)H * W;
+    site_t *st = (site_t *)malloc(sizeof(site_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) st[i] = site_load(sites, cap, i, s);
+    pix_t px;
+    double dl[64];
+    for (int64_t p = 0; p < P; ++p) {
+        double X = (double)(p % W), Y = (double)(p / W);
+        blend_pixel(st, n, lists + p * K, K, X, Y, s, SCORE_F32, &px);
+        if (!px.nv) continue;
+        double e = 0;
+        for (int ch = 0; ch < 3; ++ch) {
+            double d = px.c[ch] - (double)target[ch * P + p];
+            e += d * d;
+        }
+        removal_delta_pixel(&px, st, target, P, p, dl);
+        for (int v = 0; v < px.nv; ++v) {
+            int64_t id = px.idx[v];
+            double w = px.w[v], om = w * e;
+            double dx = X - (double)st[id].x, dy = Y - (double)st[id].y;
+            stats[ST_M * cap + id] += w;
+            stats[ST_E * cap + id] += om;
+            stats[ST_SX * cap + id] += om * dx;
+            stats[ST_SY * cap + id] += om * dy;
+            stats[ST_SXX * cap + id] += om * dx * dx;
+            stats[ST_SXY * cap + id] += om * dx * dy;
+            stats[ST_SYY * cap + id] += om * dy * dy;
+            stats[ST_RD * cap + id] += dl[v] / (double)P;
+        }
+    }
+    free(st);
+}
+
+/* Principal axis of the symmetric 2x2 matrix [[a, b], [b, c]]: eigenvalues
+ * l1 >= l2 and the unit eigenvector of l1, signed so that its first non-zero
+ * component is positive.  Returns 0 (no axis) unless the trace exceeds 1e-9 and the
+ * eigenvalue gap 2 disc exceeds 2e-6 of the trace. */
+static int principal_axis(double a, double b, double c, double *ex, double *ey, double *l1,
+                          double *l2)
+{
+    double h = 0.5 * (a - c), tr = a + c;
+    double disc = sqrt(h * h + b * b);
+    if (!(tr > 1e-9) || !(disc > 1e-6 * tr)) return 0;
+    *l1 = 0.5 * tr + disc;
+    *l2 = 0.5 * tr - disc;
+    double vx, vy;
+    if (a >= c) { vx = *l1 - c; vy = b; }
+    else        { vx = b; vy = *l1 - a; }
+    double nv = sqrt(vx * vx + vy * vy);
+    vx /= nv; vy /= nv;
+    if (vx < 0 || (vx == 0 && vy < 0)) { vx = -vx; vy = -vy; }
+    *ex = vx; *ey = vy;
+    return 1;
+}
+
+static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+static int64_t nearest_pixel(int H, int W, double x, double y)
+{
+    double fi = rint(y), fj = rint(x);
+    int64_t i = fi > 0 ? (fi > H - 1 ? H - 1 : (int64_t)fi) : 0;
+    int64_t j = fj > 0 ? (fj > W - 1 ? W - 1 : (int64_t)fj) : 0;
+    return i * W + j;
+}
+
+/* Split of one site (Sec. 4.5, App. B.5 "Split kernel").  par: the parent's ten
+ * parameters; stat: its (m, E, S_x, S_y, S_xx, S_xy, S_yy).  Writes the two children.
+ *   offset delta = 0.5 sqrt(m) pixels, clamped to [1.5, 48]
+ *   with statistics (E > 1e-12 and a principal axis of the residual-weighted
+ *   covariance C = S../E - mu mu^T, mu = (S_x, S_y) / E): children at p + mu +- delta e1,
+ *   u = e1 and a = 0.5 ln(l2 / l1) clamped to [-2, 2] (the det-1 metric whose level
+ *   sets have the covariance's aspect ratio and long axis along e1; a = -2 if l2 <= 0)
+ *   without: e1 = principal axis of the Sobel structure tensor of the target at the
+ *   site's pixel (summed over channels, edges clamped), else u; children at
+ *   p +- delta e1, u unchanged, a = 0.8 a
+ *   both: positions clamped to the image, log_tau - 0.25 in [2, 20], 0.85 r in
+ *   [1, 512], colour = target at the child's nearest pixel.
+ * Child "+" keeps the parent's slot, child "-" takes a free slot. */
+static void split_site(int H, int W, const float *target, const float *par,
+                       const float *stat, float *ca, float *cb)
+{
+    int64_t P = (int64_t)H * W;
+    double m = stat[ST_M], E = stat[ST_E];
+    double delta = clampd(0.5 * sqrt(m), 1.5, 48.0);
+    double px = par[P_X], py = par[P_Y];
+    double cx = px, cy = py, ex = 0, ey = 0, l1, l2;
+    double ux = par[P_UX], uy = par[P_UY], a = par[P_A];
+    int have = 0;
+    if (E > 1e-12) {
+        double mx = (double)stat[ST_SX] / E, my = (double)stat[ST_SY] / E;
+        double cxx = (double)stat[ST_SXX] / E - mx * mx;
+        double cxy = (double)stat[ST_SXY] / E - mx * my;
+        double cyy = (double)stat[ST_SYY] / E - my * my;
+        if (principal_axis(cxx, cxy, cyy, &ex, &ey, &l1, &l2)) {
+            have = 1;
+            cx = px + mx;
+            cy = py + my;
+            ux = ex;
+            uy = ey;
+            a = l2 > 0 ? clampd(0.5 * log(l2 / l1), -2.0, 2.0) : -2.0;
+        }
+    }
+    if (!have) {
+        int64_t q = nearest_pixel(H, W, px, py);
+        int64_t i = q / W, j = q % W;
+        int64_t im = i > 0 ? i - 1 : 0, ip = i + 1 < H ? i + 1 : H - 1;
+        int64_t jm = j > 0 ? j - 1 : 0, jp = j + 1 < W ? j + 1 : W - 1;
+        double txx = 0, txy = 0, tyy = 0;
+        for (int ch = 0; ch < 3; ++ch) {
+            const float *I = target + ch * P;
+#define T_(r, c) ((double)I[(r) * W + (c)])
+            double gx = (T_(im, jp) + 2.0 * T_(i, jp) + T_(ip, jp)) -
+                        (T_(im, jm) + 2.0 * T_(i, jm) + T_(ip, jm));
+            double gy = (T_(ip, jm) + 2.0 * T_(ip, j) + T_(ip, jp)) -
+                        (T_(im, jm) + 2.0 * T_(im, j) + T_(im, jp));
+#undef T_
+            txx += gx * gx;
+            txy += gx * gy;
+            tyy += gy * gy;
+        }
+        if (!principal_axis(txx, txy, tyy, &ex, &ey, &l1, &l2)) {
+            double nu = sqrt(ux * ux + uy * uy);
+            if (nu > 0) { ex = ux / nu; ey = uy / nu; }
+            else        { ex = 1.0; ey = 0.0; }
+        }
+        a = 0.8 * a;
+    }
+    float *kids[2] = {ca, cb};
+    for (int c = 0; c < 2; ++c) {
+        float *o = kids[c];
+        double sg = c == 0 ? 1.0 : -1.0;
+        for (int q = 0; q < NPARAM; ++q) o[q] = par[q];
+        o[P_X] = (float)clampd(cx + sg * delta * ex, 0.0, (double)(W - 1));
+        o[P_Y] = (float)clampd(cy + sg * delta * ey, 0.0, (double)(H - 1));
+        o[P_LOGTAU] = (float)clampd((double)par[P_LOGTAU] - 0.25, 2.0, 20.0);
+        o[P_R] = (float)clampd(0.85 * (double)par[P_R], 1.0, 512.0);
+        int64_t q = nearest_pixel(H, W, (double)o[P_X], (double)o[P_Y]);
+        for (int ch = 0; ch < 3; ++ch) o[P_CR + ch] = target[ch * P + q];
+        o[P_UX] = (float)ux;
+        o[P_UY] = (float)uy;
+        o[P_A] = (float)a;
+    }
+}
+
+typedef struct { float key; int64_t id; } rank_t;
+
+static int rank_cmp_desc(const void *pa, const void *pb)
+{
+    const rank_t *a = (const rank_t *)pa, *b = (const rank_t *)pb;
+    if (a->key > b->key) return -1;
+    if (a->key < b->key) return 1;
+    return a->id < b->id ? -1 : (a->id > b->id ? 1 : 0);
+}
+
+static int rank_cmp_asc(const void *pa, const void *pb)
+{
+    const rank_t *a = (const rank_t *)pa, *b = (const rank_t *)pb;
+    if (a->key < b->key) return -1;
+    if (a->key > b->key) return 1;
+    return a->id < b->id ? -1 : (a->id > b->id ? 1 : 0);
+}
+
+static int site_active(const float *sites, int64_t cap, int64_t i)
+{
+    for (int q = 0; q < NPARAM; ++q)
+        if (!isfinite(sites[(int64_t)q * cap + i])) return 0;
+    return sites[i] >= 0.0f;
+}
+
+/* One budget step (Sec. 4.5 "Adaptive Budget"; App. B.5), on slots 0..cap-1.
+ *   n_active = number of active slots.
+ *   prune (flags & 1): the floor(p_prune n_active) active sites with the smallest
+ *     removal delta R (float32, ties to the lower ID) become inactive (x = y = -1).
+ *   split (flags & 2): candidates are the active, unpruned sites with m > min_mass;
+ *     score s = E / max(m, eps)^alpha (double, rounded to float32; ties to the lower
+ *     ID); the min(floor(p_split n_active), candidates, free slots) best are split
+ *     (split_site).  Parents in ascending ID order take the free slots (inactive after
+ *     the prune) in ascending order for their second child.  Adam moments m, v of
+ *     both children's slots are zeroed (all ten parameters).
+ *   seed (flags & 4, lists non-NULL): the new child with the smallest ID at each pixel
+ *     replaces entry K-1 of that pixel's list, so that propagation starts from it.
+ * stats: float[8][cap] (ora_site_stats order; m, E, moments and R are read).
+ * counts[6] = {n_active, n_pruned, n_split, n_active after, high water (1 + largest
+ * active slot, 0 if none), split candidates}.  Parity: pinned (selections against a
+ * sort, closed-form split geometry, fallback axis of a ramp, clamps, slot order). */
+void ora_densify_prune(int H, int W, int K, const float *target, float *sites, int64_t cap,
+                       float *adam_m, float *adam_v, const float *stats, double p_prune,
+                       double p_split, double alpha, double eps, double min_mass, int flags,
+                       uint32_t *lists, int64_t *counts)
+{
+    int64_t P = (int64_t)H * W;
+    unsigned char *act = (unsigned char *)malloc((size_t)cap + 1);
+    rank_t *rk = (rank_t *)malloc(sizeof(rank_t) * (size_t)(cap + 1));
+    int64_t n_act = 0;
+    for (int64_t i = 0; i < cap; ++i) { act[i] = (unsigned char)site_active(sites, cap, i); n_act += act[i]; }
+    /* prune */
+    int64_t n_p = (flags & 1) ? (int64_t)floor(p_prune * (double)n_act) : 0;
+    int64_t nr = 0;
+    for (int64_t i = 0; i < cap; ++i)
+        if (act[i]) { rk[nr].key = stats[ST_RD * cap + i]; rk[nr].id = i; ++nr; }
+    qsort(rk, (size_t)nr, sizeof(rank_t), rank_cmp_asc);
+    if (n_p > nr) n_p = nr;
+    for (int64_t q = 0; q < n_p; ++q) {
+        int64_t i = rk[q].id;
+        act[i] = 2; /* pruned in this call */
+        sites[P_X * cap + i] = -1.0f;
+        sites[P_Y * cap + i] = -1.0f;
+    }
+    /* split */
+    int64_t n_cand = 0;
+    for (int64_t i = 0; i < cap; ++i) {
+        if (act[i] != 1) continue;
+        double m = stats[ST_M * cap + i];
+        if (!(m > min_mass)) continue;
+        double sc = (double)stats[ST_E * cap + i] / pow(m > eps ? m : eps, alpha);
+        rk[n_cand].key = (float)sc;
+        rk[n_cand].id = i;
+        ++n_cand;
+    }
+    int64_t n_free = cap - (n_act - n_p);
+    int64_t n_s = 0;
+    if (flags & 2) {
+        n_s = (int64_t)floor(p_split * (double)n_act);
+        if (n_s > n_cand) n_s = n_cand;
+        if (n_s > n_free) n_s = n_free;
+    }
+    qsort(rk, (size_t)n_cand, sizeof(rank_t), rank_cmp_desc);
+    unsigned char *par = (unsigned char *)calloc((size_t)cap + 1, 1);
+    for (int64_t q = 0; q < n_s; ++q) par[rk[q].id] = 1;
+    int64_t *child = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n_s + 1));
+    int64_t j = 0;
+    for (int64_t i = 0; i < cap && j < n_s; ++i)
+        if (act[i] != 1) child[j++] = i;
+    float pa[NPARAM], ca[NPARAM], cb[NPARAM], stv[NSTAT];
+    uint32_t *seed = NULL;
+    if ((flags & 4) && lists) {
+        seed = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)P);
+        for (int64_t p = 0; p < P; ++p) seed[p] = ORA_INVALID;
+    }
+    j = 0;
+    for (int64_t i = 0; i < cap; ++i) {
+        if (!par[i]) continue;
+        int64_t c = child[j++];
+        for (int q = 0; q < NPARAM; ++q) pa[q] = sites[(int64_t)q * cap + i];
+        for (int q = 0; q < NSTAT; ++q) stv[q] = stats[(int64_t)q * cap + i];
+        split_site(H, W, target, pa, stv, ca, cb);
+        for (int q = 0; q < NPARAM; ++q) {
+            sites[(int64_t)q * cap + i] = ca[q];
+            sites[(int64_t)q * cap + c] = cb[q];
+            if (adam_m) { adam_m[(int64_t)q * cap + i] = 0.0f; adam_m[(int64_t)q * cap + c] = 0.0f; }
+            if (adam_v) { adam_v[(int64_t)q * cap + i] = 0.0f; adam_v[(int64_t)q * cap + c] = 0.0f; }
+        }
+        if (seed) {
+            int64_t q = nearest_pixel(H, W, (double)cb[P_X], (double)cb[P_Y]);
+            if ((uint32_t)c < seed[q]) seed[q] = (uint32_t)c;
+        }
+    }
+    if (seed) {
+        for (int64_t p = 0; p < P; ++p)
+            if (seed[p] != ORA_INVALID) lists[p * K + (K - 1)] = seed[p];
+        free(seed);
+    }
+    int64_t hw = 0;
+    for (int64_t i = 0; i < cap; ++i) if (site_active(sites, cap, i)) hw = i + 1;
+    counts[0] = n_act;
+    counts[1] = n_p;
+    counts[2] = n_s;
+    counts[3] = n_act - n_p + n_s;
+    counts[4] = hw;
+    counts[5] = n_cand;
+    free(act); free(rk); free(par); free(child);
 }
