@@ -58,6 +58,177 @@ def cpu_baseline(target_np, sites_np, lists_np, budget_s):
     return H * W * steps / el / 1e6, steps, el
 
 
+def autograd_path(enc, steps):
+    """Iterations through the torch.autograd.Function wrappers: propagation pass (lists
+    are not differentiable), SADRender forward, SADMSELoss, backward, Adam on .grad."""
+    import torch
+
+    from paper_2604_21984_amd import _lib as S
+    from paper_2604_21984_amd import autograd as A
+    img, dev = enc.img, enc.device
+    sites = enc.sites.clone().requires_grad_(True)
+    rec = enc.rec.clone()
+    m, v = enc.m.clone(), enc.v.clone()
+    a, b = enc.topk.clone(), torch.empty_like(enc.topk)
+    t0 = enc.counters()[1]
+    S.prepare_sites(img, sites.detach(), rec)
+
+    def one(t):
+        nonlocal a, b
+        S.propagate_topk(img, rec, a, b, 1, J, 77, 10_000 + t)
+        a, b = b, a
+        out = A.render(sites, a, img, rec)
+        loss = A.mse_loss(out, enc.target, img)
+        loss.backward()
+        S.adam_step(img, sites.data, sites.grad, m, v, enc.adam, t0 + t + 1, rec, zero_grad=True)
+
+    for t in range(3):
+        one(t)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for t in range(3, 3 + steps):
+        one(t)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    return {"ms_per_step": round(ms, 4), "mpix_s": round(enc.H * enc.W / (ms * 1e3), 1),
+            "steps": steps,
+            "path": "propagate_topk + SADRender.apply + SADMSELoss.apply + backward + adam_step"}
+
+
+def batched_vs_loop(steps, seed=0):
+    """64 images of uneven size (0.05 sites/px, K = 8): one persistent launch per
+    iteration (autotuned, HIP graph) against a loop of per-image encoders (each one
+    graph-replayed), same seeds, same number of iterations; PSNR compared per image."""
+    import torch
+
+    import synth
+    from paper_2604_21984_amd.autotune import Autotuner
+    from paper_2604_21984_amd.batch import BatchEncoder
+    from paper_2604_21984_amd.encode import EncodeConfig, Encoder
+    shapes = synth.batch_shapes(seed)
+    cfg = EncodeConfig(K=K, n_inject=J, seed=seed)
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(8) as ex:
+        imgs = list(ex.map(lambda a: synth.image_encode(100 + a[0], a[1][0], a[1][1],
+                                                        n_polygons=max(8, a[1][0] * a[1][1] // 2000)),
+                           enumerate(shapes)))
+    tg = [torch.from_numpy(im).cuda() for im in imgs]
+    ns = [n for _, _, n in shapes]
+    P = sum(H * W for H, W, _ in shapes)
+    be = BatchEncoder(tg, ns, cfg)
+    grid, chunked, timings = Autotuner().tune(be, pairs=2, reps=2)
+    be.capture()
+    pairs = max(1, steps // 2)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    be.replay(pairs)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1)
+    ps_b = [be.psnr(i) for i in range(len(shapes))]
+    del be
+    encs = [Encoder(t, n, cfg) for t, n in zip(tg, ns)]
+    for e in encs:
+        e.capture()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(pairs):
+        for e in encs:
+            e.replay(1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_l = e0.elapsed_time(e1)
+    ps_l = [e.psnr() for e in encs]
+    dps = max(abs(x - y) for x, y in zip(ps_b, ps_l))
+    return {"images": len(shapes), "pixels": P, "sites": sum(ns), "iterations": 2 * pairs,
+            "batched_mpix_s": round(P * 2 * pairs / (ms_b * 1e3), 1),
+            "loop_mpix_s": round(P * 2 * pairs / (ms_l * 1e3), 1),
+            "speedup": round(ms_l / ms_b, 3),
+            "mean_psnr_db": round(sum(ps_b) / len(ps_b), 3), "max_abs_dpsnr_db": round(dps, 4),
+            "launch": {"grid": grid, "chunked": chunked},
+            "autotune_ms_per_iter": {k: round(v, 4) for k, v in timings.items()}}
+
+
+def serving(rates, seconds, seed=0):
+    """32 resident sets (sides 512-4096, 0.05 sites/px, K = 8), Poisson arrivals, 80 %
+    point queries of 1e3-1e6 points, 20 % full renders; admission by device memory."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2604_21984_amd import _lib as S
+    from paper_2604_21984_amd import serve as V
+    shapes = synth.serve_shapes(seed)
+    sets = []
+    for sid, (H, W, n) in enumerate(shapes):
+        sites = synth.random_sites(500 + sid, H, W, n, anisotropic=True, log_tau=4.0,
+                                   r_range=(1.0, 8.0))
+        img = S.image(H, W, K, n, n)
+        sd = torch.from_numpy(sites).cuda()
+        rec = torch.empty(n * S.REC_FLOATS, dtype=torch.float32, device="cuda")
+        S.prepare_sites(img, sd, rec)
+        a = torch.empty((K // 4, H, W, 4), dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        S.seed_topk(img, rec, a, b)
+        for t in range(16):
+            S.propagate_topk(img, rec, a, b, S.jump_step(t, H, W), J, sid, t)
+            a, b = b, a
+        del b, sd
+        sets.append(V.ResidentSet(sid, H, W, K, n, rec, a))
+    torch.cuda.synchronize()
+    resident = sum(rs.nbytes() for rs in sets)
+    out = {"sets": len(sets), "resident_pixels": sum(H * W for H, W, _ in shapes),
+           "resident_bytes": resident, "seconds_per_rate": seconds, "by_rate": {}}
+    rng = np.random.default_rng(seed)
+    for rate in rates:
+        times = V.poisson_arrivals(rate, seconds, rng)
+        reqs = []
+        for rid, _ in enumerate(times):
+            sid = int(rng.integers(0, len(sets)))
+            rs = sets[sid]
+            if rng.uniform() < 0.2:
+                reqs.append(V.Request(rid, sid, V.RENDER))
+                continue
+            M = int(np.exp(rng.uniform(np.log(1e3), np.log(1e6))))
+            xy = torch.rand((M, 2), device="cuda")
+            xy[:, 0] *= rs.W - 1
+            xy[:, 1] *= rs.H - 1
+            reqs.append(V.Request(rid, sid, V.QUERY, xy=xy, M=M))
+        torch.cuda.synchronize()
+        srv = V.Server(V.GpuBackend(), sets)
+        V.run_open_loop(srv, reqs, times)
+        torch.cuda.synchronize()
+        st = srv.stats()
+        out["by_rate"][str(rate)] = {k: (round(v, 3) if isinstance(v, float) else v)
+                                     for k, v in st.items()}
+        del reqs, srv
+    return out
+
+
+def topk_quality(trials):
+    """Propagated field vs exact top-K at 256 random pixels (Sec. 6.5 protocol): 1024^2
+    domain, sites at distinct pixel cells, 8 / 12 / 16 passes, J = 4, K = 8."""
+    import synth
+    from paper_2604_21984_amd import quality as Q
+    qt = {}
+    for n in (16384, 65536, 131072):
+        acc = {t: [0.0, 0.0] for t in (8, 12, 16)}
+        for trial in range(trials):
+            sites = synth.cell_sites(1000 + trial, 1024, 1024, n)
+            r = Q.convergence(sites, 1024, 1024, K=K, J=J, passes=(8, 12, 16), n_pix=256,
+                              seed=trial)
+            for t in acc:
+                acc[t][0] += r[t][0] / trials
+                acc[t][1] += r[t][1] / trials
+        qt[str(n)] = {str(t): {"exact_match": round(v[0], 4), "recall": round(v[1], 4)}
+                      for t, v in acc.items()}
+    return {"domain": "1024x1024", "K": K, "J": J, "pixels": 256, "trials": trials,
+            "by_sites_and_passes": qt}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -66,6 +237,16 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of single-thread oracle work for the CPU baseline (0: skip)")
     ap.add_argument("--breakdown-steps", type=int, default=20)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device copies of MIB MiB (calibrates HBM counters)")
+    ap.add_argument("--autograd-steps", type=int, default=50,
+                    help="iterations through the autograd wrappers (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=100,
+                    help="iterations of the 64-image batched vs per-image comparison (0: skip)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="seconds of Poisson arrivals per rate (0: skip serving)")
+    ap.add_argument("--quality-trials", type=int, default=4,
+                    help="trials of the top-K convergence measurement (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -74,6 +255,18 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_probe > 0:
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.rand(n, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(5):  # an elementwise kernel: reads and writes 4n bytes
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+                          "copies": 5}), flush=True)
+        return
 
     import synth
     from paper_2604_21984_amd import _lib as S
@@ -171,6 +364,22 @@ def main():
         "psnr_db": round(psnr, 3),
         "wall_s": round(wall, 4),
     }
+
+    def extra(name, fn, *a):
+        try:
+            result[name] = fn(*a)
+        except Exception as e:  # report, keep the headline line
+            result[name] = {"error": f"{type(e).__name__}: {e}"}
+        print(f"bench: {name} done", file=sys.stderr, flush=True)
+
+    if args.autograd_steps > 0:
+        extra("autograd", autograd_path, enc, args.autograd_steps)
+    if args.batch_steps > 0:
+        extra("batched", batched_vs_loop, args.batch_steps)
+    if args.serve_seconds > 0:
+        extra("serving", serving, (10, 100, 1000), args.serve_seconds)
+    if args.quality_trials > 0:
+        extra("topk_quality", topk_quality, args.quality_trials)
 
     if args.cpu_budget > 0:
         lists_np = enc.topk.cpu().numpy()

@@ -157,6 +157,15 @@ sad_status sad_render_bwd(const sad_image *img, const float *rec, const uint32_t
                           const float *grad_img, const float *target, float *grad_sites,
                           float *removal_delta, void *stream);
 
+/* Exact top-K by brute force over sites 0..n_slots-1 (the ground truth Sec. 6.5
+ * compares propagated lists with): for each pixel index pix[q] (i*W + j), the K best
+ * sites at (j, i) in list order (score descending, ID ascending), padded with
+ * SAD_INVALID_ID; an index outside [0, H*W) gives an all-invalid row.  pix: DEVICE
+ * int64[n_pix]; out: uint32[n_pix][K] (one row per pixel).  One block per pixel, so
+ * meant for samples (cost n_pix * n_slots scores). */
+sad_status sad_exact_topk(const sad_image *img, const float *rec, const int64_t *pix,
+                          int64_t n_pix, uint32_t *out, void *stream);
+
 /* ---- a8: Adam step (Sec. 5; clamps of Sec. 6.1) ----------------------------------
  * For every active slot: bias-corrected Adam on the ten parameters with gradient
  * grad[10][cap], moments m, v [10][cap] (updated), step >= 1; then clamp x to
@@ -295,6 +304,67 @@ sad_status sad_batch_train_step(const sad_batch *batch, const sad_train_config *
                                 const uint32_t *topk_in, uint32_t *topk_out, float *grad_sites,
                                 float *adam_m, float *adam_v, float *rendered, float *grad_img,
                                 sad_step_state *states, void *stream);
+
+/* ---- adaptive budget: statistics, prune, split (Sec. 4.5; App. B.5) ---------------
+ * Statistics pass.  For every pixel x, blended from its list as in sad_render_fwd, with
+ * residual e(x) = ||c(x) - I(x)||^2, and every valid entry i (w = its softmax weight,
+ * omega = w e(x), d = x - p_i):
+ *   stats[0][i] += w             soft mass m_i
+ *   stats[1][i] += omega         energy E_i
+ *   stats[2][i] += omega d_x     stats[3][i] += omega d_y
+ *   stats[4][i] += omega d_x^2   stats[5][i] += omega d_x d_y   stats[6][i] += omega d_y^2
+ *   stats[7][i] += Delta_i(x) / (H W)   removal delta (as sad_render_bwd computes it)
+ * i.e. the residual-weighted moments about the site centre.  stats: float[8][cap],
+ * accumulated (+=): the caller zeroes it.  target: float[3][H][W].  Sums are formed
+ * per 16x16 tile in 64-bit fixed point in LDS and added across tiles with float
+ * atomics, so the last bits depend on scheduling. */
+#define SAD_NSTAT 8
+sad_status sad_site_stats(const sad_image *img, const float *rec, const uint32_t *topk,
+                          const float *target, float *stats, void *stream);
+
+/* One budget step on slots 0..cap-1 (img->n_slots is not used; img->K only for
+ * seeding).  With n_active the number of active slots:
+ *   SAD_DP_PRUNE: the floor(p_prune n_active) active sites with the smallest removal
+ *     delta stats[7] (ties to the lower slot) become inactive (x = y = -1).
+ *   SAD_DP_SPLIT: candidates are the active, unpruned sites with m = stats[0] >
+ *     min_mass; their score E / max(m, eps)^alpha is evaluated in double and rounded
+ *     to float (ties to the lower slot); the min(floor(p_split n_active), candidates,
+ *     free slots) best are split in two.  Children are offset from the residual-weighted
+ *     centroid along the principal axis of the residual-weighted covariance by
+ *     0.5 sqrt(m) px (clamped to [1.5, 48]), take u = that axis and a = 0.5 ln(l2/l1)
+ *     (clamped to [-2, 2]; -2 if l2 <= 0); without usable statistics (E <= 1e-12, trace
+ *     <= 1e-9 or eigenvalue gap <= 1e-6 of the trace) they are offset from p along the
+ *     principal axis of the target's Sobel structure tensor at p (else along u), keep u
+ *     and take a = 0.8 a.  Both children: positions clamped to the image, log_tau - 0.25
+ *     and 0.85 r (clamped as by Adam), colour = target at the nearest pixel.  The "+"
+ *     child keeps the parent's slot; parents in ascending slot order give their "-"
+ *     child the free slots (inactive after the prune) in ascending order.  Adam moments
+ *     of both slots are zeroed (all ten parameters).
+ *   SAD_DP_SEED (topk non-NULL): at every pixel holding a "-" child, the child with the
+ *     smallest slot replaces list entry K-1, so that propagation starts from it.
+ * counts: DEVICE int64[6] = {n_active, pruned, split, n_active after, high water (1 +
+ * the largest active slot, 0 if none), split candidates}.  After the call the caller
+ * refreshes the derived records (sad_prepare_sites) over n_slots >= high water.
+ * stats: float[8][cap] from sad_site_stats.  workspace: device scratch of
+ * *workspace_bytes; workspace = NULL queries the size. */
+#define SAD_DP_PRUNE 1u
+#define SAD_DP_SPLIT 2u
+#define SAD_DP_SEED 4u
+typedef struct {
+    double p_prune;  /* fraction of the active count pruned (Sec. 6.1: 0.033) */
+    double p_split;  /* fraction of the active count split (Sec. 6.1: 0.01) */
+    double alpha;    /* score exponent (Sec. 6.1: 0.7) */
+    double eps;      /* mass floor (Sec. 4.5: 1e-8) */
+    double min_mass; /* sites with m <= min_mass are not split (Sec. 4.5: 1) */
+    uint32_t flags;
+    uint32_t pad;
+} sad_budget_params;
+
+sad_status sad_densify_prune(const sad_image *img, const float *target, float *sites,
+                             float *adam_m, float *adam_v, const float *stats,
+                             const sad_budget_params *params /* host */, uint32_t *topk,
+                             int64_t *counts, void *workspace, size_t *workspace_bytes,
+                             void *stream);
 
 /* ---- diagnostics ------------------------------------------------------------------ */
 const char *sad_status_string(sad_status s);

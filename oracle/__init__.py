@@ -70,7 +70,8 @@ def lib():
         L.ora_init_sites.argtypes = [i32, i32, _f32p, i64, f64, u64, f32, f32, _f32p, i64,
                                      _opt(_f64p)]
         L.ora_init_sites.restype = i64
-        L.ora_site_stats.argtypes = [i32, i32, i32, f32, _f32p, i64, i64, _u32p, _f32p, _f64p]
+        L.ora_site_stats.argtypes = [i32, i32, i32, f32, _f32p, i64, i64, _u32p, _f32p, _f64p,
+                                     _opt(_f64p), _opt(_f64p)]
         L.ora_densify_prune.argtypes = [i32, i32, i32, _f32p, _f32p, i64, _opt(_f32p),
                                         _opt(_f32p), _f32p, f64, f64, f64, f64, f64, i32,
                                         _opt(_u32p), _i64p]
@@ -221,15 +222,18 @@ NSTAT = 8
 DP_PRUNE, DP_SPLIT, DP_SEED = 1, 2, 4
 
 
-def site_stats(H, W, K, s, sites, n, lists, target):
-    """Statistics [8, cap] (m, E, S_x, S_y, S_xx, S_xy, S_yy, removal delta)."""
+def site_stats(H, W, K, s, sites, n, lists, target, scales=False):
+    """Statistics [8, cap] (m, E, S_x, S_y, S_xx, S_xy, S_yy, removal delta); with
+    scales=True also the sums of |term| and the sensitivity scales, each [8, cap]."""
     L = lib()
     sites = _sites(sites)
     cap = sites.shape[1]
     out = np.zeros((NSTAT, cap), np.float64)
+    sa = np.zeros((NSTAT, cap), np.float64) if scales else None
+    ss = np.zeros((NSTAT, cap), np.float64) if scales else None
     L.ora_site_stats(H, W, K, s, sites, cap, n, _lists(lists, H * W, K),
-                     np.ascontiguousarray(target, dtype=np.float32), out)
-    return out
+                     np.ascontiguousarray(target, dtype=np.float32), out, sa, ss)
+    return (out, sa, ss) if scales else out
 
 
 def densify_prune(target, sites, stats, p_prune, p_split, flags, K=8, adam_m=None, adam_v=None,

@@ -640,11 +640,23 @@ enum { ST_M, ST_E, ST_SX, ST_SY, ST_SXX, ST_SXY, ST_SYY, ST_RD, NSTAT };
  * The moments are weighted by the residual (the split uses a residual-weighted
  * centroid and covariance) and taken about the site centre p_i; the covariance does
  * not depend on that origin.  stats: double[8][cap] in the order (m, E, S_x, S_y,
- * S_xx, S_xy, S_yy, R), accumulated (+=).  Parity: pinned (mass is a partition of
+ * S_xx, S_xy, S_yy, R), accumulated (+=).  sabs (nullable) accumulates the absolute
+ * values of the terms; ssens (nullable) a sensitivity scale: each term's size per unit
+ * of colour error (w sqrt(e) |f(d)| for the residual terms, w for the mass, (sqrt(e) +
+ * 1) / P for the removal delta).  Both measure what the float32 evaluation of a sum
+ * can be expected to get wrong.  Parity: pinned (mass is a partition of
  * unity, energy sums to the loss, one-site moments against a weighted covariance
  * from a library routine, removal delta against ora_render_bwd). */
+static void acc3(double *stats, double *sabs, double *ssens, int64_t o, double v, double sens)
+{
+    stats[o] += v;
+    if (sabs) sabs[o] += fabs(v);
+    if (ssens) ssens[o] += sens;
+}
+
 void ora_site_stats(int H, int W, int K, float s, const float *sites, int64_t cap, int64_t n,
-                    const uint32_t *lists, const float *target, double *stats)
+                    const uint32_t *lists, const float *target, double *stats, double *sabs,
+                    double *ssens)
 {
     int64_t P = (int64_t)H * W;
     site_t *st = (site_t *)malloc(sizeof(site_t) * (size_t)(n > 0 ? n : 1));
@@ -661,18 +673,21 @@ void ora_site_stats(int H, int W, int K, float s, const float *sites, int64_t ca
             e += d * d;
         }
         removal_delta_pixel(&px, st, target, P, p, dl);
+        /* sensitivity scale of the residual terms: |d e / d c| |dc| ~ 2 sqrt(e) |dc| */
+        double se = sqrt(e);
         for (int v = 0; v < px.nv; ++v) {
             int64_t id = px.idx[v];
-            double w = px.w[v], om = w * e;
+            double w = px.w[v], om = w * e, ws = w * se;
             double dx = X - (double)st[id].x, dy = Y - (double)st[id].y;
-            stats[ST_M * cap + id] += w;
-            stats[ST_E * cap + id] += om;
-            stats[ST_SX * cap + id] += om * dx;
-            stats[ST_SY * cap + id] += om * dy;
-            stats[ST_SXX * cap + id] += om * dx * dx;
-            stats[ST_SXY * cap + id] += om * dx * dy;
-            stats[ST_SYY * cap + id] += om * dy * dy;
-            stats[ST_RD * cap + id] += dl[v] / (double)P;
+            double ax = fabs(dx), ay = fabs(dy);
+            acc3(stats, sabs, ssens, ST_M * cap + id, w, w);
+            acc3(stats, sabs, ssens, ST_E * cap + id, om, ws);
+            acc3(stats, sabs, ssens, ST_SX * cap + id, om * dx, ws * ax);
+            acc3(stats, sabs, ssens, ST_SY * cap + id, om * dy, ws * ay);
+            acc3(stats, sabs, ssens, ST_SXX * cap + id, om * dx * dx, ws * ax * ax);
+            acc3(stats, sabs, ssens, ST_SXY * cap + id, om * dx * dy, ws * ax * ay);
+            acc3(stats, sabs, ssens, ST_SYY * cap + id, om * dy * dy, ws * ay * ay);
+            acc3(stats, sabs, ssens, ST_RD * cap + id, dl[v] / (double)P, (se + 1.0) / (double)P);
         }
     }
     free(st);

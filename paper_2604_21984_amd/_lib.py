@@ -54,6 +54,12 @@ class SadBatch(C.Structure):
                 ("n_site_slots", C.c_int64), ("images", C.c_void_p)]
 
 
+class SadBudgetParams(C.Structure):
+    _fields_ = [("p_prune", C.c_double), ("p_split", C.c_double), ("alpha", C.c_double),
+                ("eps", C.c_double), ("min_mass", C.c_double), ("flags", C.c_uint32),
+                ("pad", C.c_uint32)]
+
+
 class SadQueryJob(C.Structure):
     _fields_ = [("rec", C.c_void_p), ("topk", C.c_void_p), ("xy", C.c_void_p), ("out", C.c_void_p),
                 ("M", C.c_int64), ("q0", C.c_int64), ("H", C.c_int32), ("W", C.c_int32),
@@ -80,6 +86,10 @@ def _load():
         "sad_train_step": [IMG, C.POINTER(SadTrainConfig), P, P, P, P, P, P, P, P, P, P, P, P],
         "sad_train_image_pass": [IMG, C.POINTER(SadTrainConfig), P, P, P, P, P, P, P, P, P],
         "sad_query_batch": [P, I32, I64, I32, P],
+        "sad_site_stats": [IMG, P, P, P, P, P],
+        "sad_exact_topk": [IMG, P, P, I64, P, P],
+        "sad_densify_prune": [IMG, P, P, P, P, P, C.POINTER(SadBudgetParams), P, P, P,
+                              C.POINTER(SZ), P],
         "sad_batch_train_step": [C.POINTER(SadBatch), C.POINTER(SadTrainConfig), P, P, P, P, P, P,
                                  P, P, P, P, P, P],
     }
@@ -270,6 +280,57 @@ def init_sites(img, target, n_sites, lam, seed, log_tau0, r0, sites, workspace):
                               _ptr(workspace, workspace.dtype, None, "workspace"), C.byref(nbytes),
                               _stream()),
            "sad_init_sites")
+
+
+def exact_topk(img, rec, pix, out):
+    """Brute-force top-K of the pixels pix (device int64) into out [n, K] (sad_exact_topk)."""
+    n = pix.numel()
+    _check(lib.sad_exact_topk(C.byref(img), _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                              _ptr(pix, torch.int64, n, "pix"), int(n),
+                              _ptr(out, torch.int32, n * img.K, "out"), _stream()),
+           "sad_exact_topk")
+
+
+NSTAT = 8
+DP_PRUNE, DP_SPLIT, DP_SEED = 1, 2, 4
+
+
+def site_stats(img, rec, topk, target, stats):
+    """Accumulate the per-site statistics into stats [8, cap] (sad_site_stats)."""
+    P = img.H * img.W
+    _check(lib.sad_site_stats(C.byref(img), _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                              _ptr(topk, torch.int32, img.K * P, "topk"),
+                              _ptr(target, torch.float32, 3 * P, "target"),
+                              _ptr(stats, torch.float32, NSTAT * img.cap, "stats"), _stream()),
+           "sad_site_stats")
+
+
+def budget_params(p_prune, p_split, flags, alpha=0.7, eps=1e-8, min_mass=1.0):
+    return SadBudgetParams(float(p_prune), float(p_split), float(alpha), float(eps),
+                           float(min_mass), int(flags), 0)
+
+
+def densify_workspace_bytes(img):
+    n = C.c_size_t(0)
+    _check(lib.sad_densify_prune(C.byref(img), None, None, None, None, None, None, None, None, None,
+                                 C.byref(n), None), "sad_densify_prune")
+    return int(n.value)
+
+
+def densify_prune(img, target, sites, adam_m, adam_v, stats, params, topk, counts, workspace):
+    """One budget step (sad_densify_prune); counts: device int64[6]."""
+    P = img.H * img.W
+    nbytes = C.c_size_t(workspace.numel() * workspace.element_size())
+    _check(lib.sad_densify_prune(C.byref(img), _ptr(target, torch.float32, 3 * P, "target"),
+                                 _ptr(sites, torch.float32, NPARAM * img.cap, "sites"),
+                                 _ptr(adam_m, torch.float32, NPARAM * img.cap, "adam_m"),
+                                 _ptr(adam_v, torch.float32, NPARAM * img.cap, "adam_v"),
+                                 _ptr(stats, torch.float32, NSTAT * img.cap, "stats"),
+                                 C.byref(params), _ptr(topk, torch.int32, img.K * P, "topk"),
+                                 _ptr(counts, torch.int64, 6, "counts"),
+                                 _ptr(workspace, workspace.dtype, None, "workspace"), C.byref(nbytes),
+                                 _stream()),
+           "sad_densify_prune")
 
 
 def version():

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsad.so")
-SOURCES = ["api.hip", "sites.hip", "prop.hip", "render.hip", "init.hip", "step.hip", "batch.hip"]
+SOURCES = ["api.hip", "sites.hip", "prop.hip", "render.hip", "init.hip", "step.hip", "batch.hip",
+           "budget.hip"]
 ARCH = os.environ.get("SAD_OFFLOAD_ARCH", "gfx950")
 
 HIPFLAGS = [

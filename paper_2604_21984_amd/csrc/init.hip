@@ -12,6 +12,7 @@
 
 #include "sad_device.h"
 #include "sad_host.h"
+#include "sad_internal.h"
 
 namespace sad {
 
@@ -81,15 +82,6 @@ __global__ __launch_bounds__(256) void k_keys(const float *__restrict__ I, int H
     const double key = pr > 0.0 ? log(u) / pr : -INFINITY;
     code[p] = order_f64(key);
 }
-
-// Radix-select state: prefix of the wanted code, its mask, and the rank still wanted
-// among codes matching the prefix.
-struct SelState {
-    uint64_t prefix;
-    uint64_t mask;
-    uint32_t want;
-    uint32_t pad;
-};
 
 __global__ void k_sel_init(SelState *st, uint32_t n) {
     st->prefix = 0;
@@ -247,6 +239,25 @@ __global__ void k_copy1(const uint32_t *__restrict__ a, uint32_t *__restrict__ b
 
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+void launch_radix_select(const uint64_t *code, int64_t n, SelState *st, uint32_t *hist,
+                         hipStream_t s) {
+    const int64_t nb = (n + 255) / 256;
+    const unsigned nbh = (unsigned)(nb < 1024 ? (nb > 0 ? nb : 1) : 1024);
+    for (int d = 7; d >= 0; --d) {
+        hipLaunchKernelGGL(k_sel_hist, dim3(nbh), dim3(256), 0, s, code, n, 8 * d, st, hist);
+        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(64), 0, s, st, hist, 8 * d);
+    }
+}
+
+int64_t scan_blocks(int64_t n) { return (n + kScanBlock - 1) / kScanBlock; }
+
+void launch_excl_scan(uint32_t *f, int64_t n, uint32_t *btot, hipStream_t s) {
+    const int64_t nb = scan_blocks(n);
+    hipLaunchKernelGGL(k_scan_tot, dim3((unsigned)nb), dim3(256), 0, s, f, n, btot);
+    hipLaunchKernelGGL(k_scan_btot, dim3(1), dim3(256), 0, s, btot, (int)nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(256), 0, s, f, n, btot);
+}
+
 }  // namespace sad
 
 using namespace sad;
@@ -291,11 +302,7 @@ extern "C" sad_status sad_init_sites(const sad_image *img, const float *target, 
     uint32_t *misc = reinterpret_cast<uint32_t *>(ws + off_misc);
     const unsigned nbP = (unsigned)((P + 255) / 256);
 
-    auto scan = [&](uint32_t *f) {
-        hipLaunchKernelGGL(k_scan_tot, dim3((unsigned)nb_scan), dim3(256), 0, st, f, P, btot);
-        hipLaunchKernelGGL(k_scan_btot, dim3(1), dim3(256), 0, st, btot, (int)nb_scan);
-        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb_scan), dim3(256), 0, st, f, P, btot);
-    };
+    auto scan = [&](uint32_t *f) { launch_excl_scan(f, P, btot, st); };
     if (n_sites > 0) {
         hipLaunchKernelGGL(k_gm_partial, dim3((unsigned)nb_scan), dim3(256), 0, st, target, img->H,
                            img->W, part);
@@ -304,11 +311,7 @@ extern "C" sad_status sad_init_sites(const sad_image *img, const float *target, 
                            (double)lambda, seed, G, code);
         hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(1), 0, st, sel, (uint32_t)n_sites);
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(256), 0, st, hist, 256);
-        const unsigned nbh = nbP < 1024u ? nbP : 1024u;
-        for (int d = 7; d >= 0; --d) {
-            hipLaunchKernelGGL(k_sel_hist, dim3(nbh), dim3(256), 0, st, code, P, 8 * d, sel, hist);
-            hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(64), 0, st, sel, hist, 8 * d);
-        }
+        launch_radix_select(code, P, sel, hist, st);
         hipLaunchKernelGGL(k_eq_flags, dim3(nbP), dim3(256), 0, st, code, P, sel, flag);
         scan(flag);
         hipLaunchKernelGGL(k_sel_flags, dim3(nbP), dim3(256), 0, st, code, P, sel, flag);

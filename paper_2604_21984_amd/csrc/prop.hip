@@ -35,6 +35,58 @@ __global__ __launch_bounds__(256) void k_fill_list(uint32_t *__restrict__ p, int
     if (i < n) p[i] = SAD_INVALID_ID;
 }
 
+// Exact top-K of one pixel per block by brute force: each of the 128 threads keeps the
+// best K of a strided share of the sites (keys are unique: one ID, one key), then a
+// pairwise tree of merges of sorted lists in LDS.
+constexpr int kExactThreads = 128;
+
+template <int K>
+__global__ __launch_bounds__(kExactThreads) void k_exact(int H, int W, int n_slots,
+                                                         const float4 *__restrict__ rec,
+                                                         const int64_t *__restrict__ pix,
+                                                         uint32_t *__restrict__ out) {
+    __shared__ uint64_t lk[kExactThreads][K];
+    const int t = threadIdx.x;
+    const int64_t P = (int64_t)H * W;
+    const int64_t p = pix[blockIdx.x];
+    uint64_t keys[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) keys[k] = 0ull;
+    if (p >= 0 && p < P) {
+        const float X = (float)(p % W), Y = (float)(p / W);
+        for (int i = t; i < n_slots; i += kExactThreads) {
+            const float4 q0 = rec[4 * (size_t)i], q1 = rec[4 * (size_t)i + 1];
+            if (q1.w == 0.0f) continue;
+            insert_key<K>(keys, make_key(score(q0, q1, X, Y), (uint32_t)i));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) lk[t][k] = keys[k];
+    __syncthreads();
+    for (int s = kExactThreads / 2; s >= 1; s >>= 1) {
+        if (t < s) {
+            uint64_t m[K];
+            int ia = 0, ib = 0;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const uint64_t a = ia < K ? lk[t][ia] : 0ull;
+                const uint64_t b = ib < K ? lk[t + s][ib] : 0ull;
+                const bool ta = a >= b;
+                m[k] = ta ? a : b;
+                ia += ta ? 1 : 0;
+                ib += ta ? 0 : 1;
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) lk[t][k] = m[k];
+        }
+        __syncthreads();
+    }
+    if (t < K) {
+        const uint64_t k = lk[0][t];
+        out[(int64_t)blockIdx.x * K + t] = k ? key_id(k) : SAD_INVALID_ID;
+    }
+}
+
 }  // namespace sad
 
 using namespace sad;
@@ -75,6 +127,31 @@ void sad::launch_propagate(const sad_image *img, const float *rec, const uint32_
         case 32: launch_prop<32>(a, r4, li, lo, st); break;
         default: break;
     }
+}
+
+extern "C" sad_status sad_exact_topk(const sad_image *img, const float *rec, const int64_t *pix,
+                                     int64_t n_pix, uint32_t *out, void *stream) {
+    SAD_TRY(check_image(img, nullptr));
+    SAD_REQUIRE(n_pix >= 0 && n_pix <= 0x7FFFFFFF, SAD_ERR_INVALID_ARGUMENT,
+                "sad_exact_topk: bad pixel count");
+    if (n_pix == 0) return SAD_OK;
+    SAD_REQUIRE(pix && out, SAD_ERR_INVALID_ARGUMENT, "sad_exact_topk: NULL pointer");
+    SAD_REQUIRE(img->n_slots == 0 || (rec && aligned16(rec)), SAD_ERR_INVALID_ARGUMENT,
+                "sad_exact_topk: rec NULL or not 16-byte aligned");
+    hipStream_t st = as_stream(stream);
+    const dim3 g((unsigned)n_pix), b(kExactThreads);
+    const float4 *r4 = reinterpret_cast<const float4 *>(rec);
+    switch (img->K) {
+#define SAD_EXACT_CASE(KK)                                                                    \
+    case KK:                                                                                  \
+        hipLaunchKernelGGL(k_exact<KK>, g, b, 0, st, img->H, img->W, img->n_slots, r4, pix, out); \
+        break;
+        SAD_EXACT_CASE(4) SAD_EXACT_CASE(8) SAD_EXACT_CASE(12) SAD_EXACT_CASE(16)
+        SAD_EXACT_CASE(20) SAD_EXACT_CASE(24) SAD_EXACT_CASE(28) SAD_EXACT_CASE(32)
+#undef SAD_EXACT_CASE
+        default: break;
+    }
+    return check_launch("sad_exact_topk");
 }
 
 extern "C" sad_status sad_propagate_topk(const sad_image *img, const float *rec,

@@ -179,30 +179,6 @@ __global__ __launch_bounds__(256) void k_fill(float *__restrict__ p, int64_t n, 
     if (i < n) p[i] = v;
 }
 
-static ImgArgs img_args(const sad_image *img) {
-    ImgArgs a;
-    a.H = img->H;
-    a.W = img->W;
-    a.n_slots = img->n_slots;
-    a.tiles_x = tiles_x(img);
-    a.n_blocks = n_tiles(img);
-    a.cap = img->cap;
-    a.inv_P = 1.0f / (float)((double)img->H * img->W);
-    return a;
-}
-
-#define SAD_K_SWITCH(KV, CALL)                           \
-    switch (KV) {                                        \
-        case 4: { constexpr int KK = 4; CALL; } break;   \
-        case 8: { constexpr int KK = 8; CALL; } break;   \
-        case 12: { constexpr int KK = 12; CALL; } break; \
-        case 16: { constexpr int KK = 16; CALL; } break; \
-        case 20: { constexpr int KK = 20; CALL; } break; \
-        case 24: { constexpr int KK = 24; CALL; } break; \
-        case 28: { constexpr int KK = 28; CALL; } break; \
-        case 32: { constexpr int KK = 32; CALL; } break; \
-        default: break;                                  \
-    }
 
 }  // namespace sad
 

@@ -33,6 +33,23 @@ void launch_adam(const sad_image *img, float s, float *sites, float *grad, float
                  bool zero_grad, hipStream_t st);
 void launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
 
+// Radix select over unsigned 64-bit codes (8 passes of 8 bits, most significant
+// first).  On entry st->prefix = st->mask = 0 and st->want = the rank wanted (1 = the
+// largest), all on the device; on exit st->prefix is the want-th largest code T and
+// st->want the number of codes equal to T still to take.  hist: 256 zeroed counters,
+// left zeroed.
+struct SelState {
+    uint64_t prefix;
+    uint64_t mask;
+    uint32_t want;
+    uint32_t pad;
+};
+void launch_radix_select(const uint64_t *code, int64_t n, SelState *st, uint32_t *hist,
+                         hipStream_t s);
+// Exclusive prefix sum of n uint32 flags, in place; btot: scan_blocks(n) counters.
+int64_t scan_blocks(int64_t n);
+void launch_excl_scan(uint32_t *f, int64_t n, uint32_t *btot, hipStream_t s);
+
 // Device-side jump schedule (Sec. 4.3), same formula as sad_jump_step.
 __host__ __device__ inline int32_t jump_of(int64_t t, int32_t H, int32_t W) {
     const int m = H > W ? H : W;

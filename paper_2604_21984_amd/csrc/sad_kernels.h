@@ -6,6 +6,7 @@
 #include <cmath>
 
 #include "sad_device.h"
+#include "sad_host.h"
 #include "sad_internal.h"
 
 namespace sad {
@@ -15,6 +16,31 @@ struct ImgArgs {
     int64_t cap;
     float inv_P;
 };
+
+inline ImgArgs img_args(const sad_image *img) {
+    ImgArgs a;
+    a.H = img->H;
+    a.W = img->W;
+    a.n_slots = img->n_slots;
+    a.tiles_x = tiles_x(img);
+    a.n_blocks = n_tiles(img);
+    a.cap = img->cap;
+    a.inv_P = 1.0f / (float)((double)img->H * img->W);
+    return a;
+}
+
+#define SAD_K_SWITCH(KV, CALL)                           \
+    switch (KV) {                                        \
+        case 4: { constexpr int KK = 4; CALL; } break;   \
+        case 8: { constexpr int KK = 8; CALL; } break;   \
+        case 12: { constexpr int KK = 12; CALL; } break; \
+        case 16: { constexpr int KK = 16; CALL; } break; \
+        case 20: { constexpr int KK = 20; CALL; } break; \
+        case 24: { constexpr int KK = 24; CALL; } break; \
+        case 28: { constexpr int KK = 28; CALL; } break; \
+        case 32: { constexpr int KK = 32; CALL; } break; \
+        default: break;                                  \
+    }
 
 // Valid entries of one pixel's list with their scores (K registers each).
 template <int K>

@@ -5,6 +5,11 @@ Sec. 6.1), every step on the GPU.
 The iteration is one ``sad_train_step`` call whose counters live in device memory, so a
 pair of iterations (the list field ping-pongs between two buffers) can be recorded as
 a HIP graph once and replayed.
+
+With a ``BudgetSchedule`` the encoder also densifies and prunes (Sec. 4.5, App. B.5):
+after the iterations the schedule names, a statistics pass and one
+``sad_densify_prune`` call; the new high-water mark of active slots is read back (one
+synchronisation per budget event) and becomes the slot range of later iterations.
 """
 import math
 from dataclasses import dataclass, field
@@ -17,6 +22,31 @@ from . import _lib as S
 # (x, y, log_tau, r, c_r, c_g, c_b, u_x, u_y, a).  The paper states per-parameter base
 # rates without values; positions and radius move in pixels, the rest in their units.
 LR_MULT = (100.0, 100.0, 10.0, 100.0, 1.0, 1.0, 1.0, 10.0, 10.0, 10.0)
+
+
+@dataclass
+class BudgetSchedule:
+    """Densify every densify_every iterations within [densify_start, densify_end], prune
+    every prune_every iterations within [prune_start, prune_end) (Sec. 4.5); defaults
+    are the base schedule of Sec. 6.1."""
+    densify_every: int = 20
+    densify_start: int = 20
+    densify_end: int = 3000
+    p_split: float = 0.01
+    prune_every: int = 40
+    prune_start: int = 100
+    prune_end: int = 3000
+    p_prune: float = 0.033
+    alpha: float = 0.7
+    eps: float = 1e-8
+    min_mass: float = 1.0
+    seed_lists: bool = True
+
+    def events(self, it):
+        """(densify, prune) due after iteration it (1-based)."""
+        d = self.densify_start <= it <= self.densify_end and it % self.densify_every == 0
+        p = self.prune_start <= it < self.prune_end and it % self.prune_every == 0
+        return d, p
 
 
 @dataclass
@@ -33,6 +63,7 @@ class EncodeConfig:
     log_tau0: float = None         # None: clamp(ln(2 max(H,W) / sqrt(HW/N)), 2, 20)
     seed: int = 0
     score_scale: float = 0.0       # 0: 1 / max(H, W)
+    budget: BudgetSchedule = None  # adaptive budget (None: fixed site count)
 
 
 def default_log_tau(H, W, N):
@@ -57,7 +88,7 @@ class Encoder:
         dev = self.device
         f32 = dict(dtype=torch.float32, device=dev)
         self.sites = torch.empty((S.NPARAM, cap), **f32)
-        self.rec = torch.empty(max(n_sites, 1) * S.REC_FLOATS, **f32)
+        self.rec = torch.empty(max(cap if cfg.budget else n_sites, 1) * S.REC_FLOATS, **f32)
         self.lists = [torch.empty((cfg.K // 4, H, W, 4), dtype=torch.int32, device=dev)
                       for _ in range(2)]
         self.cur = 0
@@ -79,6 +110,12 @@ class Encoder:
         self.train_cfg = S.train_config(cfg.n_inject, cfg.seed ^ 0x5AD5AD, self.adam)
         self.graph = None
         self.steps = 0
+        self.budget_log = []
+        if cfg.budget:
+            self.stats = torch.zeros((S.NSTAT, cap), **f32)
+            self.counts = torch.zeros(6, dtype=torch.int64, device=dev)
+            self.dp_ws = torch.empty(S.densify_workspace_bytes(self.img), dtype=torch.uint8,
+                                     device=dev)
 
     def loss_value(self):
         """L of the last iteration (synchronises)."""
@@ -93,12 +130,35 @@ class Encoder:
         return self.lists[self.cur]
 
     def step(self):
-        """One training iteration, enqueued on the current stream (no host sync)."""
+        """One training iteration, enqueued on the current stream (no host sync unless a
+        budget event follows it)."""
         a, b = self.lists[self.cur], self.lists[1 - self.cur]
         S.train_step(self.img, self.train_cfg, self.target, self.sites, self.rec, a, b, self.grad,
                      self.m, self.v, None, self.grad_img, self.state)
         self.cur = 1 - self.cur
         self.steps += 1
+        if self.cfg.budget:
+            d, p = self.cfg.budget.events(self.steps)
+            if d or p:
+                self.budget_step(densify=d, prune=p)
+
+    def budget_step(self, densify=True, prune=True):
+        """Statistics pass, one prune / split step, record refresh (Sec. 4.5)."""
+        bs = self.cfg.budget
+        flags = (S.DP_SPLIT if densify else 0) | (S.DP_PRUNE if prune else 0)
+        if bs.seed_lists and densify:
+            flags |= S.DP_SEED
+        self.stats.zero_()
+        S.site_stats(self.img, self.rec, self.topk, self.target, self.stats)
+        prm = S.budget_params(bs.p_prune, bs.p_split, flags, bs.alpha, bs.eps, bs.min_mass)
+        S.densify_prune(self.img, self.target, self.sites, self.m, self.v, self.stats, prm,
+                        self.topk, self.counts, self.dp_ws)
+        c = [int(x) for x in self.counts.tolist()]
+        self.img.n_slots = max(c[4], 1)
+        S.prepare_sites(self.img, self.sites, self.rec)
+        self.budget_log.append({"iteration": self.steps, "densify": densify, "prune": prune,
+                                "counts": c})
+        self.graph = None  # a recorded graph holds the old slot range
 
     def capture(self):
         """Record two iterations (A -> B -> A) as one HIP graph."""

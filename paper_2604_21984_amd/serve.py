@@ -306,9 +306,10 @@ def poisson_arrivals(rate, duration, rng):
         out.append(t)
 
 
-def run_open_loop(server, requests, times, poll_sleep=0.0):
+def run_open_loop(server, requests, times, poll_sleep=0.0, timeout=120.0):
     """Submit requests at their arrival times (seconds from now) from a feeder thread
-    while this thread runs the scheduler; returns when every request has completed."""
+    while this thread runs the scheduler; returns when every request has completed
+    (TimeoutError after `timeout` seconds)."""
     t_start = time.perf_counter()
 
     def feed():
@@ -324,6 +325,8 @@ def run_open_loop(server, requests, times, poll_sleep=0.0):
     n = len(requests)
     while th.is_alive() or len(server.completed) < n:
         server.step()
+        if time.perf_counter() - t_start > timeout:
+            raise TimeoutError(f"open loop: {len(server.completed)} of {n} requests done")
         if poll_sleep:
             time.sleep(poll_sleep)
     th.join()

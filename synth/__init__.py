@@ -213,6 +213,23 @@ def random_sites(seed, H, W, n, cap=None, log_tau=0.0, r=0.0, anisotropic=False,
     return s
 
 
+def cell_sites(seed, H, W, n, log_tau=3.0, r=1.0):
+    """n isotropic sites at distinct pixel cells (drawn without replacement) plus a
+    uniform subpixel offset in [-0.5, 0.5)^2 each, equal log_tau and r (so a pixel's
+    exact top-K is its K nearest centres), colours uniform in [0, 1]^3: the site layout
+    of the propagation-convergence measurement (Sec. 6.5)."""
+    rng = _rng(seed)
+    cells = rng.choice(H * W, n, replace=False)
+    s = np.zeros((NPARAM, n), np.float32)
+    s[0] = np.clip(cells % W + rng.uniform(-0.5, 0.5, n), 0, W - 1)
+    s[1] = np.clip(cells // W + rng.uniform(-0.5, 0.5, n), 0, H - 1)
+    s[2] = log_tau
+    s[3] = r
+    s[4:7] = rng.uniform(0, 1, (3, n))
+    s[7] = 1.0
+    return s
+
+
 def batch_shapes(seed, n_images=64, lo=256, hi=1024, density=0.05):
     """Uneven image sizes: area log-uniform in [lo^2, hi^2], aspect U[1, 2] with random
     orientation; returns a list of (H, W, n_sites)."""

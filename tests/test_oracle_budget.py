@@ -35,6 +35,12 @@ def test_stats_mass_is_partition_of_unity_and_energy_sums_to_loss():
     # second moments are sums of omega d^2 >= 0, and Cauchy-Schwarz per site
     assert (st[4] >= 0).all() and (st[6] >= 0).all()
     assert (st[5] ** 2 <= st[4] * st[6] * (1 + 1e-12) + 1e-300).all()
+    st2, sa, ss = O.site_stats(H, W, K, s, sites, N, lists, tg, scales=True)
+    np.testing.assert_array_equal(st2, st)
+    for q in (0, 1, 4, 6):                                           # terms >= 0
+        np.testing.assert_allclose(sa[q], st[q], rtol=1e-12)
+    assert (sa >= np.abs(st) * (1 - 1e-12)).all() and (ss >= 0).all()
+    np.testing.assert_allclose(ss[0], st[0], rtol=1e-12)             # mass: w per term
 
 
 def test_stats_one_site_moments_equal_weighted_covariance():
