@@ -118,7 +118,7 @@ def batched_vs_loop(steps, seed=0):
     ns = [n for _, _, n in shapes]
     P = sum(H * W for H, W, _ in shapes)
     be = BatchEncoder(tg, ns, cfg)
-    grid, chunked, timings = Autotuner().tune(be, pairs=2, reps=2)
+    grid, chunked, timings = Autotuner().tune(be, pairs=2, reps=2, schedules=(1, 2, 4))
     be.capture()
     pairs = max(1, steps // 2)
     torch.cuda.synchronize()
@@ -148,8 +148,9 @@ def batched_vs_loop(steps, seed=0):
             "loop_mpix_s": round(P * 2 * pairs / (ms_l * 1e3), 1),
             "speedup": round(ms_l / ms_b, 3),
             "mean_psnr_db": round(sum(ps_b) / len(ps_b), 3), "max_abs_dpsnr_db": round(dps, 4),
-            "launch": {"grid": grid, "chunked": chunked},
-            "autotune_ms_per_iter": {k: round(v, 4) for k, v in timings.items()}}
+            "launch": {"grid": grid, "chunked": chunked,
+                       "prop_every": timings.get("prop_every_best", 1)},
+            "autotune": timings}
 
 
 def serving(rates, seconds, seed=0):

@@ -231,9 +231,16 @@ typedef struct {
 
 typedef struct {
     int32_t n_inject;   /* J injected IDs per pixel and pass (Sec. 6.1: 4) */
-    int32_t fixed_jump; /* <= 0: the Sec. 4.3 schedule of state->pass; > 0: this jump */
+    int32_t fixed_jump; /* <= 0: the Sec. 4.3 schedule of the pass index; > 0: this jump */
     uint64_t seed;      /* injection stream */
     sad_adam_params adam;
+    /* Candidate update period f_cand (App. B.3 Tab. impl_params, Sec. 6.1): iteration
+     * state->pass propagates only when state->pass % prop_every == 0, as pass number
+     * state->pass / prop_every of the schedule and of the injection stream; the other
+     * iterations re-score and sort each pixel's own list (a pass with no neighbours and
+     * no injections).  0 or 1: propagate every iteration. */
+    int32_t prop_every;
+    int32_t pad;
 } sad_train_config;
 
 /* One iteration (Sec. 5: no host work inside the loop), enqueued as:

@@ -39,7 +39,7 @@ class SadAdamParams(C.Structure):
 
 class SadTrainConfig(C.Structure):
     _fields_ = [("n_inject", C.c_int32), ("fixed_jump", C.c_int32), ("seed", C.c_uint64),
-                ("adam", SadAdamParams)]
+                ("adam", SadAdamParams), ("prop_every", C.c_int32), ("pad", C.c_int32)]
 
 
 class SadBatchImage(C.Structure):
@@ -337,9 +337,10 @@ def version():
     return lib.sad_version().decode()
 
 
-def train_config(n_inject, seed, adam, fixed_jump=0):
+def train_config(n_inject, seed, adam, fixed_jump=0, prop_every=1):
     c = SadTrainConfig()
     c.n_inject, c.fixed_jump, c.seed, c.adam = int(n_inject), int(fixed_jump), int(seed) & (2 ** 64 - 1), adam
+    c.prop_every = int(prop_every)
     return c
 
 

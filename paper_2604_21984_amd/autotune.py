@@ -2,10 +2,12 @@
 
 Picks the persistent grid size (workgroups per compute unit) and the work assignment
 (contiguous runs of tiles per workgroup, which keeps neighbouring tiles in one XCD's L2,
-or round robin) by timing graph-replayed iterations of the actual batch.  The batch's
-state is restored after the trials, so tuning does not change the encode.  Results are
-cached per workload signature (image shapes, site counts, K) in memory and optionally
-in a JSON file.
+or round robin) by timing graph-replayed iterations of the actual batch, then the
+propagation schedule: the candidate update period f (propagate every f-th iteration,
+App. B.3), the fastest f whose batch loss after a trial window stays within `tol` of
+the loss with f = 1 from the same state.  The batch's state is restored after the
+trials, so tuning does not change the encode.  Results are cached per workload
+signature (image shapes, site counts, K) in memory and optionally in a JSON file.
 """
 import json
 import os
@@ -34,12 +36,16 @@ class Autotuner:
             with open(cache_path) as f:
                 self.cache = json.load(f)
 
-    def tune(self, enc, pairs=3, reps=2):
-        """Return (grid, chunked, timings) for a BatchEncoder and apply the best."""
-        sig = _signature(enc)
+    def tune(self, enc, pairs=3, reps=2, schedules=(1,), window=16, tol=0.01):
+        """Return (grid, chunked, timings) for a BatchEncoder and apply the best launch;
+        with more than one candidate update period in `schedules` also pick and apply
+        the period (reported under timings["prop_every"])."""
+        sig = _signature(enc) + f"|f{','.join(map(str, schedules))}"
         if sig in self.cache:
             grid, chunked = self.cache[sig]["best"]
             enc.set_launch(grid, chunked)
+            if "prop_every" in self.cache[sig]:
+                enc.set_prop_every(self.cache[sig]["prop_every"])
             return grid, chunked, self.cache[sig]["timings"]
         n_cu = torch.cuda.get_device_properties(enc.device).multi_processor_count
         snap = enc.snapshot()
@@ -65,6 +71,29 @@ class Autotuner:
         grid, chunked = (int(x) for x in key.split("/"))
         enc.set_launch(grid, chunked)
         self.cache[sig] = {"best": [grid, chunked], "timings": timings}
+        if len(schedules) > 1:
+            sched = {}
+            for f in schedules:
+                enc.restore(snap)
+                enc.set_prop_every(f)
+                enc.capture()
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                enc.replay(max(1, window // 2))
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / (2 * max(1, window // 2))
+                sched[f] = (ms, sum(enc.losses()))
+            base = sched[schedules[0]][1]
+            ok = [f for f in schedules if sched[f][1] <= base * (1.0 + tol)]
+            best_f = min(ok, key=lambda f: sched[f][0])
+            enc.restore(snap)
+            enc.set_prop_every(best_f)
+            timings["prop_every"] = {str(f): {"ms": v[0], "loss": v[1]} for f, v in sched.items()}
+            timings["prop_every_best"] = best_f
+            self.cache[sig]["prop_every"] = best_f
         if self.cache_path:
             with open(self.cache_path, "w") as f:
                 json.dump(self.cache, f, indent=1)

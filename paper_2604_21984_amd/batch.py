@@ -77,7 +77,8 @@ class BatchEncoder:
             S.seed_topk(img, self.view_rec(b), self.view_list(0, b), self.view_list(1, b))
         lr = [cfg.lr * mlt for mlt in cfg.lr_mult]
         self.adam = S.adam_params(lr, cfg.beta1, cfg.beta2, cfg.eps)
-        self.train_cfg = S.train_config(cfg.n_inject, cfg.seed ^ 0x5AD5AD, self.adam)
+        self.train_cfg = S.train_config(cfg.n_inject, cfg.seed ^ 0x5AD5AD, self.adam,
+                                        prop_every=cfg.prop_every)
         self.graph = None
         self.steps = 0
 
@@ -112,6 +113,11 @@ class BatchEncoder:
     def set_launch(self, grid, chunked):
         self.batch.grid = int(grid)
         self.batch.chunked = int(chunked)
+        self.graph = None
+
+    def set_prop_every(self, f):
+        """Candidate update period (propagate on every f-th iteration)."""
+        self.train_cfg.prop_every = int(f)
         self.graph = None
 
     def step(self):

@@ -34,7 +34,7 @@ __device__ __forceinline__ FixScale fix_scale_dev(int64_t P) {
 }
 
 struct BatchArgs {
-    int n_images, n_items, chunked, J, fixed_jump;
+    int n_images, n_items, chunked, J, fixed_jump, every;
     uint64_t seed;
     const sad_batch_image *images;
 };
@@ -78,6 +78,7 @@ __global__ __launch_bounds__(256) void k_batch_train(BatchArgs ba, const float4 
         pa.n_slots = im.n_slots;
         pa.jump = ba.fixed_jump > 0 ? ba.fixed_jump : 0;
         pa.J = ba.J;
+        pa.every = ba.every;
         pa.tiles_x = tiles_x;
         pa.n_blocks = 0;
         pa.seed = ba.seed;
@@ -203,6 +204,8 @@ extern "C" sad_status sad_batch_train_step(const sad_batch *batch, const sad_tra
                 SAD_ERR_INVALID_ARGUMENT, "sad_batch_train_step: rec / lists not 16-byte aligned");
     SAD_REQUIRE(cfg->n_inject >= 0 && cfg->n_inject <= 16, SAD_ERR_INVALID_ARGUMENT,
                 "sad_batch_train_step: n_inject must be in [0, 16]");
+    SAD_REQUIRE(cfg->prop_every >= 0 && cfg->prop_every <= 1024, SAD_ERR_INVALID_ARGUMENT,
+                "training pass: prop_every must be in [0, 1024]");
     hipStream_t st = as_stream(stream);
     BatchArgs ba;
     ba.n_images = batch->n_images;
@@ -210,6 +213,7 @@ extern "C" sad_status sad_batch_train_step(const sad_batch *batch, const sad_tra
     ba.chunked = batch->chunked;
     ba.J = cfg->n_inject;
     ba.fixed_jump = cfg->fixed_jump;
+    ba.every = cfg->prop_every;
     ba.seed = cfg->seed;
     ba.images = batch->images;
     const int grid = batch->grid > 0 ? (batch->grid < batch->n_items ? batch->grid : batch->n_items)

@@ -108,6 +108,7 @@ void sad::launch_propagate(const sad_image *img, const float *rec, const uint32_
     a.n_slots = img->n_slots;
     a.jump = jump;
     a.J = n_inject;
+    a.every = 1;
     a.tiles_x = tiles_x(img);
     a.n_blocks = n_tiles(img);
     a.seed = seed;

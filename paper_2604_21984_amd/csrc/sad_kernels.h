@@ -185,8 +185,9 @@ __device__ __forceinline__ float block_sum(float v) {
 // ---- propagation ------------------------------------------------------------------
 struct PropArgs {
     int H, W, n_slots, jump, J, tiles_x, n_blocks;
+    int every;                // candidate update period (<= 1: every iteration)
     uint64_t seed, pass;
-    const int64_t *pass_dev;  // device pass index (graph-replayable), or NULL
+    const int64_t *pass_dev;  // device iteration index (graph-replayable), or NULL
 };
 
 // One thread per pixel, 16x16 tiles (four 8x8 wave64 blocks).
@@ -221,7 +222,11 @@ __device__ __forceinline__ void prop_pixel(const PropArgs &a, const float4 *__re
     const int64_t p = (int64_t)px.i * a.W + px.j;
     const float X = (float)px.j, Y = (float)px.i;
     const uint32_t ns = (uint32_t)a.n_slots;
-    const uint64_t pass = a.pass_dev ? (uint64_t)*a.pass_dev : a.pass;
+    const uint64_t it = a.pass_dev ? (uint64_t)*a.pass_dev : a.pass;
+    // with an update period f, iteration it is pass it / f, and only every f-th
+    // iteration looks at neighbours and injections (the same for the whole launch)
+    const bool full = a.every <= 1 || it % (uint64_t)a.every == 0;
+    const uint64_t pass = a.every <= 1 ? it : it / (uint64_t)a.every;
     const int s = (a.pass_dev && a.jump <= 0) ? jump_of((int64_t)pass, a.H, a.W) : a.jump;
 
     auto exact_key = [&](uint32_t id) __attribute__((always_inline)) -> uint64_t {
@@ -285,7 +290,7 @@ __device__ __forceinline__ void prop_pixel(const PropArgs &a, const float4 *__re
 
     // 2. screen the other candidates: the four lists at +-jump, then the injections
 #pragma unroll 1
-    for (int nb = 0; nb < 4; ++nb) {
+    for (int nb = 0; nb < (full ? 4 : 0); ++nb) {
         const int di = nb == 2 ? s : (nb == 3 ? -s : 0);
         const int dj = nb == 0 ? s : (nb == 1 ? -s : 0);
         const int ii = px.i + di, jj = px.j + dj;
@@ -304,7 +309,7 @@ __device__ __forceinline__ void prop_pixel(const PropArgs &a, const float4 *__re
     }
     const uint64_t k0 = (pass * (uint64_t)P + (uint64_t)p) * (uint64_t)a.J;
 #pragma unroll 1
-    for (int j = 0; j < a.J; j += 4) {
+    for (int j = 0; j < (full ? a.J : 0); j += 4) {
         drain_if(4);
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj)

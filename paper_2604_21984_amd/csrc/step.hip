@@ -87,6 +87,8 @@ static sad_status image_pass(const sad_image *img, const sad_train_config *cfg,
                 SAD_ERR_INVALID_ARGUMENT, "training pass: rec / lists not 16-byte aligned");
     SAD_REQUIRE(cfg->n_inject >= 0 && cfg->n_inject <= 16, SAD_ERR_INVALID_ARGUMENT,
                 "training pass: n_inject must be in [0, 16]");
+    SAD_REQUIRE(cfg->prop_every >= 0 && cfg->prop_every <= 1024, SAD_ERR_INVALID_ARGUMENT,
+                "training pass: prop_every must be in [0, 1024]");
     if (img->n_slots == 0) {  // no sites: empty lists, colour 0, nothing to update
         launch_propagate(img, rec, topk_in, topk_out, 1, 0, 0, 0, nullptr, st);
         if (grad_img)
@@ -102,6 +104,7 @@ static sad_status image_pass(const sad_image *img, const sad_train_config *cfg,
     pa.n_slots = img->n_slots;
     pa.jump = cfg->fixed_jump > 0 ? cfg->fixed_jump : 0;
     pa.J = cfg->n_inject;
+    pa.every = cfg->prop_every;
     pa.tiles_x = tiles_x(img);
     pa.n_blocks = n_tiles(img);
     pa.seed = cfg->seed;

@@ -64,6 +64,7 @@ class EncodeConfig:
     seed: int = 0
     score_scale: float = 0.0       # 0: 1 / max(H, W)
     budget: BudgetSchedule = None  # adaptive budget (None: fixed site count)
+    prop_every: int = 1            # candidate update period f_cand (App. B.3)
 
 
 def default_log_tau(H, W, N):
@@ -107,7 +108,8 @@ class Encoder:
         S.seed_topk(self.img, self.rec, self.lists[0], self.lists[1])
         lr = [cfg.lr * mlt for mlt in cfg.lr_mult]
         self.adam = S.adam_params(lr, cfg.beta1, cfg.beta2, cfg.eps)
-        self.train_cfg = S.train_config(cfg.n_inject, cfg.seed ^ 0x5AD5AD, self.adam)
+        self.train_cfg = S.train_config(cfg.n_inject, cfg.seed ^ 0x5AD5AD, self.adam,
+                                        prop_every=cfg.prop_every)
         self.graph = None
         self.steps = 0
         self.budget_log = []

@@ -286,3 +286,42 @@ def test_encode_size_full_pipeline_parity(S):
                             abs_sum=True)
     w, rep = grad_report(gg, gref, ab)
     assert w <= 1.0, rep
+
+
+def test_large_image_k16_parity(S):
+    """2048x2048, N = 100 000 from the initialisation, K = 16, J = 4: initialisation,
+    seed pass and the first two passes of the schedule bit-exact over the whole field
+    (each pass from the oracle's previous field), forward and backward on the result."""
+    H = W = 2048
+    N, K = 100_000, 16
+    target = synth.image_large(0, H, W)
+    s = O.default_scale(H, W)
+    lt0 = float(np.clip(math.log(2 * max(H, W) / math.sqrt(H * W / N)), 2, 20))
+    sites, n = O.init_sites(target, N, 0.3, 3, lt0, 1.0, N)
+    assert n == N
+    img = S.image(H, W, K, N, N)
+    sd = torch.empty((10, N), dtype=torch.float32, device=DEV)
+    ws = torch.empty(S.init_workspace_bytes(img), dtype=torch.uint8, device=DEV)
+    S.init_sites(img, _t(target), N, 0.3, 3, lt0, 1.0, sd, ws)
+    torch.cuda.synchronize()
+    assert np.array_equal(sd.cpu().numpy(), sites)
+    g = Gpu(S, H, W, K, sites, N)
+    g.seed()
+    ref = O.seed_lists(H, W, K, s, sites, N)
+    assert np.array_equal(g.lists(), ref)
+    for t in range(2):
+        jmp = O.jump(t, H, W)
+        g.set_lists(ref)
+        g.prop(jmp, 4, 9, t)
+        ref = O.prop_pass(H, W, K, s, sites, N, ref, jmp, 4, 9, t)
+        got = g.lists()
+        assert np.array_equal(got, ref), f"pass {t}: {np.sum(np.any(got != ref, 1))} pixels differ"
+    col = g.render()
+    cref = O.render(H, W, K, s, sites, N, ref)
+    assert np.abs(col - cref).max() <= 1e-5
+    _, gimg = O.loss_grad(cref, target)
+    gg, _ = g.bwd(gimg.astype(np.float32))
+    gref, ab = O.render_bwd(H, W, K, s, sites, N, ref, gimg.astype(np.float32).astype(np.float64),
+                            abs_sum=True)
+    w, rep = grad_report(gg, gref, ab)
+    assert w <= 1.0, rep

@@ -65,6 +65,29 @@ def test_train_step_equals_individual_calls(mods):
     assert agree > 0.999
 
 
+def test_candidate_update_period(mods):
+    """prop_every = 2: even iterations are passes t/2 of the schedule and injection
+    stream, odd ones re-score and sort each pixel's own list (lr = 0 keeps the sites
+    fixed, so every list is a deterministic function of the previous one)."""
+    S, A, E = mods
+    H, W, N = 80, 112, 500
+    target = torch.from_numpy(synth.image_encode(6, H, W, n_polygons=20, patch=16)).to(DEV)
+    enc = E.Encoder(target, N, E.EncodeConfig(K=8, n_inject=4, seed=2, lr=0.0, prop_every=2))
+    rec = enc.rec.clone()
+    la, lb = enc.lists[0].clone(), enc.lists[1].clone()
+    img, seed = enc.img, enc.train_cfg.seed
+    for t in range(7):
+        enc.step()
+        if t % 2 == 0:
+            S.propagate_topk(img, rec, la, lb, S.jump_step(t // 2, H, W), 4, seed, t // 2)
+        else:
+            S.propagate_topk(img, rec, la, lb, max(H, W), 0, seed, 0)
+        la, lb = lb, la
+        torch.cuda.synchronize()
+        assert torch.equal(enc.topk, la), t
+    assert torch.equal(enc.rec, rec)
+
+
 def test_graph_replay_matches_eager(mods):
     S, A, E = mods
     eager, graphed = _enc(E, seed=3), _enc(E, seed=3)
