@@ -106,9 +106,7 @@ __global__ __launch_bounds__(256) void k_batch_train(BatchArgs ba, const float4 
                                                     key_id(keys[4 * g + 2]),
                                                     key_id(keys[4 * g + 3]));
             PixelBlend<K> bl;
-            float col[K][3];
-            float nrm[K];
-            blend_keys<K, true>(r4, keys, X, Y, bl, col, nrm);
+            blend_keys<K, true>(r4, keys, bl, lane_rot() % K);
             float g[3];
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
@@ -118,7 +116,7 @@ __global__ __launch_bounds__(256) void k_batch_train(BatchArgs ba, const float4 
                 if (gimg) gimg[3 * im.px0 + ch * P + p] = g[ch];
                 if (rendered) rendered[3 * im.px0 + ch * P + p] = bl.c[ch];
             }
-            bwd_pixel<K, false>(r4, bl, col, nrm, X, Y, g[0], g[1], g[2], 0.f, 0.f, 0.f, hkey, hacc,
+            bwd_pixel<K, false>(r4, bl, X, Y, g[0], g[1], g[2], 0.f, 0.f, 0.f, hkey, hacc,
                                 fx, inv_P, im.cap, gr, nullptr);
         } else if (im.n_slots == 0 && px.i < im.H && px.j < im.W) {
             // no sites: empty list, colour 0

@@ -65,10 +65,7 @@ __global__ __launch_bounds__(256) void k_stats(ImgArgs a, StatScale sc,
         const int64_t P = (int64_t)a.H * a.W, p = (int64_t)px.i * a.W + px.j;
         const float X = (float)px.j, Y = (float)px.i;
         PixelBlend<K> b;
-        float col[K][3];
-        const int lane = t & 63;
-        const int rot = ((lane & 7) + 3 * (lane >> 3)) & 7;
-        blend<K, false>(rec, (uint32_t)a.n_slots, topk, P, p, X, Y, b, col, nullptr, rot % K);
+        blend<K, true>(rec, (uint32_t)a.n_slots, topk, P, p, X, Y, b, lane_rot() % K);
         if (b.nv) {
             const float invS = __builtin_amdgcn_rcpf(b.S);
             const float e0 = b.c[0] - tgt[p], e1 = b.c[1] - tgt[P + p], e2 = b.c[2] - tgt[2 * P + p];
@@ -76,30 +73,9 @@ __global__ __launch_bounds__(256) void k_stats(ImgArgs a, StatScale sc,
             // removal delta with the reference entry r (largest score), as in the
             // backward: c'_k - c = -w_k / (1 - w_k) (c_k - c) for k != r, and c'_r from
             // the softmax of the others
-            int r = 0;
-            float mx = -INFINITY;
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                if (b.ok[k] && b.l[k] > mx) {
-                    mx = b.l[k];
-                    r = k;
-                }
-            float cr0 = 0.f, cr1 = 0.f, cr2 = 0.f;
-#pragma unroll
-            for (int k = 0; k < K; ++k)
-                if (k == r) {
-                    cr0 = col[k][0];
-                    cr1 = col[k][1];
-                    cr2 = col[k][2];
-                }
-            float dc0 = 0.f, dc1 = 0.f, dc2 = 0.f;
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const float w = b.e[k] * invS;
-                dc0 = fmaf(w, col[k][0] - cr0, dc0);
-                dc1 = fmaf(w, col[k][1] - cr1, dc1);
-                dc2 = fmaf(w, col[k][2] - cr2, dc2);
-            }
+            const int r = b.r;
+            const float cr0 = b.cr[0], cr1 = b.cr[1], cr2 = b.cr[2];
+            const float dc0 = b.dc[0], dc1 = b.dc[1], dc2 = b.dc[2];
             float dr0, dr1, dr2;
             if (b.nv > 1) {
                 float m2 = -INFINITY;
@@ -110,11 +86,12 @@ __global__ __launch_bounds__(256) void k_stats(ImgArgs a, StatScale sc,
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
                     if (!b.ok[k] || k == r) continue;
+                    const float4 q2 = rec[4 * (size_t)b.id[k] + 2];
                     const float ee = __expf(b.l[k] - m2);
                     S2 += ee;
-                    n0 = fmaf(ee, col[k][0] - cr0, n0);
-                    n1 = fmaf(ee, col[k][1] - cr1, n1);
-                    n2 = fmaf(ee, col[k][2] - cr2, n2);
+                    n0 = fmaf(ee, q2.x - cr0, n0);
+                    n1 = fmaf(ee, q2.y - cr1, n1);
+                    n2 = fmaf(ee, q2.z - cr2, n2);
                 }
                 const float inv2 = __builtin_amdgcn_rcpf(S2);
                 dr0 = n0 * inv2 - dc0;
@@ -130,6 +107,7 @@ __global__ __launch_bounds__(256) void k_stats(ImgArgs a, StatScale sc,
                 if (!b.ok[k]) continue;
                 const uint32_t id = b.id[k];
                 const float4 q0 = rec[4 * (size_t)id];
+                const float4 q2 = rec[4 * (size_t)id + 2];
                 const float w = b.e[k] * invS;
                 const float om = w * err;
                 const float dx = X - q0.x, dy = Y - q0.y;
@@ -140,9 +118,9 @@ __global__ __launch_bounds__(256) void k_stats(ImgArgs a, StatScale sc,
                     p2 = dr2;
                 } else {
                     const float f = -w * __builtin_amdgcn_rcpf(1.0f - w);
-                    p0 = f * ((col[k][0] - cr0) - dc0);
-                    p1 = f * ((col[k][1] - cr1) - dc1);
-                    p2 = f * ((col[k][2] - cr2) - dc2);
+                    p0 = f * ((q2.x - cr0) - dc0);
+                    p1 = f * ((q2.y - cr1) - dc1);
+                    p2 = f * ((q2.z - cr2) - dc2);
                 }
                 float v[kNStat];
                 v[0] = w;

@@ -18,9 +18,8 @@ __global__ __launch_bounds__(256) void k_fwd(ImgArgs a, const float4 *__restrict
     if (px.i >= a.H || px.j >= a.W) return;
     const int64_t P = (int64_t)a.H * a.W, p = (int64_t)px.i * a.W + px.j;
     PixelBlend<K> b;
-    float col[K][3];
-    blend<K, false>(rec, (uint32_t)a.n_slots, topk, P, p, (float)px.j, (float)px.i, b, col,
-                    nullptr);
+    blend<K, false>(rec, (uint32_t)a.n_slots, topk, P, p, (float)px.j, (float)px.i, b,
+                    lane_rot() % K);
     out[p] = b.c[0];
     out[P + p] = b.c[1];
     out[2 * P + p] = b.c[2];
@@ -68,9 +67,8 @@ __global__ __launch_bounds__(256) void k_fwd_loss(ImgArgs a, const float4 *__res
     if (px.i < a.H && px.j < a.W) {
         const int64_t P = (int64_t)a.H * a.W, p = (int64_t)px.i * a.W + px.j;
         PixelBlend<K> b;
-        float col[K][3];
-        blend<K, false>(rec, (uint32_t)a.n_slots, topk, P, p, (float)px.j, (float)px.i, b, col,
-                        nullptr);
+        blend<K, false>(rec, (uint32_t)a.n_slots, topk, P, p, (float)px.j, (float)px.i, b,
+                        lane_rot() % K);
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             const float d = b.c[ch] - tgt[ch * P + p];
@@ -92,7 +90,6 @@ __global__ __launch_bounds__(256) void k_bwd(ImgArgs a, FixScale fx, const float
                                              float *__restrict__ grad, float *__restrict__ rdel) {
     __shared__ uint32_t hkey[kHashSlots];
     __shared__ unsigned long long hacc[kAcc][kHashSlots];
-    const int t = threadIdx.x;
     bwd_tile_init(hkey, hacc);
     __syncthreads();
 
@@ -102,14 +99,10 @@ __global__ __launch_bounds__(256) void k_bwd(ImgArgs a, FixScale fx, const float
         const int64_t P = (int64_t)a.H * a.W, p = (int64_t)px.i * a.W + px.j;
         const float X = (float)px.j, Y = (float)px.i;
         PixelBlend<K> b;
-        float col[K][3];
-        float nrm[K];
-        const int lane = t & 63;
-        const int rot = ((lane & 7) + 3 * (lane >> 3)) & 7;
-        blend<K, true>(rec, (uint32_t)a.n_slots, topk, P, p, X, Y, b, col, nrm, rot % K);
+        blend<K, true>(rec, (uint32_t)a.n_slots, topk, P, p, X, Y, b, lane_rot() % K);
         const float I0 = kRD ? tgt[p] : 0.f, I1 = kRD ? tgt[P + p] : 0.f;
         const float I2 = kRD ? tgt[2 * P + p] : 0.f;
-        bwd_pixel<K, kRD>(rec, b, col, nrm, X, Y, gimg[p], gimg[P + p], gimg[2 * P + p], I0, I1, I2,
+        bwd_pixel<K, kRD>(rec, b, X, Y, gimg[p], gimg[P + p], gimg[2 * P + p], I0, I1, I2,
                           hkey, hacc, fx, a.inv_P, a.cap, grad, rdel);
     }
     __syncthreads();
@@ -130,8 +123,7 @@ __global__ __launch_bounds__(256) void k_query(ImgArgs a, const float4 *__restri
     const int jj = !(fj > 0.f) ? 0 : (fj > (float)(a.W - 1) ? a.W - 1 : (int)fj);
     const int64_t P = (int64_t)a.H * a.W, p = (int64_t)ii * a.W + jj;
     PixelBlend<K> b;
-    float col[K][3];
-    blend<K, false>(rec, (uint32_t)a.n_slots, topk, P, p, pt.x, pt.y, b, col, nullptr);
+    blend<K, false>(rec, (uint32_t)a.n_slots, topk, P, p, pt.x, pt.y, b);
     out[3 * q] = b.c[0];
     out[3 * q + 1] = b.c[1];
     out[3 * q + 2] = b.c[2];
@@ -162,9 +154,8 @@ __global__ __launch_bounds__(256) void k_query_batch(const sad_query_job *__rest
     float c0 = 0.f, c1 = 0.f, c2 = 0.f;
     if (jb.n_slots > 0) {
         PixelBlend<K> b;
-        float col[K][3];
         blend<K, false>(reinterpret_cast<const float4 *>(jb.rec), (uint32_t)jb.n_slots,
-                        reinterpret_cast<const uint4 *>(jb.topk), P, p, pt.x, pt.y, b, col, nullptr);
+                        reinterpret_cast<const uint4 *>(jb.topk), P, p, pt.x, pt.y, b);
         c0 = b.c[0];
         c1 = b.c[1];
         c2 = b.c[2];

@@ -51,18 +51,23 @@ struct PixelBlend {
     bool ok[K];
     float S, c[3];
     int nv;
+    int r;                // reference entry (largest score), when requested
+    float cr[3], dc[3];   // its colour and sum_k w_k (c_k - c_r)
 };
 
-// Gather and score the list of pixel p at point (X, Y); max-subtracted softmax; colour.
-// Rotate ids[] left by `rot` (0 <= rot < 8) with three conditional stages.  Used by the
-// backward so that neighbouring lanes work on different ranks of their (similar) lists
-// in the same instruction, which spreads their LDS atomics over different sites.
-template <int K>
-__device__ __forceinline__ void rotate_ids(uint32_t (&ids)[K], int rot) {
+// Rotate ids[] left by `rot` (0 <= rot < 8) with three conditional stages.  The
+// image-space kernels take a pixel's entries in an order rotated by the lane's
+// position in its 8x8 block (lane_rot), so that neighbouring lanes, whose sorted lists
+// are nearly the same, work on different sites in the same instruction: the
+// backward's LDS atomics then go to different slots instead of all to the best site's.
+// Every image-space kernel uses the same rotation, so their sums are formed in the
+// same order.
+template <int K, typename T>
+__device__ __forceinline__ void rotate_ids(T (&ids)[K], int rot) {
 #pragma unroll
     for (int st = 1; st < 8 && st < K; st <<= 1) {
         const bool c = (rot & st) != 0;
-        uint32_t t[K];
+        T t[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) t[j] = c ? ids[(j + st) % K] : ids[j];
 #pragma unroll
@@ -70,11 +75,65 @@ __device__ __forceinline__ void rotate_ids(uint32_t (&ids)[K], int rot) {
     }
 }
 
-template <int K, bool kNeedN>
+__device__ __forceinline__ int lane_rot() {
+    const int lane = threadIdx.x & 63;
+    return ((lane & 7) + 3 * (lane >> 3)) & 7;
+}
+
+// Softmax and colour of a pixel whose entries have been gathered: the max-subtracted
+// weights (App. B.4), c = sum_k w_k c_k, and with kRef the reference entry r (the
+// first entry with the largest score), its colour c_r and dc = sum_k w_k (c_k - c_r),
+// which the backward needs to form c_k - c without cancellation.
+template <int K, bool kRef>
+__device__ __forceinline__ void finish_blend(PixelBlend<K> &b, const float (*col)[3], float m) {
+    b.r = 0;
+    b.cr[0] = b.cr[1] = b.cr[2] = 0.f;
+    if (kRef) {
+        float mx = -INFINITY;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (b.ok[k] && b.l[k] > mx) {
+                mx = b.l[k];
+                b.r = k;
+            }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (k == b.r) {
+                b.cr[0] = col[k][0];
+                b.cr[1] = col[k][1];
+                b.cr[2] = col[k][2];
+            }
+    }
+    b.S = 0.f;
+    float c0 = 0.f, c1 = 0.f, c2 = 0.f, d0 = 0.f, d1 = 0.f, d2 = 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        b.e[k] = b.ok[k] ? __expf(b.l[k] - m) : 0.0f;
+        b.S += b.e[k];
+        c0 = fmaf(b.e[k], col[k][0], c0);
+        c1 = fmaf(b.e[k], col[k][1], c1);
+        c2 = fmaf(b.e[k], col[k][2], c2);
+        if (kRef) {
+            d0 = fmaf(b.e[k], col[k][0] - b.cr[0], d0);
+            d1 = fmaf(b.e[k], col[k][1] - b.cr[1], d1);
+            d2 = fmaf(b.e[k], col[k][2] - b.cr[2], d2);
+        }
+    }
+    const float inv = b.nv ? __builtin_amdgcn_rcpf(b.S) : 0.f;
+    b.c[0] = c0 * inv;
+    b.c[1] = c1 * inv;
+    b.c[2] = c2 * inv;
+    b.dc[0] = d0 * inv;
+    b.dc[1] = d1 * inv;
+    b.dc[2] = d2 * inv;
+}
+
+// Gather and score the list of pixel p at point (X, Y); max-subtracted softmax; colour.
+// The entries are taken in the order rotated by `rot`.
+template <int K, bool kRef>
 __device__ __forceinline__ void blend(const float4 *__restrict__ rec, uint32_t ns,
                                       const uint4 *__restrict__ topk, int64_t P, int64_t p,
-                                      float X, float Y, PixelBlend<K> &b, float (*col)[3],
-                                      float *nrm, int rot = 0) {
+                                      float X, float Y, PixelBlend<K> &b, int rot = 0) {
     float m = -INFINITY;
     b.nv = 0;
     uint32_t ids[K];
@@ -87,57 +146,41 @@ __device__ __forceinline__ void blend(const float4 *__restrict__ rec, uint32_t n
         ids[4 * g + 3] = v.w;
     }
     if (rot) rotate_ids<K>(ids, rot);
-#pragma unroll
-    for (int g = 0; g < K / 4; ++g) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int k = 4 * g + t;
-            const uint32_t id = ids[k];
-            const bool in_range = id < ns;
-            const uint32_t idc = in_range ? id : 0u;
-            const float4 q0 = rec[4 * (size_t)idc], q1 = rec[4 * (size_t)idc + 1];
-            const float4 q2 = rec[4 * (size_t)idc + 2];
-            b.id[k] = idc;
-            b.ok[k] = in_range && q1.w != 0.0f;
-            float n;
-            b.l[k] = score(q0, q1, X, Y, &n);
-            if (kNeedN) nrm[k] = n;
-            col[k][0] = q2.x;
-            col[k][1] = q2.y;
-            col[k][2] = q2.z;
-            if (b.ok[k]) {
-                m = fmaxf(m, b.l[k]);
-                ++b.nv;
-            }
-        }
-    }
-    b.S = 0.f;
-    b.c[0] = b.c[1] = b.c[2] = 0.f;
+    float col[K][3];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        b.e[k] = b.ok[k] ? __expf(b.l[k] - m) : 0.0f;
-        b.S += b.e[k];
-        b.c[0] = fmaf(b.e[k], col[k][0], b.c[0]);
-        b.c[1] = fmaf(b.e[k], col[k][1], b.c[1]);
-        b.c[2] = fmaf(b.e[k], col[k][2], b.c[2]);
+        const uint32_t id = ids[k];
+        const bool in_range = id < ns;
+        const uint32_t idc = in_range ? id : 0u;
+        const float4 q0 = rec[4 * (size_t)idc], q1 = rec[4 * (size_t)idc + 1];
+        const float4 q2 = rec[4 * (size_t)idc + 2];
+        b.id[k] = idc;
+        b.ok[k] = in_range && q1.w != 0.0f;
+        b.l[k] = score(q0, q1, X, Y);
+        col[k][0] = q2.x;
+        col[k][1] = q2.y;
+        col[k][2] = q2.z;
+        if (b.ok[k]) {
+            m = fmaxf(m, b.l[k]);
+            ++b.nv;
+        }
     }
-    if (b.nv) {
-        const float inv = __builtin_amdgcn_rcpf(b.S);
-        b.c[0] *= inv;
-        b.c[1] *= inv;
-        b.c[2] *= inv;
-    }
+    finish_blend<K, kRef>(b, col, m);
 }
 
 // The blend of a pixel from its freshly propagated keys (sorted descending, so entry 0
-// holds the maximum score): the scores are the keys' own exact float32 scores; the
-// norms are recomputed for the backward.
-template <int K, bool kNeedN>
-__device__ __forceinline__ void blend_keys(const float4 *__restrict__ rec, const uint64_t (&keys)[K],
-                                           float X, float Y, PixelBlend<K> &b, float (*col)[3],
-                                           float *nrm) {
+// holds the maximum score): the scores are the keys' own exact float32 scores.  The
+// entries are taken in the order rotated by `rot`, as blend() does with its list.
+template <int K, bool kRef>
+__device__ __forceinline__ void blend_keys(const float4 *__restrict__ rec, const uint64_t (&sorted)[K],
+                                           PixelBlend<K> &b, int rot = 0) {
     b.nv = 0;
-    const float m = keys[0] ? key_score(keys[0]) : 0.0f;
+    const float m = sorted[0] ? key_score(sorted[0]) : 0.0f;
+    uint64_t keys[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) keys[k] = sorted[k];
+    if (rot) rotate_ids<K>(keys, rot);
+    float col[K][3];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         b.ok[k] = keys[k] != 0ull;
@@ -148,28 +191,9 @@ __device__ __forceinline__ void blend_keys(const float4 *__restrict__ rec, const
         col[k][0] = q2.x;
         col[k][1] = q2.y;
         col[k][2] = q2.z;
-        if (kNeedN) {
-            const float4 q0 = rec[4 * (size_t)id], q1 = rec[4 * (size_t)id + 1];
-            nrm[k] = __fsqrt_rn(quad(q0, q1, X, Y));
-        }
         b.nv += b.ok[k] ? 1 : 0;
     }
-    b.S = 0.f;
-    b.c[0] = b.c[1] = b.c[2] = 0.f;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        b.e[k] = b.ok[k] ? __expf(b.l[k] - m) : 0.0f;
-        b.S += b.e[k];
-        b.c[0] = fmaf(b.e[k], col[k][0], b.c[0]);
-        b.c[1] = fmaf(b.e[k], col[k][1], b.c[1]);
-        b.c[2] = fmaf(b.e[k], col[k][2], b.c[2]);
-    }
-    if (b.nv) {
-        const float inv = __builtin_amdgcn_rcpf(b.S);
-        b.c[0] *= inv;
-        b.c[1] *= inv;
-        b.c[2] *= inv;
-    }
+    finish_blend<K, kRef>(b, col, m);
 }
 
 __device__ __forceinline__ float block_sum(float v) {
@@ -371,136 +395,116 @@ __device__ __forceinline__ int hash_slot(uint32_t *__restrict__ hkey, uint32_t i
     return -1;
 }
 
-// Contributions of one pixel (its blend b, colours col, norms nrm) to the site
+// Contributions of one pixel (its blend b, with the reference terms) to the site
 // gradients for dL/dc = (g0, g1, g2), added into the tile table (hkey, hacc) or, if
 // the table is full or a term is out of fixed-point range, straight to global memory.
-// With kRD also the removal delta against the target colour (I0, I1, I2).
+// With kRD also the removal delta against the target colour (I0, I1, I2).  Each
+// entry's record is gathered again here (colour, metric, direction) rather than kept
+// in registers from the blend.
 template <int K, bool kRD>
 __device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const PixelBlend<K> &b,
-                                          const float (*col)[3], const float *nrm, float X,
-                                          float Y, float g0, float g1, float g2, float I0,
-                                          float I1, float I2, uint32_t *__restrict__ hkey,
+                                          float X, float Y, float g0, float g1, float g2,
+                                          float I0, float I1, float I2,
+                                          uint32_t *__restrict__ hkey,
                                           unsigned long long (*hacc)[kHashSlots],
                                           const FixScale &fx, float inv_P, int64_t cap,
                                           float *__restrict__ grad, float *__restrict__ rdel) {
-    if (b.nv) {
-        const float invS = __builtin_amdgcn_rcpf(b.S);
-        // Reference entry r: the largest score (e_r = 1).  Differences are formed
-        // relative to it, so that nothing cancels when one weight is close to 1:
-        //   c_k - c = (c_k - c_r) - dc_r,  dc_r = sum_j w_j (c_j - c_r).
-        int r = 0;
-        float mx = -INFINITY;
+    if (!b.nv) return;
+    const float invS = __builtin_amdgcn_rcpf(b.S);
+    // c_k - c = (c_k - c_r) - dc with dc = sum_j w_j (c_j - c_r), r the reference entry
+    // (largest score, e_r = 1): nothing cancels when one weight is close to 1.
+    const int r = b.r;
+    const float cr0 = b.cr[0], cr1 = b.cr[1], cr2 = b.cr[2];
+    const float dc0 = b.dc[0], dc1 = b.dc[1], dc2 = b.dc[2];
+    // removal delta (Sec. 4.5): Delta = (c' - c) . ((c' - c) + 2 (c - I))
+    float e0 = 0.f, e1 = 0.f, e2 = 0.f;      // c - I
+    float dr0 = 0.f, dr1 = 0.f, dr2 = 0.f;   // c'_r - c for the reference entry
+    if (kRD) {
+        e0 = b.c[0] - I0;
+        e1 = b.c[1] - I1;
+        e2 = b.c[2] - I2;
+        if (b.nv > 1) {
+            float m2 = -INFINITY;
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (b.ok[k] && b.l[k] > mx) {
-                mx = b.l[k];
-                r = k;
+            for (int k = 0; k < K; ++k)
+                if (b.ok[k] && k != r) m2 = fmaxf(m2, b.l[k]);
+            float S2 = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if (!b.ok[k] || k == r) continue;
+                const float4 q2 = rec[4 * (size_t)b.id[k] + 2];
+                const float ee = __expf(b.l[k] - m2);
+                S2 += ee;
+                n0 = fmaf(ee, q2.x - cr0, n0);
+                n1 = fmaf(ee, q2.y - cr1, n1);
+                n2 = fmaf(ee, q2.z - cr2, n2);
             }
-        float cr0 = 0.f, cr1 = 0.f, cr2 = 0.f;
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (k == r) {
-                cr0 = col[k][0];
-                cr1 = col[k][1];
-                cr2 = col[k][2];
-            }
-        float dc0 = 0.f, dc1 = 0.f, dc2 = 0.f;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const float w = b.e[k] * invS;  // 0 for invalid entries
-            dc0 = fmaf(w, col[k][0] - cr0, dc0);
-            dc1 = fmaf(w, col[k][1] - cr1, dc1);
-            dc2 = fmaf(w, col[k][2] - cr2, dc2);
+            const float inv2 = __builtin_amdgcn_rcpf(S2);
+            dr0 = n0 * inv2 - dc0;
+            dr1 = n1 * inv2 - dc1;
+            dr2 = n2 * inv2 - dc2;
+        } else {  // no other entry: the pixel would render 0
+            dr0 = -b.c[0];
+            dr1 = -b.c[1];
+            dr2 = -b.c[2];
         }
-        // removal delta (Sec. 4.5): Delta = (c' - c) . ((c' - c) + 2 (c - I))
-        float e0 = 0.f, e1 = 0.f, e2 = 0.f;      // c - I
-        float dr0 = 0.f, dr1 = 0.f, dr2 = 0.f;   // c'_r - c for the reference entry
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (!b.ok[k]) continue;
+        const uint32_t id = b.id[k];
+        const float4 q0 = rec[4 * (size_t)id], q1 = rec[4 * (size_t)id + 1];
+        const float4 q2 = rec[4 * (size_t)id + 2], q3 = rec[4 * (size_t)id + 3];
+        const float w = b.e[k] * invS;
+        const float d0 = (q2.x - cr0) - dc0;  // c_k - c
+        const float d1 = (q2.y - cr1) - dc1;
+        const float d2 = (q2.z - cr2) - dc2;
+        float acc[kAcc];
+        acc[4] = w * g0;
+        acc[5] = w * g1;
+        acc[6] = w * g2;
+        const float gam = w * (g0 * d0 + g1 * d1 + g2 * d2);
+        acc[2] = gam * b.l[k];
+        acc[3] = gam * q1.y;
+        const float n = __fsqrt_rn(quad(q0, q1, X, Y));
+        acc[0] = acc[1] = acc[7] = acc[8] = acc[9] = 0.f;
+        if (n > 0.f) {
+            const float rho = -0.5f * gam * q1.y * __builtin_amdgcn_rcpf(n);
+            const float ux = q2.w, uy = q3.x, ep = q3.y, em = q3.z;
+            const float dx = X - q0.x, dy = Y - q0.y;
+            const float al = ux * dx + uy * dy, be = ux * dy - uy * dx;
+            const float A = ep * al, B = em * be;
+            acc[0] = -2.0f * rho * (A * ux - B * uy);
+            acc[1] = -2.0f * rho * (A * uy + B * ux);
+            acc[9] = rho * (A * al - B * be);
+            acc[7] = 2.0f * rho * (A * dx + B * dy);
+            acc[8] = 2.0f * rho * (A * dy - B * dx);
+        }
+        acc[10] = 0.f;
         if (kRD) {
-            e0 = b.c[0] - I0;
-            e1 = b.c[1] - I1;
-            e2 = b.c[2] - I2;
-            if (b.nv > 1) {
-                float m2 = -INFINITY;
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-                    if (b.ok[k] && k != r) m2 = fmaxf(m2, b.l[k]);
-                float S2 = 0.f, n0 = 0.f, n1 = 0.f, n2 = 0.f;
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    if (!b.ok[k] || k == r) continue;
-                    const float ee = __expf(b.l[k] - m2);
-                    S2 += ee;
-                    n0 = fmaf(ee, col[k][0] - cr0, n0);
-                    n1 = fmaf(ee, col[k][1] - cr1, n1);
-                    n2 = fmaf(ee, col[k][2] - cr2, n2);
-                }
-                const float inv2 = __builtin_amdgcn_rcpf(S2);
-                dr0 = n0 * inv2 - dc0;
-                dr1 = n1 * inv2 - dc1;
-                dr2 = n2 * inv2 - dc2;
-            } else {  // no other entry: the pixel would render 0
-                dr0 = -b.c[0];
-                dr1 = -b.c[1];
-                dr2 = -b.c[2];
+            float p0, p1, p2;  // c'_k - c
+            if (k == r) {
+                p0 = dr0;
+                p1 = dr1;
+                p2 = dr2;
+            } else {  // c' - c = -w / (1 - w) (c_k - c), with w <= 1/2 here
+                const float f = -w * __builtin_amdgcn_rcpf(1.0f - w);
+                p0 = f * d0;
+                p1 = f * d1;
+                p2 = f * d2;
             }
+            acc[10] = (p0 * (p0 + 2.0f * e0) + p1 * (p1 + 2.0f * e1) +
+                       p2 * (p2 + 2.0f * e2)) * inv_P;
         }
+        const int slot = hash_slot(hkey, id);
+        constexpr int nq = kRD ? kAcc : 10;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            if (!b.ok[k]) continue;
-            const uint32_t id = b.id[k];
-            const float4 q0 = rec[4 * (size_t)id], q1 = rec[4 * (size_t)id + 1];
-            const float4 q2 = rec[4 * (size_t)id + 2], q3 = rec[4 * (size_t)id + 3];
-            const float w = b.e[k] * invS;
-            const float d0 = (col[k][0] - cr0) - dc0;  // c_k - c
-            const float d1 = (col[k][1] - cr1) - dc1;
-            const float d2 = (col[k][2] - cr2) - dc2;
-            float acc[kAcc];
-            acc[4] = w * g0;
-            acc[5] = w * g1;
-            acc[6] = w * g2;
-            const float gam = w * (g0 * d0 + g1 * d1 + g2 * d2);
-            acc[2] = gam * b.l[k];
-            acc[3] = gam * q1.y;
-            const float n = nrm[k];
-            acc[0] = acc[1] = acc[7] = acc[8] = acc[9] = 0.f;
-            if (n > 0.f) {
-                const float rho = -0.5f * gam * q1.y * __builtin_amdgcn_rcpf(n);
-                const float ux = q2.w, uy = q3.x, ep = q3.y, em = q3.z;
-                const float dx = X - q0.x, dy = Y - q0.y;
-                const float al = ux * dx + uy * dy, be = ux * dy - uy * dx;
-                const float A = ep * al, B = em * be;
-                acc[0] = -2.0f * rho * (A * ux - B * uy);
-                acc[1] = -2.0f * rho * (A * uy + B * ux);
-                acc[9] = rho * (A * al - B * be);
-                acc[7] = 2.0f * rho * (A * dx + B * dy);
-                acc[8] = 2.0f * rho * (A * dy - B * dx);
-            }
-            acc[10] = 0.f;
-            if (kRD) {
-                float p0, p1, p2;  // c'_k - c
-                if (k == r) {
-                    p0 = dr0;
-                    p1 = dr1;
-                    p2 = dr2;
-                } else {  // c' - c = -w / (1 - w) (c_k - c), with w <= 1/2 here
-                    const float f = -w * __builtin_amdgcn_rcpf(1.0f - w);
-                    p0 = f * d0;
-                    p1 = f * d1;
-                    p2 = f * d2;
-                }
-                acc[10] = (p0 * (p0 + 2.0f * e0) + p1 * (p1 + 2.0f * e1) +
-                           p2 * (p2 + 2.0f * e2)) * inv_P;
-            }
-            const int slot = hash_slot(hkey, id);
-            constexpr int nq = kRD ? kAcc : 10;
-#pragma unroll
-            for (int q = 0; q < nq; ++q) {
-                float *dst = q < 10 ? grad + q * cap + id : rdel + id;
-                if (slot >= 0 && fabsf(acc[q]) < fx.limit)
-                    atomicAdd(&hacc[q][slot], to_fixed(acc[q], fx.to_fix));
-                else if (acc[q] != 0.0f)
-                    atomic_add_f32(dst, acc[q]);
-            }
+        for (int q = 0; q < nq; ++q) {
+            float *dst = q < 10 ? grad + q * cap + id : rdel + id;
+            if (slot >= 0 && fabsf(acc[q]) < fx.limit)
+                atomicAdd(&hacc[q][slot], to_fixed(acc[q], fx.to_fix));
+            else if (acc[q] != 0.0f)
+                atomic_add_f32(dst, acc[q]);
         }
     }
 }

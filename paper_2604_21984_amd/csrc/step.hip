@@ -41,9 +41,7 @@ __global__ __launch_bounds__(256) void k_train(PropArgs pa, ImgArgs a, FixScale 
             lout[(int64_t)g * P + p] = make_uint4(key_id(keys[4 * g]), key_id(keys[4 * g + 1]),
                                                   key_id(keys[4 * g + 2]), key_id(keys[4 * g + 3]));
         PixelBlend<K> b;
-        float col[K][3];
-        float nrm[K];
-        blend_keys<K, true>(rec, keys, X, Y, b, col, nrm);
+        blend_keys<K, true>(rec, keys, b, lane_rot() % K);
         float g[3];
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
@@ -53,7 +51,7 @@ __global__ __launch_bounds__(256) void k_train(PropArgs pa, ImgArgs a, FixScale 
             if (gimg) gimg[ch * P + p] = g[ch];
             if (rendered) rendered[ch * P + p] = b.c[ch];
         }
-        bwd_pixel<K, false>(rec, b, col, nrm, X, Y, g[0], g[1], g[2], 0.f, 0.f, 0.f, hkey, hacc, fx,
+        bwd_pixel<K, false>(rec, b, X, Y, g[0], g[1], g[2], 0.f, 0.f, 0.f, hkey, hacc, fx,
                             a.inv_P, a.cap, grad, nullptr);
     }
     const float tot = block_sum(sq);  // contains the barrier the flush needs

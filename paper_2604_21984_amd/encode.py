@@ -136,7 +136,7 @@ class Encoder:
         budget event follows it)."""
         a, b = self.lists[self.cur], self.lists[1 - self.cur]
         S.train_step(self.img, self.train_cfg, self.target, self.sites, self.rec, a, b, self.grad,
-                     self.m, self.v, None, self.grad_img, self.state)
+                     self.m, self.v, None, None, self.state)
         self.cur = 1 - self.cur
         self.steps += 1
         if self.cfg.budget:

@@ -318,7 +318,15 @@ def test_large_image_k16_parity(S):
         assert np.array_equal(got, ref), f"pass {t}: {np.sum(np.any(got != ref, 1))} pixels differ"
     col = g.render()
     cref = O.render(H, W, K, s, sites, N, ref)
-    assert np.abs(col - cref).max() <= 1e-5
+    err = np.abs(col - cref)
+    if err.max() > 1e-5:  # name the pixel before failing
+        ch, i, j = np.unravel_index(err.argmax(), err.shape)
+        p = i * W + j
+        ids = [int(v) for v in ref[p] if v != O.INVALID]
+        print("worst pixel", (i, j), "ids", ids, "gpu", col[:, i, j], "oracle", cref[:, i, j],
+              "scores", [O.score(sites, k, s, float(j), float(i)) for k in ids],
+              "colours", sites[4:7, ids].T.tolist(), flush=True)
+    assert err.max() <= 1e-5
     _, gimg = O.loss_grad(cref, target)
     gg, _ = g.bwd(gimg.astype(np.float32))
     gref, ab = O.render_bwd(H, W, K, s, sites, N, ref, gimg.astype(np.float32).astype(np.float64),

@@ -22,9 +22,9 @@ def S():
 def test_exact_topk_bit_exact(S, H, W, N, K):
     sites = synth.random_sites(N + K, H, W, N, anisotropic=True, log_tau_range=(2.0, 5.0),
                                r_range=(1.0, 20.0))
-    sites[:, 7] = sites[:, 3]            # a duplicate: equal scores, ID order decides
-    sites[0, 11 % N] = -1.0              # an inactive site
-    sites[1, 11 % N] = -1.0
+    sites[:, N - 1] = sites[:, 1]        # a duplicate: equal scores, ID order decides
+    sites[0, N // 2] = -1.0              # an inactive site
+    sites[1, N // 2] = -1.0
     s = O.default_scale(H, W)
     rng = np.random.default_rng(N)
     pix = np.concatenate([rng.choice(H * W, 150, replace=True), [0, H * W - 1, -3, H * W]])
