@@ -12,7 +12,8 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libsad.so")
+# SAD_LIBRARY may name another build of the same library (same ABI), e.g. for A/B timing
+LIB_PATH = os.environ.get("SAD_LIBRARY") or os.path.join(_HERE, "libsad.so")
 
 NPARAM = 10
 REC_FLOATS = 16

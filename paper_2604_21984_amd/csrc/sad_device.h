@@ -28,7 +28,11 @@ __device__ __forceinline__ float quad(const float4 q0, const float4 q1, float X,
 //   t = fma(2 G12, dy, G11 dx); q = fma(t, dx, (G22 dy) dy); q = max(q, 0);
 //   n = sqrt(q); l = kappa (r - n) + 0
 // with every operation correctly rounded (explicit _rn intrinsics; the TU is also
-// compiled without contraction).  The trailing "+ 0" maps -0 to +0.
+// compiled without contraction).  The square root is sqrtf, which the compiler expands
+// to the hardware estimate plus an fma test of its two neighbours, i.e. correctly
+// rounded; __fsqrt_rn compiles to the bare estimate (1 ulp) on this target and would
+// let scores drift by an ulp from the reference sequence.  The trailing "+ 0" maps -0
+// to +0.
 __device__ __forceinline__ float score(const float4 q0, const float4 q1, float X, float Y,
                                        float *n_out = nullptr) {
     const float dx = __fsub_rn(X, q0.x);
@@ -36,7 +40,7 @@ __device__ __forceinline__ float score(const float4 q0, const float4 q1, float X
     const float t = __fmaf_rn(q0.w, dy, __fmul_rn(q0.z, dx));
     float q = __fmaf_rn(t, dx, __fmul_rn(__fmul_rn(q1.x, dy), dy));
     q = fmaxf(q, 0.0f);
-    const float n = __fsqrt_rn(q);
+    const float n = sqrtf(q);
     if (n_out) *n_out = n;
     return __fadd_rn(__fmul_rn(q1.y, __fsub_rn(q1.z, n)), 0.0f);
 }

@@ -288,12 +288,14 @@ __device__ __forceinline__ void prop_pixel(const PropArgs &a, const float4 *__re
 
     auto screen = [&](uint32_t id) __attribute__((always_inline)) {
         const bool in_range = id < ns;
-        const uint32_t idc = in_range ? id : 0u;
-        const float4 q0 = rec[4 * (size_t)idc], q1 = rec[4 * (size_t)idc + 1];
         const uint32_t nid = ~id;
         bool kept = false;
 #pragma unroll
         for (int k = 0; k < K; ++k) kept = kept || ((uint32_t)keys[k] == nid);
+        // a kept or out-of-range ID reads record 0: all such lanes of the wave share one
+        // line, so the gather only fetches the records of IDs that are new to the pixel
+        const uint32_t idc = (in_range && !kept) ? id : 0u;
+        const float4 q0 = rec[4 * (size_t)idc], q1 = rec[4 * (size_t)idc + 1];
         const float na = __builtin_amdgcn_sqrtf(quad(q0, q1, X, Y));
         const float la = q1.y * (q1.z - na);
         const float bound = fmaf(q1.y, fabsf(q1.z) + na, fabsf(la)) * 0x1p-19f;
@@ -466,7 +468,7 @@ __device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const 
         const float gam = w * (g0 * d0 + g1 * d1 + g2 * d2);
         acc[2] = gam * b.l[k];
         acc[3] = gam * q1.y;
-        const float n = __fsqrt_rn(quad(q0, q1, X, Y));
+        const float n = sqrtf(quad(q0, q1, X, Y));
         acc[0] = acc[1] = acc[7] = acc[8] = acc[9] = 0.f;
         if (n > 0.f) {
             const float rho = -0.5f * gam * q1.y * __builtin_amdgcn_rcpf(n);
