@@ -27,7 +27,7 @@ __device__ __forceinline__ FixScale fix_scale_dev(int64_t P) {
     int e = 0;
     while ((int64_t)1 << (e + 1) < P) ++e;
     FixScale fx;
-    fx.shift = 40 + e;
+    fx.to_fix = ldexp(1.0, 40 + e);
     fx.from_fix = ldexp(1.0, -(40 + e));
     fx.limit = (float)ldexp(1.0, 15 - e);
     return fx;

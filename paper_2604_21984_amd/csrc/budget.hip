@@ -27,7 +27,7 @@ constexpr int kNStat = SAD_NSTAT;
 // straight to a float global atomic.  The removal delta carries 1/P and uses 2^(40+e),
 // 2^e ~ P / 2, as the backward does.
 struct StatScale {
-    int shift[kNStat];
+    double to[kNStat];
     double from[kNStat];
     float limit[kNStat];
 };
@@ -38,7 +38,7 @@ static StatScale stat_scale(int64_t P) {
     const int ex[kNStat] = {40, 40, 36, 36, 30, 30, 30, 40 + e};
     StatScale sc;
     for (int q = 0; q < kNStat; ++q) {
-        sc.shift[q] = ex[q];
+        sc.to[q] = std::ldexp(1.0, ex[q]);
         sc.from[q] = std::ldexp(1.0, -ex[q]);
         sc.limit[q] = (float)std::ldexp(1.0, 54 - ex[q]);
     }
@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void k_stats(ImgArgs a, StatScale sc,
 #pragma unroll
                 for (int q = 0; q < kNStat; ++q) {
                     if (slot >= 0 && fabsf(v[q]) < sc.limit[q])
-                        atomicAdd(&hacc[q][slot], to_fixed(v[q], sc.shift[q]));
+                        atomicAdd(&hacc[q][slot], to_fixed(v[q], sc.to[q]));
                     else if (v[q] != 0.0f)
                         atomic_add_f32(stats + q * a.cap + id, v[q]);
                 }

@@ -364,22 +364,16 @@ constexpr int kProbes = 8;
 constexpr int kAcc = 11;  // 10 parameters + removal delta
 
 struct FixScale {
-    int shift;         // 40 + e: a term v is added as v 2^shift
+    double to_fix;     // 2^(40 + e)
     double from_fix;   // 2^-(40 + e)
     float limit;       // |v| must be below 2^(15 - e)
 };
 
-// v 2^shift as a two's-complement 64-bit integer, truncated toward zero, assembled from
-// the float's exponent and mantissa with integer shifts (no double arithmetic).  The
-// callers guarantee |v| 2^shift < 2^62; zero and denormal v give 0.
-__device__ __forceinline__ unsigned long long to_fixed(float v, int shift) {
-    const uint32_t b = __float_as_uint(v);
-    const int ex = (int)((b >> 23) & 0xFFu);
-    const unsigned long long m = (unsigned long long)((b & 0x7FFFFFu) | 0x800000u);
-    const int sh = ex - 150 + shift;  // v 2^shift = m 2^sh
-    unsigned long long mag = sh >= 0 ? (m << sh) : (sh > -40 ? (m >> -sh) : 0ull);
-    mag = ex ? mag : 0ull;
-    return (b >> 31) ? (unsigned long long)(-(long long)mag) : mag;
+__device__ __forceinline__ unsigned long long to_fixed(float v, double scale) {
+    const double x = rint((double)v * scale);
+    const double hi = floor(x * 0x1p-32);
+    const double lo = fma(hi, -0x1p32, x);  // exact, in [0, 2^32)
+    return ((unsigned long long)(uint32_t)(int32_t)hi << 32) | (uint32_t)lo;
 }
 
 __device__ __forceinline__ float from_fixed(unsigned long long u, double inv_scale) {
@@ -510,7 +504,7 @@ __device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const 
         for (int q = 0; q < nq; ++q) {
             float *dst = q < 10 ? grad + q * cap + id : rdel + id;
             if (slot >= 0 && fabsf(acc[q]) < fx.limit)
-                atomicAdd(&hacc[q][slot], to_fixed(acc[q], fx.shift));
+                atomicAdd(&hacc[q][slot], to_fixed(acc[q], fx.to_fix));
             else if (acc[q] != 0.0f)
                 atomic_add_f32(dst, acc[q]);
         }
@@ -548,7 +542,7 @@ inline FixScale fix_scale(int64_t P) {
     int e = 0;
     while ((int64_t)1 << (e + 1) < P) ++e;
     FixScale fx;
-    fx.shift = 40 + e;
+    fx.to_fix = std::ldexp(1.0, 40 + e);
     fx.from_fix = std::ldexp(1.0, -(40 + e));
     fx.limit = (float)std::ldexp(1.0, 15 - e);
     return fx;
