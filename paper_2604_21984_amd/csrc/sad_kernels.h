@@ -512,12 +512,13 @@ __device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const 
 }
 
 // Clear the tile table (one slot per thread of a 256-thread block).
+template <int NQ = kAcc>
 __device__ __forceinline__ void bwd_tile_init(uint32_t *__restrict__ hkey,
                                               unsigned long long (*hacc)[kHashSlots]) {
     const int t = threadIdx.x;
     hkey[t] = SAD_INVALID_ID;
 #pragma unroll
-    for (int q = 0; q < kAcc; ++q) hacc[q][t] = 0ull;
+    for (int q = 0; q < NQ; ++q) hacc[q][t] = 0ull;
 }
 
 // Flush the tile table: one float global atomic per occupied (site, parameter).

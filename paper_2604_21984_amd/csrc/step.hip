@@ -23,23 +23,33 @@ __global__ __launch_bounds__(256) void k_train(PropArgs pa, ImgArgs a, FixScale 
                                                float *__restrict__ gimg,
                                                sad_loss_acc *__restrict__ loss,
                                                float *__restrict__ grad) {
-    __shared__ uint32_t queue[QueueDepth<K>::v][256];
+    // The propagation's candidate queue and the backward's accumulators are used in
+    // turn, so they share one LDS buffer (ten 64-bit channels: no removal delta here).
+    constexpr int kQ = QueueDepth<K>::v;
+    constexpr int kWords = (kQ > 20 ? kQ : 20) * 256;
+    static_assert(kWords >= 10 * 2 * kHashSlots, "accumulators must fit");
+    __shared__ __align__(16) uint32_t lds[kWords];
     __shared__ uint32_t hkey[kHashSlots];
-    __shared__ unsigned long long hacc[kAcc][kHashSlots];
-    bwd_tile_init(hkey, hacc);
-    __syncthreads();
+    uint32_t(*queue)[256] = reinterpret_cast<uint32_t(*)[256]>(lds);
+    unsigned long long(*hacc)[kHashSlots] = reinterpret_cast<unsigned long long(*)[kHashSlots]>(lds);
     const int tile = xcd_tile(blockIdx.x, a.n_blocks);
     const TilePix px = tile_pixel(tile, a.tiles_x);
-    float sq = 0.f;
-    if (px.i < a.H && px.j < a.W) {
-        const int64_t P = (int64_t)a.H * a.W, p = (int64_t)px.i * a.W + px.j;
-        const float X = (float)px.j, Y = (float)px.i;
-        uint64_t keys[K];
+    const bool in = px.i < a.H && px.j < a.W;
+    const int64_t P = (int64_t)a.H * a.W, p = (int64_t)px.i * a.W + px.j;
+    uint64_t keys[K];
+    if (in) {
         prop_pixel<K>(pa, rec, lin, px, queue, keys);
 #pragma unroll
         for (int g = 0; g < K / 4; ++g)
             lout[(int64_t)g * P + p] = make_uint4(key_id(keys[4 * g]), key_id(keys[4 * g + 1]),
                                                   key_id(keys[4 * g + 2]), key_id(keys[4 * g + 3]));
+    }
+    __syncthreads();  // the queue is free: clear the accumulators in its place
+    bwd_tile_init<10>(hkey, hacc);
+    __syncthreads();
+    float sq = 0.f;
+    if (in) {
+        const float X = (float)px.j, Y = (float)px.i;
         PixelBlend<K> b;
         blend_keys<K, true>(rec, keys, b, lane_rot() % K);
         float g[3];
