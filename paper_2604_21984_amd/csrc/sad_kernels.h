@@ -451,13 +451,30 @@ __device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const 
             dr2 = -b.c[2];
         }
     }
+    // Entries are visited one at a time from the front of shifting copies of the
+    // per-entry arrays (a rolled loop without dynamic register indexing), which keeps
+    // one entry's records in flight and the register footprint small.
+    uint32_t ids[K];
+    float ls[K], ws[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        if (!b.ok[k]) continue;
-        const uint32_t id = b.id[k];
+        ids[k] = b.ok[k] ? b.id[k] : SAD_INVALID_ID;
+        ls[k] = b.l[k];
+        ws[k] = b.e[k] * invS;
+    }
+#pragma unroll 1
+    for (int k = 0; k < K; ++k) {
+        const uint32_t id = ids[0];
+        const float lk = ls[0], w = ws[0];
+#pragma unroll
+        for (int j = 0; j + 1 < K; ++j) {
+            ids[j] = ids[j + 1];
+            ls[j] = ls[j + 1];
+            ws[j] = ws[j + 1];
+        }
+        if (id == SAD_INVALID_ID) continue;
         const float4 q0 = rec[4 * (size_t)id], q1 = rec[4 * (size_t)id + 1];
         const float4 q2 = rec[4 * (size_t)id + 2], q3 = rec[4 * (size_t)id + 3];
-        const float w = b.e[k] * invS;
         const float d0 = (q2.x - cr0) - dc0;  // c_k - c
         const float d1 = (q2.y - cr1) - dc1;
         const float d2 = (q2.z - cr2) - dc2;
@@ -466,7 +483,7 @@ __device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const 
         acc[5] = w * g1;
         acc[6] = w * g2;
         const float gam = w * (g0 * d0 + g1 * d1 + g2 * d2);
-        acc[2] = gam * b.l[k];
+        acc[2] = gam * lk;
         acc[3] = gam * q1.y;
         const float n = sqrtf(quad(q0, q1, X, Y));
         acc[0] = acc[1] = acc[7] = acc[8] = acc[9] = 0.f;
