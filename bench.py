@@ -325,7 +325,7 @@ def main():
                            enc.state)
         E[1].record(stream)
         S.adam_step(img, enc.sites, enc.grad, enc.m, enc.v, enc.adam, st[1] + it + 1, enc.rec,
-                    zero_grad=True)
+                    zero_grad=True, grad_site_major=True)
         E[2].record(stream)
         enc.cur = 1 - enc.cur
     torch.cuda.synchronize()

@@ -173,8 +173,11 @@ sad_status sad_exact_topk(const sad_image *img, const float *rec, const int64_t 
  * [0, 1] and renormalise u (u = (1, 0) if |u| = 0).  Inactive slots are untouched.  If
  * rec != NULL the derived records of the updated sites are rewritten as by
  * sad_prepare_sites.  With flags & SAD_ADAM_ZERO_GRAD the gradient is cleared after it
- * has been read (the next backward accumulates into zeros).  params: host. */
+ * has been read (the next backward accumulates into zeros); with flags &
+ * SAD_ADAM_GRAD_SITE_MAJOR the gradient is the training step's site-major [cap][10]
+ * accumulator instead of [10][cap].  params: host. */
 #define SAD_ADAM_ZERO_GRAD 1u
+#define SAD_ADAM_GRAD_SITE_MAJOR 2u
 sad_status sad_adam_step(const sad_image *img, float *sites, float *grad, float *m, float *v,
                          const sad_adam_params *params, int64_t step, float *rec, uint32_t flags,
                          void *stream);
@@ -248,7 +251,10 @@ typedef struct {
  *   2. the forward blend of topk_out and the loss gradient dL/dc, written to grad_img
  *      [3][H][W] if grad_img != NULL, the image to rendered [3][H][W] if rendered !=
  *      NULL, L to state->loss.value;
- *   3. the backward scatter into grad_sites [10][cap], which must be zero on entry;
+ *   3. the backward scatter into grad_sites, which must be zero on entry.  This
+ *      accumulator is SITE-MAJOR, float[cap][10] (the ten parameters of site i at
+ *      10*i .. 10*i+9), unlike the [10][cap] of sad_render_bwd: each tile adds the
+ *      ten sums of a site into one cache line;
  *   (1-3 are one kernel: the new keys of a pixel carry the scores its blend needs.)
  *   4. Adam step number state->adam_step + 1 (clamps, renormalised u), rec refreshed,
  *      grad_sites cleared again (ready for the next call);
@@ -263,8 +269,8 @@ sad_status sad_train_step(const sad_image *img, const sad_train_config *cfg, con
 
 /* Steps 1-3 of sad_train_step alone (rows a3-a6 as one kernel): the propagation pass
  * with pass index state->pass (not advanced), the blend, the loss gradient (L added to
- * state->loss.value) and the backward into grad_sites (accumulated, +=).  Same argument
- * meaning as sad_train_step. */
+ * state->loss.value) and the backward into grad_sites (site-major [cap][10],
+ * accumulated, +=).  Same argument meaning as sad_train_step. */
 sad_status sad_train_image_pass(const sad_image *img, const sad_train_config *cfg,
                                 const float *target, const float *rec, const uint32_t *topk_in,
                                 uint32_t *topk_out, float *grad_sites, float *rendered,
@@ -274,8 +280,9 @@ sad_status sad_train_image_pass(const sad_image *img, const sad_train_config *cf
  * Images of uneven size and site budget share pooled buffers.  Image b's blocks start
  * at fixed offsets: pixel pools (target [3][P_b] at 3*px0 floats, each list field
  * [K/4][P_b][4] at K*px0 words, optional rendered / grad_img [3][P_b] at 3*px0 floats)
- * and site pools (sites, grad, m, v [10][cap_b] at 10*site0 floats, derived records
- * [cap_b][16] at 16*site0 floats).  All images use the batch's K. */
+ * and site pools (sites, m, v [10][cap_b] and the site-major gradient [cap_b][10], each
+ * at 10*site0 floats; derived records [cap_b][16] at 16*site0 floats).  All images use
+ * the batch's K. */
 typedef struct {
     int32_t H, W;
     int32_t n_slots;

@@ -232,15 +232,20 @@ def adam_params(lr, beta1=0.9, beta2=0.999, eps=1e-8):
 
 
 ADAM_ZERO_GRAD = 1
+ADAM_GRAD_SITE_MAJOR = 2
 
 
-def adam_step(img, sites, grad, m, v, params, step, rec=None, zero_grad=False):
+def adam_step(img, sites, grad, m, v, params, step, rec=None, zero_grad=False,
+              grad_site_major=False):
+    """sad_adam_step; grad is [10][cap], or the training step's [cap][10] accumulator
+    with grad_site_major=True."""
     n = NPARAM * img.cap
     _check(lib.sad_adam_step(C.byref(img), _ptr(sites, torch.float32, n, "sites"),
                              _ptr(grad, torch.float32, n, "grad"), _ptr(m, torch.float32, n, "m"),
                              _ptr(v, torch.float32, n, "v"), C.byref(params), int(step),
                              _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
-                             ADAM_ZERO_GRAD if zero_grad else 0, _stream()),
+                             (ADAM_ZERO_GRAD if zero_grad else 0) |
+                             (ADAM_GRAD_SITE_MAJOR if grad_site_major else 0), _stream()),
            "sad_adam_step")
 
 

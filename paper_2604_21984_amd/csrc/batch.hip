@@ -40,7 +40,8 @@ struct BatchArgs {
 };
 
 template <int K>
-__global__ __launch_bounds__(256) void k_batch_train(BatchArgs ba, const float4 *__restrict__ rec,
+// (at most 128 VGPRs: four waves per SIMD without spilling)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batch_train(BatchArgs ba, const float4 *__restrict__ rec,
                                                      const uint4 *__restrict__ lin,
                                                      uint4 *__restrict__ lout,
                                                      const float *__restrict__ tgt,
@@ -48,9 +49,14 @@ __global__ __launch_bounds__(256) void k_batch_train(BatchArgs ba, const float4 
                                                      float *__restrict__ gimg,
                                                      sad_step_state *__restrict__ states,
                                                      float *__restrict__ grad) {
-    __shared__ uint32_t queue[QueueDepth<K>::v][256];
+    // candidate queue and accumulators share one LDS buffer (used in turn, as in k_train)
+    constexpr int kQ = QueueDepth<K>::v;
+    constexpr int kWords = (kQ > 20 ? kQ : 20) * 256;
+    __shared__ __align__(16) uint32_t lds[kWords];
     __shared__ uint32_t hkey[kHashSlots];
-    __shared__ unsigned long long hacc[kAcc][kHashSlots];
+    __shared__ uint32_t occ[kHashSlots + 1];
+    uint32_t(*queue)[256] = reinterpret_cast<uint32_t(*)[256]>(lds);
+    unsigned long long(*hacc)[kHashSlots] = reinterpret_cast<unsigned long long(*)[kHashSlots]>(lds);
     const int G = gridDim.x;
     // work assignment: contiguous runs (block -> XCD-local range) or round robin
     int first, step, last;
@@ -66,9 +72,21 @@ __global__ __launch_bounds__(256) void k_batch_train(BatchArgs ba, const float4 
         step = G;
     }
     for (int item = first; item < last; item += step) {
-        const int b = upper_index(ba.n_images, item,
-                                  [&](int k) { return (int64_t)ba.images[k].tile0; });
-        const sad_batch_image im = ba.images[b];
+        // the item, and so the image, is the same for the whole block: keep its
+        // descriptor in scalar registers
+        const int b = __builtin_amdgcn_readfirstlane(
+            upper_index(ba.n_images, item, [&](int k) { return (int64_t)ba.images[k].tile0; }));
+        sad_batch_image im = ba.images[b];
+        im.H = __builtin_amdgcn_readfirstlane(im.H);
+        im.W = __builtin_amdgcn_readfirstlane(im.W);
+        im.n_slots = __builtin_amdgcn_readfirstlane(im.n_slots);
+        im.tile0 = __builtin_amdgcn_readfirstlane(im.tile0);
+        im.cap = ((int64_t)__builtin_amdgcn_readfirstlane((int)(im.cap >> 32)) << 32) |
+                 (uint32_t)__builtin_amdgcn_readfirstlane((int)im.cap);
+        im.px0 = ((int64_t)__builtin_amdgcn_readfirstlane((int)(im.px0 >> 32)) << 32) |
+                 (uint32_t)__builtin_amdgcn_readfirstlane((int)im.px0);
+        im.site0 = ((int64_t)__builtin_amdgcn_readfirstlane((int)(im.site0 >> 32)) << 32) |
+                   (uint32_t)__builtin_amdgcn_readfirstlane((int)im.site0);
         const int tiles_x = (im.W + 15) / 16;
         const TilePix px = tile_pixel(item - im.tile0, tiles_x);
         const int64_t P = (int64_t)im.H * im.W;
@@ -92,19 +110,23 @@ __global__ __launch_bounds__(256) void k_batch_train(BatchArgs ba, const float4 
         const float *tg = tgt + 3 * im.px0;
         float *gr = grad + 10 * im.site0;
 
-        bwd_tile_init(hkey, hacc);
-        __syncthreads();
-        float sq = 0.f;
-        if (im.n_slots > 0 && px.i < im.H && px.j < im.W) {
-            const int64_t p = (int64_t)px.i * im.W + px.j;
-            const float X = (float)px.j, Y = (float)px.i;
-            uint64_t keys[K];
+        const bool live = im.n_slots > 0 && px.i < im.H && px.j < im.W;
+        const int64_t p = (int64_t)px.i * im.W + px.j;
+        uint64_t keys[K];
+        if (live) {
             prop_pixel<K>(pa, r4, li, px, queue, keys);
 #pragma unroll
             for (int g = 0; g < K / 4; ++g)
                 lo[(int64_t)g * P + p] = make_uint4(key_id(keys[4 * g]), key_id(keys[4 * g + 1]),
                                                     key_id(keys[4 * g + 2]),
                                                     key_id(keys[4 * g + 3]));
+        }
+        __syncthreads();  // the queue is free: clear the accumulators in its place
+        bwd_tile_init<10>(hkey, hacc);
+        __syncthreads();
+        float sq = 0.f;
+        if (live) {
+            const float X = (float)px.j, Y = (float)px.i;
             PixelBlend<K> bl;
             blend_keys<K, true>(r4, keys, bl, lane_rot() % K);
             float g[3];
@@ -116,11 +138,10 @@ __global__ __launch_bounds__(256) void k_batch_train(BatchArgs ba, const float4 
                 if (gimg) gimg[3 * im.px0 + ch * P + p] = g[ch];
                 if (rendered) rendered[3 * im.px0 + ch * P + p] = bl.c[ch];
             }
-            bwd_pixel<K, false>(r4, bl, X, Y, g[0], g[1], g[2], 0.f, 0.f, 0.f, hkey, hacc,
+            bwd_pixel<K, false, true>(r4, bl, X, Y, g[0], g[1], g[2], 0.f, 0.f, 0.f, hkey, hacc,
                                 fx, inv_P, im.cap, gr, nullptr);
         } else if (im.n_slots == 0 && px.i < im.H && px.j < im.W) {
             // no sites: empty list, colour 0
-            const int64_t p = (int64_t)px.i * im.W + px.j;
 #pragma unroll
             for (int g = 0; g < K / 4; ++g)
                 lo[(int64_t)g * P + p] = make_uint4(SAD_INVALID_ID, SAD_INVALID_ID, SAD_INVALID_ID,
@@ -136,7 +157,7 @@ __global__ __launch_bounds__(256) void k_batch_train(BatchArgs ba, const float4 
         const float tot = block_sum(sq);  // includes a barrier
         if (threadIdx.x == 0)
             atomic_add_f32(&states[b].loss.part[item % SAD_LOSS_PARTS], tot * inv_P);
-        bwd_flush<false>(hkey, hacc, fx, im.cap, gr, nullptr);
+        bwd_flush<false, true>(hkey, hacc, fx, im.cap, gr, nullptr, occ);
         __syncthreads();  // the next item re-initialises the table
     }
 }
@@ -244,6 +265,7 @@ extern "C" sad_status sad_batch_train_step(const sad_batch *batch, const sad_tra
     A.eps = cfg->adam.eps;
     A.c1 = A.c2 = 1.0f;  // formed on the device from each image's step
     A.zero_grad = 1;
+    A.grad_site_major = 1;
     if (batch->n_site_slots > 0)
         hipLaunchKernelGGL(k_batch_adam, dim3((unsigned)((batch->n_site_slots + 255) / 256)),
                            dim3(256), 0, st, batch->n_images, batch->images, batch->n_site_slots,

@@ -89,6 +89,7 @@ __global__ __launch_bounds__(256) void k_bwd(ImgArgs a, FixScale fx, const float
                                              const float *__restrict__ tgt,
                                              float *__restrict__ grad, float *__restrict__ rdel) {
     __shared__ uint32_t hkey[kHashSlots];
+    __shared__ uint32_t occ[kHashSlots + 1];
     __shared__ unsigned long long hacc[kAcc][kHashSlots];
     bwd_tile_init(hkey, hacc);
     __syncthreads();
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(256) void k_bwd(ImgArgs a, FixScale fx, const float
                           hkey, hacc, fx, a.inv_P, a.cap, grad, rdel);
     }
     __syncthreads();
-    bwd_flush<kRD>(hkey, hacc, fx, a.cap, grad, rdel);
+    bwd_flush<kRD>(hkey, hacc, fx, a.cap, grad, rdel, occ);
 }
 
 // ---- point queries ----------------------------------------------------------------

@@ -363,6 +363,15 @@ constexpr int kHashSlots = 256;
 constexpr int kProbes = 8;
 constexpr int kAcc = 11;  // 10 parameters + removal delta
 
+// Address of gradient element (parameter q, site id): parameter-major [10][cap] (the
+// layout of sad_render_bwd's output) or site-major [cap][10] (the training step's own
+// accumulator: the ten sums of one site share a cache line, so the flush's atomics of a
+// (tile, site) pair coalesce into one or two line requests).
+template <bool kSiteMajor>
+__device__ __forceinline__ float *grad_at(float *grad, int q, uint32_t id, int64_t cap) {
+    return kSiteMajor ? grad + (int64_t)id * SAD_NPARAM + q : grad + q * cap + id;
+}
+
 struct FixScale {
     double to_fix;     // 2^(40 + e)
     double from_fix;   // 2^-(40 + e)
@@ -403,7 +412,7 @@ __device__ __forceinline__ int hash_slot(uint32_t *__restrict__ hkey, uint32_t i
 // With kRD also the removal delta against the target colour (I0, I1, I2).  Each
 // entry's record is gathered again here (colour, metric, direction) rather than kept
 // in registers from the blend.
-template <int K, bool kRD>
+template <int K, bool kRD, bool kSiteMajor = false>
 __device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const PixelBlend<K> &b,
                                           float X, float Y, float g0, float g1, float g2,
                                           float I0, float I1, float I2,
@@ -519,7 +528,7 @@ __device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const 
         constexpr int nq = kRD ? kAcc : 10;
 #pragma unroll
         for (int q = 0; q < nq; ++q) {
-            float *dst = q < 10 ? grad + q * cap + id : rdel + id;
+            float *dst = q < 10 ? grad_at<kSiteMajor>(grad, q, id, cap) : rdel + id;
             if (slot >= 0 && fabsf(acc[q]) < fx.limit)
                 atomicAdd(&hacc[q][slot], to_fixed(acc[q], fx.to_fix));
             else if (acc[q] != 0.0f)
@@ -538,20 +547,34 @@ __device__ __forceinline__ void bwd_tile_init(uint32_t *__restrict__ hkey,
     for (int q = 0; q < NQ; ++q) hacc[q][t] = 0ull;
 }
 
-// Flush the tile table: one float global atomic per occupied (site, parameter).
-template <bool kRD>
+// Flush the tile table: one float global atomic per occupied (site, parameter).  The
+// occupied slots are first listed compactly; thread i then takes (slot i / nq, parameter
+// i % nq), so that consecutive lanes add into consecutive parameters of one site (one
+// cache line in the site-major layout).  Every thread of the block must call it.
+// occ: LDS scratch of kHashSlots + 1 words (the list and its length).
+template <bool kRD, bool kSiteMajor = false>
 __device__ __forceinline__ void bwd_flush(const uint32_t *__restrict__ hkey,
                                           unsigned long long (*hacc)[kHashSlots],
                                           const FixScale &fx, int64_t cap,
-                                          float *__restrict__ grad, float *__restrict__ rdel) {
+                                          float *__restrict__ grad, float *__restrict__ rdel,
+                                          uint32_t *__restrict__ occ) {
     const int t = threadIdx.x;
-    const uint32_t id = hkey[t];
-    if (id == SAD_INVALID_ID) return;
+    uint32_t &n_occ = occ[kHashSlots];
+    if (t == 0) n_occ = 0;
+    __syncthreads();
+    if (hkey[t] != SAD_INVALID_ID) occ[atomicAdd(&n_occ, 1u)] = (uint32_t)t;
+    __syncthreads();
     constexpr int nq = kRD ? kAcc : 10;
-#pragma unroll
-    for (int q = 0; q < nq; ++q) {
-        const unsigned long long u = hacc[q][t];
-        if (u) atomic_add_f32(q < 10 ? grad + q * cap + id : rdel + id, from_fixed(u, fx.from_fix));
+    const int n = (int)n_occ * nq;
+    for (int i = t; i < n; i += kHashSlots) {
+        const int j = i / nq, q = i - j * nq;
+        const int sl = occ[j];
+        const uint32_t id = hkey[sl];
+        const unsigned long long u = hacc[q][sl];
+        if (!u) continue;
+        float *dst = (kRD && q == 10) ? rdel + id
+                     : (kSiteMajor ? grad + (int64_t)id * SAD_NPARAM + q : grad + q * cap + id);
+        atomic_add_f32(dst, from_fixed(u, fx.from_fix));
     }
 }
 

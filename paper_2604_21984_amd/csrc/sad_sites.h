@@ -54,19 +54,23 @@ struct AdamArgs {
     float lr[SAD_NPARAM];
     float b1, b2, eps, c1, c2;  // c1 = 1 - b1^t, c2 = 1 - b2^t (host step)
     int zero_grad;              // clear the gradient after reading it
+    int grad_site_major;        // gradient [cap][10] (training step) instead of [10][cap]
 };
 
 // Adam on slot i of one image's [10][cap] buffers (site order of App. B.2), then clamps
-// and renormalised u; inactive slots are left untouched.  step_dev, if set, holds the
-// number of steps taken so far.
+// and renormalised u; inactive slots are left untouched.  The gradient is [10][cap] or,
+// with A.grad_site_major, [cap][10].  step_dev, if set, holds the number of steps taken
+// so far.
 __device__ __forceinline__ void adam_site(float *__restrict__ sites, float *__restrict__ grad,
                                           float *__restrict__ m, float *__restrict__ v,
                                           int64_t cap, int64_t i, int H, int W, const AdamArgs &A,
                                           const int64_t *step_dev, float s,
                                           float4 *__restrict__ rec) {
+    const int64_t gs = A.grad_site_major ? 1 : cap;             // parameter stride
+    const int64_t g0 = A.grad_site_major ? i * SAD_NPARAM : i;  // first element of site i
     if (!(sites[i] >= 0.0f)) {  // inactive slot: parameters untouched
         if (A.zero_grad)
-            for (int p = 0; p < SAD_NPARAM; ++p) grad[p * cap + i] = 0.0f;
+            for (int p = 0; p < SAD_NPARAM; ++p) grad[g0 + p * gs] = 0.0f;
         if (rec) write_record(sites, cap, i, s, rec);
         return;
     }
@@ -83,8 +87,8 @@ __device__ __forceinline__ void adam_site(float *__restrict__ sites, float *__re
 #pragma unroll
     for (int p = 0; p < SAD_NPARAM; ++p) {
         const int64_t o = p * cap + i;
-        const float g = grad[o];
-        if (A.zero_grad) grad[o] = 0.0f;
+        const float g = grad[g0 + p * gs];
+        if (A.zero_grad) grad[g0 + p * gs] = 0.0f;
         const float mm = A.b1 * m[o] + (1.0f - A.b1) * g;
         const float vv = A.b2 * v[o] + (1.0f - A.b2) * g * g;
         m[o] = mm;

@@ -30,6 +30,7 @@ __global__ __launch_bounds__(256) void k_train(PropArgs pa, ImgArgs a, FixScale 
     static_assert(kWords >= 10 * 2 * kHashSlots, "accumulators must fit");
     __shared__ __align__(16) uint32_t lds[kWords];
     __shared__ uint32_t hkey[kHashSlots];
+    __shared__ uint32_t occ[kHashSlots + 1];
     uint32_t(*queue)[256] = reinterpret_cast<uint32_t(*)[256]>(lds);
     unsigned long long(*hacc)[kHashSlots] = reinterpret_cast<unsigned long long(*)[kHashSlots]>(lds);
     const int tile = xcd_tile(blockIdx.x, a.n_blocks);
@@ -61,12 +62,12 @@ __global__ __launch_bounds__(256) void k_train(PropArgs pa, ImgArgs a, FixScale 
             if (gimg) gimg[ch * P + p] = g[ch];
             if (rendered) rendered[ch * P + p] = b.c[ch];
         }
-        bwd_pixel<K, false>(rec, b, X, Y, g[0], g[1], g[2], 0.f, 0.f, 0.f, hkey, hacc, fx,
+        bwd_pixel<K, false, true>(rec, b, X, Y, g[0], g[1], g[2], 0.f, 0.f, 0.f, hkey, hacc, fx,
                             a.inv_P, a.cap, grad, nullptr);
     }
     const float tot = block_sum(sq);  // contains the barrier the flush needs
     if (threadIdx.x == 0) atomic_add_f32(&loss->part[blockIdx.x % SAD_LOSS_PARTS], tot * a.inv_P);
-    bwd_flush<false>(hkey, hacc, fx, a.cap, grad, nullptr);
+    bwd_flush<false, true>(hkey, hacc, fx, a.cap, grad, nullptr, occ);
 }
 
 __global__ void k_state_advance(sad_step_state *__restrict__ s) {
@@ -172,7 +173,7 @@ extern "C" sad_status sad_train_step(const sad_image *img, const sad_train_confi
     SAD_TRY(image_pass(img, cfg, target, rec, topk_in, topk_out, grad_sites, rendered, grad_img,
                        state, true, st));
     launch_adam(img, s, sites, grad_sites, adam_m, adam_v, &cfg->adam, 1, &state->adam_step, rec,
-                true, st);
+                true, true, st);
     hipLaunchKernelGGL(k_state_advance, dim3(1), dim3(64), 0, st, state);
     return check_launch("sad_train_step");
 }

@@ -93,7 +93,7 @@ class Encoder:
         self.lists = [torch.empty((cfg.K // 4, H, W, 4), dtype=torch.int32, device=dev)
                       for _ in range(2)]
         self.cur = 0
-        self.grad = torch.zeros((S.NPARAM, cap), **f32)
+        self.grad = torch.zeros((cap, S.NPARAM), **f32)  # site-major accumulator
         self.m = torch.zeros((S.NPARAM, cap), **f32)
         self.v = torch.zeros((S.NPARAM, cap), **f32)
         self.rendered = torch.empty((3, H, W), **f32)
