@@ -162,3 +162,35 @@ def test_encoder_budget_schedule(S):
     ids = lists[lists != 0xFFFFFFFF]
     assert active[ids].all()                             # lists hold active sites only
     assert enc.psnr() > p0 + 3.0
+
+
+def test_densify_prune_large_image_scale(S):
+    """2048x2048, N = 100 000 from the initialisation in a 400 000-slot buffer, K = 16:
+    statistics within the float32 bound on the oracle's lists, then one prune + split
+    + seed step against the oracle on the oracle's statistics."""
+    import math
+    H = W = 2048
+    N, cap, K = 100_000, 400_000, 16
+    tg = synth.image_large(1, H, W)
+    s = O.default_scale(H, W)
+    lt0 = float(np.clip(math.log(2 * max(H, W) / math.sqrt(H * W / N)), 2, 20))
+    sites, n = O.init_sites(tg, N, 0.3, 5, lt0, 1.0, cap)
+    lists = O.seed_lists(H, W, K, s, sites, N)
+    lists = O.prop_pass(H, W, K, s, sites, N, lists, O.jump(0, H, W), 4, 3, 0)
+    ref, sabs, sens = O.site_stats(H, W, K, s, sites, N, lists, tg, scales=True)
+    got = _gpu_stats(S, H, W, K, N, cap, sites, lists, tg)
+    floor = 1e-7 * np.abs(ref).max(axis=1, keepdims=True)
+    tol = 1e-4 * np.abs(ref) + 2e-5 * sabs + 1e-5 * sens + floor
+    assert not (np.abs(got - ref) > tol).any()
+    stats = ref.astype(np.float32)
+    rs = sites.copy()
+    am = np.full((10, cap), 3.0, np.float32)
+    av = np.full((10, cap), 5.0, np.float32)
+    rl = lists.copy()
+    rc = O.densify_prune(tg, rs, stats, 0.033, 0.01, 7, K=K, adam_m=am, adam_v=av, lists=rl)
+    gs, gm, gv, gc, gl = _run_dp(S, H, W, K, sites, tg, stats, 0.033, 0.01, 7, lists=lists)
+    assert gc == rc and rc[1] == 3300 and rc[2] == 1000
+    _compare_sites(gs, rs)
+    np.testing.assert_array_equal(gm, am)
+    np.testing.assert_array_equal(gv, av)
+    np.testing.assert_array_equal(gl, rl)
