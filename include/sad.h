@@ -230,6 +230,8 @@ typedef struct {
     int64_t pass;      /* refresh counter t: jump s_t (Sec. 4.3) and injection stream */
     int64_t adam_step; /* Adam steps taken so far */
     sad_loss_acc loss; /* loss.value = L of the last step */
+    uint64_t done;     /* blocks of the step's last kernel that have finished (the last
+                          one folds the loss and advances the counters, then resets it) */
 } sad_step_state;
 
 typedef struct {

@@ -19,7 +19,7 @@ NPARAM = 10
 REC_FLOATS = 16
 LOSS_PARTS = 64
 LOSS_ACC_FLOATS = 1 + LOSS_PARTS          # sad_loss_acc
-STEP_STATE_INT64 = (16 + 4 * LOSS_ACC_FLOATS + 7) // 8   # sad_step_state, 8-byte aligned
+STEP_STATE_INT64 = (16 + 4 * LOSS_ACC_FLOATS + 7) // 8 + 1   # sad_step_state (+ block counter)
 INVALID_ID = 0xFFFFFFFF
 MAX_K = 32
 

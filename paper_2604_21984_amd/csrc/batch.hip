@@ -171,14 +171,13 @@ __global__ __launch_bounds__(64) void k_batch_loss_fold(sad_step_state *__restri
     if (i == 0) loss->value = v;
 }
 
-__global__ __launch_bounds__(256) void k_batch_adam(int n_images, const sad_batch_image *__restrict__ imgs,
-                                                    int64_t n_slots_total, float *__restrict__ sites,
-                                                    float *__restrict__ grad, float *__restrict__ m,
-                                                    float *__restrict__ v, float4 *__restrict__ rec,
-                                                    const sad_step_state *__restrict__ states,
-                                                    AdamArgs A) {
-    const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gi >= n_slots_total) return;
+__device__ __forceinline__ void batch_adam_slot(int n_images,
+                                                const sad_batch_image *__restrict__ imgs,
+                                                int64_t gi, float *__restrict__ sites,
+                                                float *__restrict__ grad, float *__restrict__ m,
+                                                float *__restrict__ v, float4 *__restrict__ rec,
+                                                const sad_step_state *__restrict__ states,
+                                                const AdamArgs &A) {
     const int b = upper_index(n_images, gi, [&](int k) { return imgs[k].site0; });
     const sad_batch_image im = imgs[b];
     const int64_t i = gi - im.site0;
@@ -188,6 +187,19 @@ __global__ __launch_bounds__(256) void k_batch_adam(int n_images, const sad_batc
     const int64_t o = 10 * im.site0;
     adam_site(sites + o, grad + o, m + o, v + o, im.cap, i, im.H, im.W, A, &states[b].adam_step, s,
               rec + 4 * im.site0);
+}
+
+// Adam over every site slot of the batch; the last block folds every image's loss and
+// advances every image's counters.
+__global__ __launch_bounds__(256) void k_batch_adam(int n_images, const sad_batch_image *__restrict__ imgs,
+                                                    int64_t n_slots_total, float *__restrict__ sites,
+                                                    float *__restrict__ grad, float *__restrict__ m,
+                                                    float *__restrict__ v, float4 *__restrict__ rec,
+                                                    sad_step_state *__restrict__ states,
+                                                    AdamArgs A) {
+    const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi < n_slots_total) batch_adam_slot(n_images, imgs, gi, sites, grad, m, v, rec, states, A);
+    finish_iteration(states, n_images);
 }
 
 __global__ __launch_bounds__(256) void k_batch_advance(sad_step_state *__restrict__ states, int n) {
@@ -257,7 +269,6 @@ extern "C" sad_status sad_batch_train_step(const sad_batch *batch, const sad_tra
         default: break;
     }
 #undef SAD_BATCH_CASE
-    hipLaunchKernelGGL(k_batch_loss_fold, dim3(batch->n_images), dim3(64), 0, st, states);
     AdamArgs A;
     for (int p = 0; p < SAD_NPARAM; ++p) A.lr[p] = cfg->adam.lr[p];
     A.b1 = cfg->adam.beta1;
@@ -266,12 +277,15 @@ extern "C" sad_status sad_batch_train_step(const sad_batch *batch, const sad_tra
     A.c1 = A.c2 = 1.0f;  // formed on the device from each image's step
     A.zero_grad = 1;
     A.grad_site_major = 1;
-    if (batch->n_site_slots > 0)
+    if (batch->n_site_slots > 0) {  // the last Adam block folds the losses, advances the counters
         hipLaunchKernelGGL(k_batch_adam, dim3((unsigned)((batch->n_site_slots + 255) / 256)),
                            dim3(256), 0, st, batch->n_images, batch->images, batch->n_site_slots,
                            sites, grad_sites, adam_m, adam_v, reinterpret_cast<float4 *>(rec),
                            states, A);
-    hipLaunchKernelGGL(k_batch_advance, dim3((batch->n_images + 255) / 256), dim3(256), 0, st,
-                       states, batch->n_images);
+    } else {
+        hipLaunchKernelGGL(k_batch_loss_fold, dim3(batch->n_images), dim3(64), 0, st, states);
+        hipLaunchKernelGGL(k_batch_advance, dim3((batch->n_images + 255) / 256), dim3(256), 0, st,
+                           states, batch->n_images);
+    }
     return check_launch("sad_batch_train_step");
 }

@@ -29,9 +29,11 @@ void launch_bwd(const sad_image *img, const float *rec, const uint32_t *topk, co
 // Adam; if step_dev != NULL the step is *step_dev + 1 (device), else `step`.  If
 // zero_grad, the gradient is cleared after it has been read (ready for the next step).
 // The gradient is [10][cap], or [cap][10] with grad_site_major (the training step's).
+// If fin != NULL the last block also folds fin's loss partials and advances its
+// counters (the end of a training iteration).  Nothing is launched if n_slots == 0.
 void launch_adam(const sad_image *img, float s, float *sites, float *grad, float *m, float *v,
                  const sad_adam_params *p, int64_t step, const int64_t *step_dev, float *rec,
-                 bool zero_grad, bool grad_site_major, hipStream_t st);
+                 bool zero_grad, bool grad_site_major, sad_step_state *fin, hipStream_t st);
 void launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
 
 // Radix select over unsigned 64-bit codes (8 passes of 8 bits, most significant

@@ -49,6 +49,38 @@ __device__ __forceinline__ void write_record(const float *__restrict__ sites, in
     rec[4 * i + 3] = q3;
 }
 
+// ---- end of a training iteration ---------------------------------------------------
+// Called by every thread of every block of the iteration's last kernel after its own
+// work: the last block to arrive folds the loss partials of each state in st[0..n)
+// into its value (written), clears them and advances pass and adam_step; the block
+// counter lives in st[0].done and is reset by that block, so the kernel can be replayed
+// from a graph.  Every block reads the counters before it arrives here.
+__device__ __forceinline__ void finish_iteration(sad_step_state *__restrict__ st, int n) {
+    __shared__ int last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        last = atomicAdd(reinterpret_cast<unsigned long long *>(&st[0].done), 1ull) ==
+               (unsigned long long)(gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int b = w; b < n; b += blockDim.x >> 6) {  // one wave per state
+        sad_loss_acc *loss = &st[b].loss;
+        float v = lane < SAD_LOSS_PARTS ? loss->part[lane] : 0.f;
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane < SAD_LOSS_PARTS) loss->part[lane] = 0.f;
+        if (lane == 0) {
+            loss->value = v;
+            st[b].pass += 1;
+            st[b].adam_step += 1;
+        }
+    }
+    if (threadIdx.x == 0) st[0].done = 0ull;
+}
+
 // ---- Adam (Sec. 5; clamps of Sec. 6.1) ----------------------------------------------
 struct AdamArgs {
     float lr[SAD_NPARAM];

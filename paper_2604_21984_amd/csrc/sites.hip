@@ -80,10 +80,11 @@ __global__ __launch_bounds__(256) void k_adam(float *__restrict__ sites,
                                               float *__restrict__ m, float *__restrict__ v,
                                               int64_t cap, int n, int H, int W, AdamArgs A,
                                               const int64_t *step_dev, float s,
-                                              float4 *__restrict__ rec) {
+                                              float4 *__restrict__ rec,
+                                              sad_step_state *__restrict__ fin) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    adam_site(sites, grad, m, v, cap, i, H, W, A, step_dev, s, rec);
+    if (i < n) adam_site(sites, grad, m, v, cap, i, H, W, A, step_dev, s, rec);
+    if (fin) finish_iteration(fin, 1);
 }
 
 }  // namespace sad
@@ -135,7 +136,7 @@ extern "C" sad_status sad_seed_topk(const sad_image *img, const float *rec, uint
 void sad::launch_adam(const sad_image *img, float s, float *sites, float *grad, float *m,
                       float *v, const sad_adam_params *params, int64_t step,
                       const int64_t *step_dev, float *rec, bool zero_grad, bool grad_site_major,
-                      hipStream_t st) {
+                      sad_step_state *fin, hipStream_t st) {
     if (img->n_slots == 0) return;
     AdamArgs A;
     for (int p = 0; p < SAD_NPARAM; ++p) A.lr[p] = params->lr[p];
@@ -148,7 +149,7 @@ void sad::launch_adam(const sad_image *img, float s, float *sites, float *grad, 
     A.grad_site_major = grad_site_major ? 1 : 0;
     const int n = img->n_slots;
     hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, st, sites, grad, m, v, img->cap,
-                       n, img->H, img->W, A, step_dev, s, reinterpret_cast<float4 *>(rec));
+                       n, img->H, img->W, A, step_dev, s, reinterpret_cast<float4 *>(rec), fin);
 }
 
 extern "C" sad_status sad_adam_step(const sad_image *img, float *sites, float *grad, float *m,
@@ -166,6 +167,6 @@ extern "C" sad_status sad_adam_step(const sad_image *img, float *sites, float *g
                 "sad_adam_step: unknown flags 0x%x", flags);
     launch_adam(img, s, sites, grad, m, v, params, step, nullptr, rec,
                 (flags & SAD_ADAM_ZERO_GRAD) != 0, (flags & SAD_ADAM_GRAD_SITE_MAJOR) != 0,
-                as_stream(stream));
+                nullptr, as_stream(stream));
     return check_launch("sad_adam_step");
 }

@@ -85,7 +85,7 @@ static sad_status image_pass(const sad_image *img, const sad_train_config *cfg,
                              const float *target, const float *rec, const uint32_t *topk_in,
                              uint32_t *topk_out, float *grad_sites, float *rendered,
                              float *grad_img, sad_step_state *state, bool overwrite_loss,
-                             hipStream_t st) {
+                             bool fold, hipStream_t st) {
     SAD_TRY(check_image(img, nullptr));
     SAD_REQUIRE(cfg && state, SAD_ERR_INVALID_ARGUMENT, "training pass: cfg / state is NULL");
     SAD_REQUIRE(target && rec && topk_in && topk_out && grad_sites, SAD_ERR_INVALID_ARGUMENT,
@@ -148,7 +148,7 @@ static sad_status image_pass(const sad_image *img, const sad_train_config *cfg,
         default: break;
     }
 #undef SAD_TRAIN_CASE
-    launch_loss_fold(&state->loss, overwrite_loss, st);
+    if (fold) launch_loss_fold(&state->loss, overwrite_loss, st);
     return check_launch("training pass");
 }
 
@@ -158,7 +158,7 @@ extern "C" sad_status sad_train_image_pass(const sad_image *img, const sad_train
                                            float *grad_sites, float *rendered, float *grad_img,
                                            sad_step_state *state, void *stream) {
     return image_pass(img, cfg, target, rec, topk_in, topk_out, grad_sites, rendered, grad_img,
-                      state, false, as_stream(stream));
+                      state, false, true, as_stream(stream));
 }
 
 extern "C" sad_status sad_train_step(const sad_image *img, const sad_train_config *cfg,
@@ -170,10 +170,17 @@ extern "C" sad_status sad_train_step(const sad_image *img, const sad_train_confi
     SAD_TRY(check_image(img, &s));
     SAD_REQUIRE(sites && adam_m && adam_v, SAD_ERR_INVALID_ARGUMENT, "sad_train_step: NULL pointer");
     hipStream_t st = as_stream(stream);
+    if (img->n_slots == 0) {  // nothing to optimise: fold the loss, advance the counters
+        SAD_TRY(image_pass(img, cfg, target, rec, topk_in, topk_out, grad_sites, rendered,
+                           grad_img, state, true, true, st));
+        hipLaunchKernelGGL(k_state_advance, dim3(1), dim3(64), 0, st, state);
+        return check_launch("sad_train_step");
+    }
+    // the image pass leaves its loss partials; the last Adam block folds them and
+    // advances the counters (two kernels per iteration)
     SAD_TRY(image_pass(img, cfg, target, rec, topk_in, topk_out, grad_sites, rendered, grad_img,
-                       state, true, st));
+                       state, true, false, st));
     launch_adam(img, s, sites, grad_sites, adam_m, adam_v, &cfg->adam, 1, &state->adam_step, rec,
-                true, true, st);
-    hipLaunchKernelGGL(k_state_advance, dim3(1), dim3(64), 0, st, state);
+                true, true, state, st);
     return check_launch("sad_train_step");
 }
