@@ -2,8 +2,8 @@
 
 One step = one training iteration of the 768x512 encode workload (N = 20 000 sites,
 K = 8, J = 4): propagation pass + forward blend + loss gradient + backward scatter +
-Adam, i.e. one ``sad_train_step``.  Steps run as replays of a recorded HIP graph (two
-iterations per graph; all counters live on the device).  Inputs are resident in HBM
+Adam, i.e. one ``sad_train_step``.  Steps run as replays of a recorded HIP graph (up to
+ten iterations per graph; all counters live on the device).  Inputs are resident in HBM
 before the timed region.  Prints ONE JSON line.
 
     python bench.py [--steps 100] [--warmup 10] [--gpus 1]
@@ -28,9 +28,9 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources they were taken with: HBM bytes per launch from FETCH_SIZE + WRITE_SIZE
 # scaled by a copy kernel's readings, and the utilisation counters.
 PROFILED = {
-    "8fd21a7ca3483b78": {"traffic_bytes": 44940317,
-                         "counters": {"VALUBusy_pct": 51.0, "LDSBankConflict_pct": 14.1,
-                                      "OccupancyPercent": 52.0, "MemUnitStalled_pct": 0.06}},
+    "5b07f3174214c80f": {"traffic_bytes": 44942194,
+                         "counters": {"VALUBusy_pct": 51.5, "LDSBankConflict_pct": 14.5,
+                                      "OccupancyPercent": 52.5, "MemUnitStalled_pct": 0.07}},
 }
 
 
@@ -304,13 +304,16 @@ def main():
     if enc.cur == 1:
         enc.step()
     torch.cuda.synchronize()
-    enc.capture()
-    enc.replay(2)
+    # one graph holds up to ten iterations (the list field ping-pongs, so an even number)
+    gpairs = max(1, min(5, args.steps // 2))
+    enc.capture(gpairs)
+    enc.replay(1)
     torch.cuda.synchronize()
 
-    # ---- timed region: K iterations = K/2 graph replays -----------------------------
-    pairs = max(1, (args.steps + 1) // 2)
-    steps = 2 * pairs
+    # ---- timed region: K iterations rounded up to whole graphs --------------------------
+    per_graph = 2 * gpairs
+    pairs = max(1, -(-args.steps // per_graph))  # graph replays
+    steps = per_graph * pairs
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()

@@ -189,17 +189,17 @@ __device__ __forceinline__ void batch_adam_slot(int n_images,
               rec + 4 * im.site0);
 }
 
-// Adam over every site slot of the batch; the last block folds every image's loss and
-// advances every image's counters.
+// Adam over every site slot of the batch.  (The loss fold and the counter update stay
+// separate one-block kernels here: a finishing block would need one same-address atomic
+// per Adam block, thousands for a large batch.)
 __global__ __launch_bounds__(256) void k_batch_adam(int n_images, const sad_batch_image *__restrict__ imgs,
                                                     int64_t n_slots_total, float *__restrict__ sites,
                                                     float *__restrict__ grad, float *__restrict__ m,
                                                     float *__restrict__ v, float4 *__restrict__ rec,
-                                                    sad_step_state *__restrict__ states,
+                                                    const sad_step_state *__restrict__ states,
                                                     AdamArgs A) {
     const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gi < n_slots_total) batch_adam_slot(n_images, imgs, gi, sites, grad, m, v, rec, states, A);
-    finish_iteration(states, n_images);
 }
 
 __global__ __launch_bounds__(256) void k_batch_advance(sad_step_state *__restrict__ states, int n) {
@@ -277,15 +277,13 @@ extern "C" sad_status sad_batch_train_step(const sad_batch *batch, const sad_tra
     A.c1 = A.c2 = 1.0f;  // formed on the device from each image's step
     A.zero_grad = 1;
     A.grad_site_major = 1;
-    if (batch->n_site_slots > 0) {  // the last Adam block folds the losses, advances the counters
+    hipLaunchKernelGGL(k_batch_loss_fold, dim3(batch->n_images), dim3(64), 0, st, states);
+    if (batch->n_site_slots > 0)
         hipLaunchKernelGGL(k_batch_adam, dim3((unsigned)((batch->n_site_slots + 255) / 256)),
                            dim3(256), 0, st, batch->n_images, batch->images, batch->n_site_slots,
                            sites, grad_sites, adam_m, adam_v, reinterpret_cast<float4 *>(rec),
                            states, A);
-    } else {
-        hipLaunchKernelGGL(k_batch_loss_fold, dim3(batch->n_images), dim3(64), 0, st, states);
-        hipLaunchKernelGGL(k_batch_advance, dim3((batch->n_images + 255) / 256), dim3(256), 0, st,
-                           states, batch->n_images);
-    }
+    hipLaunchKernelGGL(k_batch_advance, dim3((batch->n_images + 255) / 256), dim3(256), 0, st,
+                       states, batch->n_images);
     return check_launch("sad_batch_train_step");
 }

@@ -162,22 +162,25 @@ class Encoder:
                                 "counts": c})
         self.graph = None  # a recorded graph holds the old slot range
 
-    def capture(self):
-        """Record two iterations (A -> B -> A) as one HIP graph."""
+    def capture(self, pairs=1):
+        """Record 2 * pairs iterations (the list field ping-pongs A -> B -> A) as one HIP
+        graph; more pairs per graph amortise the graph launch."""
         assert self.cur == 0, "capture from the first list buffer"
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            self.step()
-            self.step()
-        self.steps -= 2  # recording does not execute
+            for _ in range(2 * pairs):
+                self.step()
+        self.steps -= 2 * pairs  # recording does not execute
         self.graph = g
+        self.graph_steps = 2 * pairs
         return g
 
-    def replay(self, pairs=1):
-        for _ in range(pairs):
+    def replay(self, n=1):
+        """Replay the recorded graph n times."""
+        for _ in range(n):
             self.graph.replay()
-        self.steps += 2 * pairs
+        self.steps += self.graph_steps * n
 
     def render(self, out=None):
         out = out if out is not None else torch.empty((3, self.H, self.W), dtype=torch.float32,
