@@ -39,26 +39,127 @@ struct BatchArgs {
     const sad_batch_image *images;
 };
 
+// One (image, tile) work item: propagate, render, loss gradient and backward of its 256
+// pixels, flushed into the image's site-major gradient.  The queue and the accumulators
+// share one LDS buffer (used in turn, as in the single-image training kernel).
 template <int K>
-// (at most 128 VGPRs: four waves per SIMD without spilling)
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batch_train(BatchArgs ba, const float4 *__restrict__ rec,
-                                                     const uint4 *__restrict__ lin,
-                                                     uint4 *__restrict__ lout,
-                                                     const float *__restrict__ tgt,
-                                                     float *__restrict__ rendered,
-                                                     float *__restrict__ gimg,
-                                                     sad_step_state *__restrict__ states,
-                                                     float *__restrict__ grad) {
-    // candidate queue and accumulators share one LDS buffer (used in turn, as in k_train)
-    constexpr int kQ = QueueDepth<K>::v;
-    constexpr int kWords = (kQ > 20 ? kQ : 20) * 256;
-    __shared__ __align__(16) uint32_t lds[kWords];
-    __shared__ uint32_t hkey[kHashSlots];
-    __shared__ uint32_t occ[kHashSlots + 1];
+__device__ __forceinline__ void batch_item(const BatchArgs &ba, int item,
+                                           const float4 *__restrict__ rec,
+                                           const uint4 *__restrict__ lin,
+                                           uint4 *__restrict__ lout,
+                                           const float *__restrict__ tgt,
+                                           float *__restrict__ rendered, float *__restrict__ gimg,
+                                           sad_step_state *__restrict__ states,
+                                           float *__restrict__ grad, uint32_t *lds,
+                                           uint32_t *hkey, uint32_t *occ) {
     uint32_t(*queue)[256] = reinterpret_cast<uint32_t(*)[256]>(lds);
     unsigned long long(*hacc)[kHashSlots] = reinterpret_cast<unsigned long long(*)[kHashSlots]>(lds);
+    // the item, and so the image, is the same for the whole block: keep its
+    // descriptor in scalar registers
+    const int b = __builtin_amdgcn_readfirstlane(
+        upper_index(ba.n_images, item, [&](int k) { return (int64_t)ba.images[k].tile0; }));
+    sad_batch_image im = ba.images[b];
+    im.H = __builtin_amdgcn_readfirstlane(im.H);
+    im.W = __builtin_amdgcn_readfirstlane(im.W);
+    im.n_slots = __builtin_amdgcn_readfirstlane(im.n_slots);
+    im.tile0 = __builtin_amdgcn_readfirstlane(im.tile0);
+    im.cap = ((int64_t)__builtin_amdgcn_readfirstlane((int)(im.cap >> 32)) << 32) |
+             (uint32_t)__builtin_amdgcn_readfirstlane((int)im.cap);
+    im.px0 = ((int64_t)__builtin_amdgcn_readfirstlane((int)(im.px0 >> 32)) << 32) |
+             (uint32_t)__builtin_amdgcn_readfirstlane((int)im.px0);
+    im.site0 = ((int64_t)__builtin_amdgcn_readfirstlane((int)(im.site0 >> 32)) << 32) |
+               (uint32_t)__builtin_amdgcn_readfirstlane((int)im.site0);
+    const int tiles_x = (im.W + 15) / 16;
+    const TilePix px = tile_pixel(item - im.tile0, tiles_x);
+    const int64_t P = (int64_t)im.H * im.W;
+    PropArgs pa;
+    pa.H = im.H;
+    pa.W = im.W;
+    pa.n_slots = im.n_slots;
+    pa.jump = ba.fixed_jump > 0 ? ba.fixed_jump : 0;
+    pa.J = ba.J;
+    pa.every = ba.every;
+    pa.tiles_x = tiles_x;
+    pa.n_blocks = 0;
+    pa.seed = ba.seed;
+    pa.pass = 0;
+    pa.pass_dev = &states[b].pass;
+    const float inv_P = (float)(1.0 / (double)P);
+    const FixScale fx = fix_scale_dev(P);
+    const float4 *r4 = rec + 4 * im.site0;
+    const uint4 *li = lin + (int64_t)(K / 4) * im.px0;
+    uint4 *lo = lout + (int64_t)(K / 4) * im.px0;
+    const float *tg = tgt + 3 * im.px0;
+    float *gr = grad + 10 * im.site0;
+
+    const bool live = im.n_slots > 0 && px.i < im.H && px.j < im.W;
+    const int64_t p = (int64_t)px.i * im.W + px.j;
+    uint64_t keys[K];
+    if (live) {
+        prop_pixel<K>(pa, r4, li, px, queue, keys);
+#pragma unroll
+        for (int g = 0; g < K / 4; ++g)
+            lo[(int64_t)g * P + p] = make_uint4(key_id(keys[4 * g]), key_id(keys[4 * g + 1]),
+                                                key_id(keys[4 * g + 2]),
+                                                key_id(keys[4 * g + 3]));
+    }
+    __syncthreads();  // the queue is free: clear the accumulators in its place
+    bwd_tile_init<10>(hkey, hacc);
+    __syncthreads();
+    float sq = 0.f;
+    if (live) {
+        const float X = (float)px.j, Y = (float)px.i;
+        PixelBlend<K> bl;
+        blend_keys<K, true>(r4, keys, bl, lane_rot() % K);
+        float g[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const float d = bl.c[ch] - tg[ch * P + p];
+            g[ch] = 2.0f * inv_P * d;
+            sq = fmaf(d, d, sq);
+            if (gimg) gimg[3 * im.px0 + ch * P + p] = g[ch];
+            if (rendered) rendered[3 * im.px0 + ch * P + p] = bl.c[ch];
+        }
+        bwd_pixel<K, false, true>(r4, bl, X, Y, g[0], g[1], g[2], 0.f, 0.f, 0.f, hkey, hacc,
+                            fx, inv_P, im.cap, gr, nullptr);
+    } else if (im.n_slots == 0 && px.i < im.H && px.j < im.W) {
+        // no sites: empty list, colour 0
+#pragma unroll
+        for (int g = 0; g < K / 4; ++g)
+            lo[(int64_t)g * P + p] = make_uint4(SAD_INVALID_ID, SAD_INVALID_ID, SAD_INVALID_ID,
+                                                SAD_INVALID_ID);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const float d = -tg[ch * P + p];
+            sq = fmaf(d, d, sq);
+            if (gimg) gimg[3 * im.px0 + ch * P + p] = 2.0f * inv_P * d;
+            if (rendered) rendered[3 * im.px0 + ch * P + p] = 0.f;
+        }
+    }
+    const float tot = block_sum(sq);  // includes a barrier
+    if (threadIdx.x == 0)
+        atomic_add_f32(&states[b].loss.part[item % SAD_LOSS_PARTS], tot * inv_P);
+    bwd_flush<false, true>(hkey, hacc, fx, im.cap, gr, nullptr, occ);
+}
+
+template <int K>
+constexpr int batch_lds_words() {
+    return (QueueDepth<K>::v > 20 ? QueueDepth<K>::v : 20) * 256;
+}
+
+// Persistent form: gridDim.x blocks walk the items in contiguous runs (block -> XCD-local
+// range) or round robin.  The loop costs registers: for K <= 8 the kernel is held to 128
+// VGPRs (four waves per SIMD, no spill); larger K would spill under that cap and is left
+// uncapped.
+template <int K>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8 ? 4 : 1, 8))) void k_batch_train(
+    BatchArgs ba, const float4 *__restrict__ rec, const uint4 *__restrict__ lin,
+    uint4 *__restrict__ lout, const float *__restrict__ tgt, float *__restrict__ rendered,
+    float *__restrict__ gimg, sad_step_state *__restrict__ states, float *__restrict__ grad) {
+    __shared__ __align__(16) uint32_t lds[batch_lds_words<K>()];
+    __shared__ uint32_t hkey[kHashSlots];
+    __shared__ uint32_t occ[kHashSlots + 1];
     const int G = gridDim.x;
-    // work assignment: contiguous runs (block -> XCD-local range) or round robin
     int first, step, last;
     if (ba.chunked) {
         const int b = xcd_tile(blockIdx.x, G);
@@ -72,94 +173,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) voi
         step = G;
     }
     for (int item = first; item < last; item += step) {
-        // the item, and so the image, is the same for the whole block: keep its
-        // descriptor in scalar registers
-        const int b = __builtin_amdgcn_readfirstlane(
-            upper_index(ba.n_images, item, [&](int k) { return (int64_t)ba.images[k].tile0; }));
-        sad_batch_image im = ba.images[b];
-        im.H = __builtin_amdgcn_readfirstlane(im.H);
-        im.W = __builtin_amdgcn_readfirstlane(im.W);
-        im.n_slots = __builtin_amdgcn_readfirstlane(im.n_slots);
-        im.tile0 = __builtin_amdgcn_readfirstlane(im.tile0);
-        im.cap = ((int64_t)__builtin_amdgcn_readfirstlane((int)(im.cap >> 32)) << 32) |
-                 (uint32_t)__builtin_amdgcn_readfirstlane((int)im.cap);
-        im.px0 = ((int64_t)__builtin_amdgcn_readfirstlane((int)(im.px0 >> 32)) << 32) |
-                 (uint32_t)__builtin_amdgcn_readfirstlane((int)im.px0);
-        im.site0 = ((int64_t)__builtin_amdgcn_readfirstlane((int)(im.site0 >> 32)) << 32) |
-                   (uint32_t)__builtin_amdgcn_readfirstlane((int)im.site0);
-        const int tiles_x = (im.W + 15) / 16;
-        const TilePix px = tile_pixel(item - im.tile0, tiles_x);
-        const int64_t P = (int64_t)im.H * im.W;
-        PropArgs pa;
-        pa.H = im.H;
-        pa.W = im.W;
-        pa.n_slots = im.n_slots;
-        pa.jump = ba.fixed_jump > 0 ? ba.fixed_jump : 0;
-        pa.J = ba.J;
-        pa.every = ba.every;
-        pa.tiles_x = tiles_x;
-        pa.n_blocks = 0;
-        pa.seed = ba.seed;
-        pa.pass = 0;
-        pa.pass_dev = &states[b].pass;
-        const float inv_P = (float)(1.0 / (double)P);
-        const FixScale fx = fix_scale_dev(P);
-        const float4 *r4 = rec + 4 * im.site0;
-        const uint4 *li = lin + (int64_t)(K / 4) * im.px0;
-        uint4 *lo = lout + (int64_t)(K / 4) * im.px0;
-        const float *tg = tgt + 3 * im.px0;
-        float *gr = grad + 10 * im.site0;
-
-        const bool live = im.n_slots > 0 && px.i < im.H && px.j < im.W;
-        const int64_t p = (int64_t)px.i * im.W + px.j;
-        uint64_t keys[K];
-        if (live) {
-            prop_pixel<K>(pa, r4, li, px, queue, keys);
-#pragma unroll
-            for (int g = 0; g < K / 4; ++g)
-                lo[(int64_t)g * P + p] = make_uint4(key_id(keys[4 * g]), key_id(keys[4 * g + 1]),
-                                                    key_id(keys[4 * g + 2]),
-                                                    key_id(keys[4 * g + 3]));
-        }
-        __syncthreads();  // the queue is free: clear the accumulators in its place
-        bwd_tile_init<10>(hkey, hacc);
-        __syncthreads();
-        float sq = 0.f;
-        if (live) {
-            const float X = (float)px.j, Y = (float)px.i;
-            PixelBlend<K> bl;
-            blend_keys<K, true>(r4, keys, bl, lane_rot() % K);
-            float g[3];
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                const float d = bl.c[ch] - tg[ch * P + p];
-                g[ch] = 2.0f * inv_P * d;
-                sq = fmaf(d, d, sq);
-                if (gimg) gimg[3 * im.px0 + ch * P + p] = g[ch];
-                if (rendered) rendered[3 * im.px0 + ch * P + p] = bl.c[ch];
-            }
-            bwd_pixel<K, false, true>(r4, bl, X, Y, g[0], g[1], g[2], 0.f, 0.f, 0.f, hkey, hacc,
-                                fx, inv_P, im.cap, gr, nullptr);
-        } else if (im.n_slots == 0 && px.i < im.H && px.j < im.W) {
-            // no sites: empty list, colour 0
-#pragma unroll
-            for (int g = 0; g < K / 4; ++g)
-                lo[(int64_t)g * P + p] = make_uint4(SAD_INVALID_ID, SAD_INVALID_ID, SAD_INVALID_ID,
-                                                    SAD_INVALID_ID);
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                const float d = -tg[ch * P + p];
-                sq = fmaf(d, d, sq);
-                if (gimg) gimg[3 * im.px0 + ch * P + p] = 2.0f * inv_P * d;
-                if (rendered) rendered[3 * im.px0 + ch * P + p] = 0.f;
-            }
-        }
-        const float tot = block_sum(sq);  // includes a barrier
-        if (threadIdx.x == 0)
-            atomic_add_f32(&states[b].loss.part[item % SAD_LOSS_PARTS], tot * inv_P);
-        bwd_flush<false, true>(hkey, hacc, fx, im.cap, gr, nullptr, occ);
+        batch_item<K>(ba, item, rec, lin, lout, tgt, rendered, gimg, states, grad, lds, hkey, occ);
         __syncthreads();  // the next item re-initialises the table
     }
+}
+
+// One block per item (no loop, no register cap).
+template <int K>
+__global__ __launch_bounds__(256) void k_batch_train_1(
+    BatchArgs ba, const float4 *__restrict__ rec, const uint4 *__restrict__ lin,
+    uint4 *__restrict__ lout, const float *__restrict__ tgt, float *__restrict__ rendered,
+    float *__restrict__ gimg, sad_step_state *__restrict__ states, float *__restrict__ grad) {
+    __shared__ __align__(16) uint32_t lds[batch_lds_words<K>()];
+    __shared__ uint32_t hkey[kHashSlots];
+    __shared__ uint32_t occ[kHashSlots + 1];
+    batch_item<K>(ba, (int)blockIdx.x, rec, lin, lout, tgt, rendered, gimg, states, grad, lds, hkey,
+                  occ);
 }
 
 __global__ __launch_bounds__(64) void k_batch_loss_fold(sad_step_state *__restrict__ states) {
@@ -254,8 +283,12 @@ extern "C" sad_status sad_batch_train_step(const sad_batch *batch, const sad_tra
     uint4 *lo = reinterpret_cast<uint4 *>(topk_out);
 #define SAD_BATCH_CASE(KK)                                                                     \
     case KK:                                                                                   \
-        hipLaunchKernelGGL(k_batch_train<KK>, dim3(grid), dim3(256), 0, st, ba, r4, li, lo, target, \
-                           rendered, grad_img, states, grad_sites);                           \
+        if (batch->grid > 0 && grid < batch->n_items)                                          \
+            hipLaunchKernelGGL(k_batch_train<KK>, dim3(grid), dim3(256), 0, st, ba, r4, li, lo,  \
+                               target, rendered, grad_img, states, grad_sites);               \
+        else                                                                                   \
+            hipLaunchKernelGGL(k_batch_train_1<KK>, dim3(ba.n_items), dim3(256), 0, st, ba, r4,  \
+                               li, lo, target, rendered, grad_img, states, grad_sites);       \
         break;
     switch (batch->K) {
         SAD_BATCH_CASE(4)

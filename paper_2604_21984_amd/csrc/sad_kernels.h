@@ -233,6 +233,27 @@ struct QueueDepth {
     static constexpr int v = K + 8;  // room for one whole list (or 4 injections) after a check
 };
 
+// Exact keys of NC candidate IDs at pixel centre (X, Y) into out[].  The NC record
+// loads are issued before any score is formed, so a wave waits for one memory round
+// trip per group rather than one per candidate.  An ID >= ns or a site marked invalid
+// gives the empty key 0.
+template <int NC>
+__device__ __forceinline__ void exact_keys(const float4 *__restrict__ rec, uint32_t ns, float X,
+                                           float Y, const uint32_t (&id)[NC], uint64_t *out) {
+    float4 q0[NC], q1[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const uint32_t idc = id[c] < ns ? id[c] : 0u;
+        q0[c] = rec[4 * (size_t)idc];
+        q1[c] = rec[4 * (size_t)idc + 1];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const uint64_t k = make_key(score(q0[c], q1[c], X, Y), id[c]);
+        out[c] = ((id[c] < ns) & (q1[c].w != 0.0f)) ? k : 0ull;
+    }
+}
+
 // The new list of pixel (px.i, px.j) into keys[] (sorted, 0 = empty).  Lanes of pixels
 // outside the image must not call it (it votes across the wave, so call it from a
 // branch that those lanes skip).  queue: the kernel's LDS queue, Q x 256 words.
@@ -253,21 +274,16 @@ __device__ __forceinline__ void prop_pixel(const PropArgs &a, const float4 *__re
     const uint64_t pass = a.every <= 1 ? it : it / (uint64_t)a.every;
     const int s = (a.pass_dev && a.jump <= 0) ? jump_of((int64_t)pass, a.H, a.W) : a.jump;
 
-    auto exact_key = [&](uint32_t id) __attribute__((always_inline)) -> uint64_t {
-        const bool in_range = id < ns;
-        const uint32_t idc = in_range ? id : 0u;
-        const float4 q0 = rec[4 * (size_t)idc], q1 = rec[4 * (size_t)idc + 1];
-        return (in_range && q1.w != 0.0f) ? make_key(score(q0, q1, X, Y), id) : 0ull;
-    };
-
     // 1. own list
+    {
+        uint4 ol[K / 4];
 #pragma unroll
-    for (int g = 0; g < K / 4; ++g) {
-        const uint4 v = lin[(int64_t)g * P + p];
-        keys[4 * g] = exact_key(v.x);
-        keys[4 * g + 1] = exact_key(v.y);
-        keys[4 * g + 2] = exact_key(v.z);
-        keys[4 * g + 3] = exact_key(v.w);
+        for (int g = 0; g < K / 4; ++g) ol[g] = lin[(int64_t)g * P + p];
+#pragma unroll
+        for (int g = 0; g < K / 4; ++g) {
+            const uint32_t id[4] = {ol[g].x, ol[g].y, ol[g].z, ol[g].w};
+            exact_keys<4>(rec, ns, X, Y, id, &keys[4 * g]);
+        }
     }
     sort_keys_desc<K>(keys);
     bool rep = false;
@@ -286,28 +302,50 @@ __device__ __forceinline__ void prop_pixel(const PropArgs &a, const float4 *__re
     float kth = keys[K - 1] ? key_score(keys[K - 1]) : -INFINITY;
     int qn = 0;
 
-    auto screen = [&](uint32_t id) __attribute__((always_inline)) {
-        const bool in_range = id < ns;
-        const uint32_t nid = ~id;
-        bool kept = false;
+    // Screen four candidates: drop IDs already in the list and out-of-range IDs, then
+    // estimate each remaining score with the hardware square root and queue the ID
+    // unless the estimate is below the K-th score by more than its error bound.  The
+    // four record loads go out together; a dropped ID reads record 0, which all such
+    // lanes of the wave share, so the gather only fetches records of new IDs.
+    auto screen4 = [&](uint4 v) __attribute__((always_inline)) {
+        const uint32_t id[4] = {v.x, v.y, v.z, v.w};
+        uint32_t idc[4];
+        bool ok[4];
 #pragma unroll
-        for (int k = 0; k < K; ++k) kept = kept || ((uint32_t)keys[k] == nid);
-        // a kept or out-of-range ID reads record 0: all such lanes of the wave share one
-        // line, so the gather only fetches the records of IDs that are new to the pixel
-        const uint32_t idc = (in_range && !kept) ? id : 0u;
-        const float4 q0 = rec[4 * (size_t)idc], q1 = rec[4 * (size_t)idc + 1];
-        const float na = __builtin_amdgcn_sqrtf(quad(q0, q1, X, Y));
-        const float la = q1.y * (q1.z - na);
-        const float bound = fmaf(q1.y, fabsf(q1.z) + na, fabsf(la)) * 0x1p-19f;
-        const bool maybe = in_range && q1.w != 0.0f && !kept &&
-                           (keys[K - 1] == 0ull || la + bound >= kth);
-        if (maybe) queue[qn++][tid] = id;
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t nid = ~id[c];
+            bool kept = false;
+#pragma unroll
+            for (int k = 0; k < K; ++k) kept |= ((uint32_t)keys[k] == nid);
+            ok[c] = (id[c] < ns) & !kept;
+            idc[c] = ok[c] ? id[c] : 0u;
+        }
+        float4 q0[4], q1[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            q0[c] = rec[4 * (size_t)idc[c]];
+            q1[c] = rec[4 * (size_t)idc[c] + 1];
+        }
+        const bool open = keys[K - 1] == 0ull;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const float na = __builtin_amdgcn_sqrtf(quad(q0[c], q1[c], X, Y));
+            const float la = q1[c].y * (q1[c].z - na);
+            const float bound = fmaf(q1[c].y, fabsf(q1[c].z) + na, fabsf(la)) * 0x1p-19f;
+            const bool maybe = ok[c] & (q1[c].w != 0.0f) & (open | (la + bound >= kth));
+            if (maybe) queue[qn++][tid] = id[c];
+        }
     };
     auto drain_if = [&](int room) __attribute__((always_inline)) {
         if (__any(qn > Q - room)) {
-            for (int i = 0; i < Q; ++i) {
+            for (int i = 0; i < Q; i += 2) {
                 if (!__any(i < qn)) break;
-                if (i < qn) insert_key<K>(keys, exact_key(queue[i][tid]));
+                const uint32_t id[2] = {i < qn ? queue[i][tid] : SAD_INVALID_ID,
+                                        i + 1 < qn ? queue[i + 1][tid] : SAD_INVALID_ID};
+                uint64_t nk[2];
+                exact_keys<2>(rec, ns, X, Y, id, nk);
+                insert_key<K>(keys, nk[0]);
+                insert_key<K>(keys, nk[1]);
             }
             qn = 0;
             kth = keys[K - 1] ? key_score(keys[K - 1]) : -INFINITY;
@@ -323,26 +361,24 @@ __device__ __forceinline__ void prop_pixel(const PropArgs &a, const float4 *__re
         drain_if(K);
         if (ii >= 0 && ii < a.H && jj >= 0 && jj < a.W) {
             const int64_t q = (int64_t)ii * a.W + jj;
+            uint4 nl[K / 4];
 #pragma unroll
-            for (int g = 0; g < K / 4; ++g) {
-                const uint4 v = lin[(int64_t)g * P + q];
-                screen(v.x);
-                screen(v.y);
-                screen(v.z);
-                screen(v.w);
-            }
+            for (int g = 0; g < K / 4; ++g) nl[g] = lin[(int64_t)g * P + q];
+#pragma unroll
+            for (int g = 0; g < K / 4; ++g) screen4(nl[g]);
         }
     }
     const uint64_t k0 = (pass * (uint64_t)P + (uint64_t)p) * (uint64_t)a.J;
 #pragma unroll 1
     for (int j = 0; j < (full ? a.J : 0); j += 4) {
         drain_if(4);
+        uint32_t inj[4];
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj)
-            if (j + jj < a.J) {
-                const uint64_t hi = splitmix64(a.seed, k0 + (uint64_t)(j + jj)) >> 32;
-                screen((uint32_t)((hi * (uint64_t)ns) >> 32));
-            }
+        for (int jj = 0; jj < 4; ++jj) {
+            const uint64_t hi = splitmix64(a.seed, k0 + (uint64_t)(j + jj)) >> 32;
+            inj[jj] = j + jj < a.J ? (uint32_t)((hi * (uint64_t)ns) >> 32) : SAD_INVALID_ID;
+        }
+        screen4(make_uint4(inj[0], inj[1], inj[2], inj[3]));
     }
     // 3. remaining survivors
     drain_if(Q + 1);
