@@ -117,6 +117,43 @@ def autograd_path(enc, steps):
             "path": "propagate_topk + SADRender.apply + SADMSELoss.apply + backward + adam_step"}
 
 
+def large_image(steps, seed=1):
+    """Whole iterations (graph replay, as the headline) on 2048x2048 images: K = 16 at
+    100 000 and at 400 000 sites (the start and the cap of the large-image encode with
+    budget control), and K = 8 at 32 768 sites (1 bit per pixel, the workload of the
+    paper's per-epoch training time)."""
+    import torch
+
+    import synth
+    from paper_2604_21984_amd.encode import EncodeConfig, Encoder
+    Hl = Wl = 2048
+    target = torch.from_numpy(synth.image_large(seed, Hl, Wl)).cuda()
+    out = {}
+    for name, n, k in (("k16_n100k", 100_000, 16), ("k16_n400k", 400_000, 16),
+                       ("k8_n32768", 32_768, 8)):
+        enc = Encoder(target, n, EncodeConfig(K=k, n_inject=J, seed=seed))
+        for _ in range(10):
+            enc.step()
+        if enc.cur == 1:
+            enc.step()
+        enc.capture(2)
+        enc.replay(1)
+        torch.cuda.synchronize()
+        reps = max(1, steps // 4)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        enc.replay(reps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / (4 * reps)
+        out[name] = {"H": Hl, "W": Wl, "K": k, "n_sites": n, "steps": 4 * reps,
+                     "ms_per_step": round(ms, 4), "mpix_s": round(Hl * Wl / (ms * 1e3), 1),
+                     "psnr_db": round(enc.psnr(), 3)}
+        del enc
+        torch.cuda.empty_cache()
+    return out
+
+
 def batched_vs_loop(steps, seed=0):
     """64 images of uneven size (0.05 sites/px, K = 8): one persistent launch per
     iteration (autotuned, HIP graph) against a loop of per-image encoders (each one
@@ -262,6 +299,8 @@ def main():
                     help="only run 5 plain device copies of MIB MiB (calibrates HBM counters)")
     ap.add_argument("--autograd-steps", type=int, default=50,
                     help="iterations through the autograd wrappers (0: skip)")
+    ap.add_argument("--large-steps", type=int, default=40,
+                    help="iterations per 2048x2048 workload of the large-image timing (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=100,
                     help="iterations of the 64-image batched vs per-image comparison (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
@@ -399,6 +438,8 @@ def main():
 
     if args.autograd_steps > 0:
         extra("autograd", autograd_path, enc, args.autograd_steps)
+    if args.large_steps > 0:
+        extra("large_image", large_image, args.large_steps)
     if args.batch_steps > 0:
         extra("batched", batched_vs_loop, args.batch_steps)
     if args.serve_seconds > 0:

@@ -313,7 +313,10 @@ __device__ __forceinline__ void prop_pixel(const PropArgs &a, const float4 *__re
         bool ok[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            const uint32_t nid = ~id[c];
+            // (the empty asm keeps ~id as a value, so each test below is one compare
+            // instead of an xor and a compare with -1)
+            uint32_t nid = ~id[c];
+            asm("" : "+v"(nid));
             bool kept = false;
 #pragma unroll
             for (int k = 0; k < K; ++k) kept |= ((uint32_t)keys[k] == nid);

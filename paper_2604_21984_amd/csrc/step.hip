@@ -14,7 +14,7 @@
 namespace sad {
 
 template <int K>
-__global__ __launch_bounds__(256) void k_train(PropArgs pa, ImgArgs a, FixScale fx,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K == 16 ? 4 : 1, 8))) void k_train(PropArgs pa, ImgArgs a, FixScale fx,
                                                const float4 *__restrict__ rec,
                                                const uint4 *__restrict__ lin,
                                                uint4 *__restrict__ lout,
