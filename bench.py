@@ -28,9 +28,9 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources they were taken with: HBM bytes per launch from FETCH_SIZE + WRITE_SIZE
 # scaled by a copy kernel's readings, and the utilisation counters.
 PROFILED = {
-    "5b07f3174214c80f": {"traffic_bytes": 44942194,
-                         "counters": {"VALUBusy_pct": 51.5, "LDSBankConflict_pct": 14.5,
-                                      "OccupancyPercent": 52.5, "MemUnitStalled_pct": 0.07}},
+    "d4cb861b525e42c9": {"traffic_bytes": 44986518,
+                         "counters": {"VALUBusy_pct": 58.1, "LDSBankConflict_pct": 16.0,
+                                      "OccupancyPercent": 49.3, "MemUnitStalled_pct": 0.07}},
 }
 
 
