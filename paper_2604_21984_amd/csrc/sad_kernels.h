@@ -534,9 +534,10 @@ __device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const 
         acc[2] = gam * lk;
         acc[3] = gam * q1.y;
         const float n = sqrtf(quad(q0, q1, X, Y));
-        acc[0] = acc[1] = acc[7] = acc[8] = acc[9] = 0.f;
-        if (n > 0.f) {
-            const float rho = -0.5f * gam * q1.y * __builtin_amdgcn_rcpf(n);
+        {
+            // (a select, not a branch, for n = 0: a branch here lets the compiler defer
+            // the gather of q2.w and q3 behind it, a second dependent round trip)
+            const float rho = n > 0.f ? -0.5f * gam * q1.y * __builtin_amdgcn_rcpf(n) : 0.f;
             const float ux = q2.w, uy = q3.x, ep = q3.y, em = q3.z;
             const float dx = X - q0.x, dy = Y - q0.y;
             const float al = ux * dx + uy * dy, be = ux * dy - uy * dx;
@@ -565,13 +566,24 @@ __device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const 
         }
         const int slot = hash_slot(hkey, id);
         constexpr int nq = kRD ? kAcc : 10;
+        // Every term is added to the table (zero when it goes to global memory instead),
+        // so the ten adds are straight-line code; the rare out-of-range or table-full
+        // terms follow in one branch.
+        const int sl = slot >= 0 ? slot : 0;
+        bool spill = false;
 #pragma unroll
         for (int q = 0; q < nq; ++q) {
-            float *dst = q < 10 ? grad_at<kSiteMajor>(grad, q, id, cap) : rdel + id;
-            if (slot >= 0 && fabsf(acc[q]) < fx.limit)
-                atomicAdd(&hacc[q][slot], to_fixed(acc[q], fx.to_fix));
-            else if (acc[q] != 0.0f)
-                atomic_add_f32(dst, acc[q]);
+            const bool in = slot >= 0 && fabsf(acc[q]) < fx.limit;
+            spill |= !in && acc[q] != 0.0f;
+            atomicAdd(&hacc[q][sl], in ? to_fixed(acc[q], fx.to_fix) : 0ull);
+        }
+        if (spill) {
+#pragma unroll
+            for (int q = 0; q < nq; ++q) {
+                const bool in = slot >= 0 && fabsf(acc[q]) < fx.limit;
+                float *dst = q < 10 ? grad_at<kSiteMajor>(grad, q, id, cap) : rdel + id;
+                if (!in && acc[q] != 0.0f) atomic_add_f32(dst, acc[q]);
+            }
         }
     }
 }
