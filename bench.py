@@ -79,42 +79,41 @@ def cpu_baseline(target_np, sites_np, lists_np, budget_s):
 
 
 def autograd_path(enc, steps):
-    """Iterations through the torch.autograd.Function wrappers: propagation pass (lists
-    are not differentiable), SADRender forward, SADMSELoss, backward, Adam on .grad."""
+    """Iterations through the torch.autograd.Function wrappers (propagation pass, lists
+    not differentiable; SADRender forward; SADMSELoss; backward; Adam on sites.grad),
+    counters in a device step state: eagerly, and recorded as a HIP graph of ten
+    iterations and replayed."""
     import torch
 
-    from paper_2604_21984_amd import _lib as S
     from paper_2604_21984_amd import autograd as A
-    img, dev = enc.img, enc.device
-    sites = enc.sites.clone().requires_grad_(True)
-    rec = enc.rec.clone()
-    m, v = enc.m.clone(), enc.v.clone()
-    a, b = enc.topk.clone(), torch.empty_like(enc.topk)
-    t0 = enc.counters()[1]
-    S.prepare_sites(img, sites.detach(), rec)
-
-    def one(t):
-        nonlocal a, b
-        S.propagate_topk(img, rec, a, b, 1, J, 77, 10_000 + t)
-        a, b = b, a
-        out = A.render(sites, a, img, rec)
-        loss = A.mse_loss(out, enc.target, img)
-        loss.backward()
-        S.adam_step(img, sites.data, sites.grad, m, v, enc.adam, t0 + t + 1, rec, zero_grad=True)
-
-    for t in range(3):
-        one(t)
+    tr = A.AutogradTrainer(enc.img, enc.sites, enc.topk, enc.target, enc.adam, n_inject=J,
+                           seed=77)
+    for _ in range(4):
+        tr.step()
     torch.cuda.synchronize()
+    n = 2 * max(1, steps // 2)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    for t in range(3, 3 + steps):
-        one(t)
+    for _ in range(n):
+        tr.step()
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / steps
+    ms = e0.elapsed_time(e1) / n
+    tr.capture(pairs=5)
+    tr.replay(1)
+    torch.cuda.synchronize()
+    reps = max(1, n // 10)
+    e0.record()
+    tr.replay(reps)
+    e1.record()
+    torch.cuda.synchronize()
+    gms = e0.elapsed_time(e1) / (10 * reps)
     return {"ms_per_step": round(ms, 4), "mpix_s": round(enc.H * enc.W / (ms * 1e3), 1),
-            "steps": steps,
-            "path": "propagate_topk + SADRender.apply + SADMSELoss.apply + backward + adam_step"}
+            "steps": n, "graph_ms_per_step": round(gms, 4),
+            "graph_mpix_s": round(enc.H * enc.W / (gms * 1e3), 1), "graph_steps": 10 * reps,
+            "loss": round(float(tr.loss.item()), 6),
+            "path": "propagate_topk_state + SADRender.apply + SADMSELoss.apply + backward "
+                    "+ adam_step_state (eager, and as a HIP graph of ten iterations)"}
 
 
 def large_image(steps, seed=1):

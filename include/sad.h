@@ -278,6 +278,29 @@ sad_status sad_train_image_pass(const sad_image *img, const sad_train_config *cf
                                 uint32_t *topk_out, float *grad_sites, float *rendered,
                                 float *grad_img, sad_step_state *state, void *stream);
 
+/* Device-counter forms of sad_propagate_topk and sad_adam_step (Sec. 4.3 schedule,
+ * Sec. 5 Adam), for an iteration assembled from the separate calls (e.g. around the
+ * autograd wrapper) and recorded once into a HIP graph: the counters live in a
+ * sad_step_state on the device, so every replay continues the schedule.
+ *
+ * sad_propagate_topk_state: one pass with pass index state->pass and the jump
+ * s_t = sad_jump_step(state->pass, H, W), both read on the device; state is not
+ * modified.  Other arguments as sad_propagate_topk.
+ *
+ * sad_adam_step_state: sad_adam_step with step = state->adam_step + 1 read on the
+ * device; when the update is done the last block folds state->loss.part into
+ * state->loss.value and advances state->pass and state->adam_step by one (the end of
+ * an iteration, as in sad_train_step; with n_slots = 0 only the counters advance).
+ * flags as sad_adam_step.  state: device, zeroed before the first call; calls that
+ * share a state must not overlap. */
+sad_status sad_propagate_topk_state(const sad_image *img, const float *rec,
+                                    const uint32_t *topk_in, uint32_t *topk_out,
+                                    int32_t n_inject, uint64_t seed,
+                                    const sad_step_state *state, void *stream);
+sad_status sad_adam_step_state(const sad_image *img, float *sites, float *grad, float *m,
+                               float *v, const sad_adam_params *params, float *rec,
+                               uint32_t flags, sad_step_state *state, void *stream);
+
 /* ---- a8: batched training of many images in one persistent launch ----------------
  * Images of uneven size and site budget share pooled buffers.  Image b's blocks start
  * at fixed offsets: pixel pools (target [3][P_b] at 3*px0 floats, each list field

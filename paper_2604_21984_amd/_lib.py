@@ -81,6 +81,8 @@ def _load():
         "sad_loss_grad": [IMG, P, P, P, P, P],
         "sad_render_bwd": [IMG, P, P, P, P, P, P, P],
         "sad_adam_step": [IMG, P, P, P, P, C.POINTER(SadAdamParams), I64, P, C.c_uint32, P],
+        "sad_propagate_topk_state": [IMG, P, P, P, I32, U64, P, P],
+        "sad_adam_step_state": [IMG, P, P, P, P, C.POINTER(SadAdamParams), P, C.c_uint32, P, P],
         "sad_render_fwd_loss": [IMG, P, P, P, P, P, P, P],
         "sad_query_points": [IMG, P, P, P, I64, P, P],
         "sad_init_sites": [IMG, P, I32, F32, U64, F32, F32, P, P, C.POINTER(SZ), P],
@@ -169,6 +171,19 @@ def propagate_topk(img, rec, topk_in, topk_out, jump, n_inject, seed, pass_index
                                   int(jump), int(n_inject), int(seed) & (2 ** 64 - 1),
                                   int(pass_index), _stream()),
            "sad_propagate_topk")
+
+
+def propagate_topk_state(img, rec, topk_in, topk_out, n_inject, seed, state):
+    """sad_propagate_topk_state: pass index and jump from state (a step_state())."""
+    P = img.H * img.W
+    _check(lib.sad_propagate_topk_state(C.byref(img),
+                                        _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                                        _ptr(topk_in, torch.int32, img.K * P, "topk_in"),
+                                        _ptr(topk_out, torch.int32, img.K * P, "topk_out"),
+                                        int(n_inject), int(seed) & (2 ** 64 - 1),
+                                        _ptr(state, torch.int64, STEP_STATE_INT64, "state"),
+                                        _stream()),
+           "sad_propagate_topk_state")
 
 
 def jump_step(t, H, W):
@@ -348,6 +363,21 @@ def train_config(n_inject, seed, adam, fixed_jump=0, prop_every=1):
     c.n_inject, c.fixed_jump, c.seed, c.adam = int(n_inject), int(fixed_jump), int(seed) & (2 ** 64 - 1), adam
     c.prop_every = int(prop_every)
     return c
+
+
+def adam_step_state(img, sites, grad, m, v, params, rec, state, zero_grad=False,
+                    grad_site_major=False):
+    """sad_adam_step_state: step from state, whose counters advance at the end."""
+    n = NPARAM * img.cap
+    _check(lib.sad_adam_step_state(C.byref(img), _ptr(sites, torch.float32, n, "sites"),
+                                   _ptr(grad, torch.float32, n, "grad"),
+                                   _ptr(m, torch.float32, n, "m"), _ptr(v, torch.float32, n, "v"),
+                                   C.byref(params),
+                                   _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                                   (ADAM_ZERO_GRAD if zero_grad else 0) |
+                                   (ADAM_GRAD_SITE_MAJOR if grad_site_major else 0),
+                                   _ptr(state, torch.int64, STEP_STATE_INT64, "state"), _stream()),
+           "sad_adam_step_state")
 
 
 def train_step(img, cfg, target, sites, rec, topk_in, topk_out, grad, m, v, rendered, grad_img,

@@ -57,3 +57,65 @@ def render(sites, topk, img, rec=None):
 
 def mse_loss(rendered, target, img):
     return SADMSELoss.apply(rendered, target, img)
+
+
+class AutogradTrainer:
+    """Training iterations through the autograd wrappers: a propagation pass (the lists
+    are not differentiable), ``SADRender``, ``SADMSELoss``, ``backward()`` and Adam on
+    ``sites.grad``.  The pass index (jump schedule, injection stream) and the Adam step
+    live in a device step state, so an iteration issues no host-side counter and the
+    iterations can be recorded once as a HIP graph (``capture``) and replayed.
+
+    sites: float32 [10, cap] device tensor (copied); topk: the current list field
+    (copied); target: float32 [3, H, W]; adam: a ``SadAdamParams``."""
+
+    def __init__(self, img, sites, topk, target, adam, n_inject=4, seed=0):
+        self.img, self.adam, self.J, self.seed = img, adam, int(n_inject), int(seed)
+        dev = sites.device
+        self.sites = sites.detach().clone().requires_grad_(True)
+        self.rec = torch.empty(max(img.n_slots, 1) * S.REC_FLOATS, dtype=torch.float32,
+                               device=dev)
+        S.prepare_sites(img, self.sites.detach(), self.rec)
+        self.m = torch.zeros_like(self.sites.detach())
+        self.v = torch.zeros_like(self.sites.detach())
+        self.lists = [topk.clone(), torch.empty_like(topk)]
+        self.cur = 0
+        self.target = target
+        self.state = S.step_state(dev)
+        self.loss = None
+        self.graph = None
+
+    def step(self):
+        a, b = self.lists[self.cur], self.lists[1 - self.cur]
+        S.propagate_topk_state(self.img, self.rec, a, b, self.J, self.seed, self.state)
+        out = render(self.sites, b, self.img, self.rec)
+        loss = mse_loss(out, self.target, self.img)
+        loss.backward()
+        self.loss = loss.detach()  # keep no autograd graph alive across iterations
+        S.adam_step_state(self.img, self.sites.data, self.sites.grad, self.m, self.v,
+                          self.adam, self.rec, self.state, zero_grad=True)
+        self.cur = 1 - self.cur
+
+    def capture(self, pairs=1, warmup=2):
+        """Record 2 * pairs iterations as one graph (the list field ping-pongs, so the
+        graph starts and ends on the same buffer), after `warmup` eager iteration pairs
+        on a side stream."""
+        side = torch.cuda.Stream(device=self.sites.device)
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(2 * warmup):
+                self.step()
+        torch.cuda.current_stream().wait_stream(side)
+        assert self.cur == 0
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            for _ in range(2 * pairs):
+                self.step()
+
+    def replay(self, n=1):
+        for _ in range(n):
+            self.graph.replay()
+
+    def counters(self):
+        """(pass, adam_step) on the host (synchronises)."""
+        return tuple(int(x) for x in S.state_counters(self.state).cpu())

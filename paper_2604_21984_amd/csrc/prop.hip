@@ -155,6 +155,27 @@ extern "C" sad_status sad_exact_topk(const sad_image *img, const float *rec, con
     return check_launch("sad_exact_topk");
 }
 
+extern "C" sad_status sad_propagate_topk_state(const sad_image *img, const float *rec,
+                                               const uint32_t *topk_in, uint32_t *topk_out,
+                                               int32_t n_inject, uint64_t seed,
+                                               const sad_step_state *state, void *stream) {
+    SAD_TRY(check_image(img, nullptr));
+    SAD_REQUIRE(state, SAD_ERR_INVALID_ARGUMENT, "sad_propagate_topk_state: state is NULL");
+    SAD_REQUIRE(topk_in && topk_out, SAD_ERR_INVALID_ARGUMENT,
+                "sad_propagate_topk_state: NULL list");
+    SAD_REQUIRE(topk_in != topk_out, SAD_ERR_INVALID_ARGUMENT,
+                "sad_propagate_topk_state: topk_in and topk_out must not alias (Jacobi pass)");
+    SAD_REQUIRE(aligned16(topk_in) && aligned16(topk_out), SAD_ERR_INVALID_ARGUMENT,
+                "sad_propagate_topk_state: lists must be 16-byte aligned");
+    SAD_REQUIRE(n_inject >= 0 && n_inject <= 16, SAD_ERR_INVALID_ARGUMENT,
+                "sad_propagate_topk_state: n_inject must be in [0, 16]");
+    SAD_REQUIRE(img->n_slots == 0 || (rec && aligned16(rec)), SAD_ERR_INVALID_ARGUMENT,
+                "sad_propagate_topk_state: rec NULL or not 16-byte aligned");
+    launch_propagate(img, rec, topk_in, topk_out, 0, n_inject, seed, 0, &state->pass,
+                     as_stream(stream));
+    return check_launch("sad_propagate_topk_state");
+}
+
 extern "C" sad_status sad_propagate_topk(const sad_image *img, const float *rec,
                                          const uint32_t *topk_in, uint32_t *topk_out,
                                          int32_t jump, int32_t n_inject, uint64_t seed,

@@ -35,6 +35,8 @@ void launch_adam(const sad_image *img, float s, float *sites, float *grad, float
                  const sad_adam_params *p, int64_t step, const int64_t *step_dev, float *rec,
                  bool zero_grad, bool grad_site_major, sad_step_state *fin, hipStream_t st);
 void launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
+// state->pass += 1 and state->adam_step += 1 (one thread).
+void launch_state_advance(sad_step_state *state, hipStream_t st);
 
 // Radix select over unsigned 64-bit codes (8 passes of 8 bits, most significant
 // first).  On entry st->prefix = st->mask = 0 and st->want = the rank wanted (1 = the

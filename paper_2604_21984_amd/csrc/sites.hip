@@ -170,3 +170,28 @@ extern "C" sad_status sad_adam_step(const sad_image *img, float *sites, float *g
                 nullptr, as_stream(stream));
     return check_launch("sad_adam_step");
 }
+
+extern "C" sad_status sad_adam_step_state(const sad_image *img, float *sites, float *grad,
+                                          float *m, float *v, const sad_adam_params *params,
+                                          float *rec, uint32_t flags, sad_step_state *state,
+                                          void *stream) {
+    float s;
+    SAD_TRY(check_image(img, &s));
+    SAD_REQUIRE(params && state, SAD_ERR_INVALID_ARGUMENT,
+                "sad_adam_step_state: params or state is NULL");
+    SAD_REQUIRE((flags & ~(SAD_ADAM_ZERO_GRAD | SAD_ADAM_GRAD_SITE_MAJOR)) == 0,
+                SAD_ERR_INVALID_ARGUMENT, "sad_adam_step_state: unknown flags 0x%x", flags);
+    hipStream_t st = as_stream(stream);
+    if (img->n_slots == 0) {
+        launch_state_advance(state, st);
+        return check_launch("sad_adam_step_state");
+    }
+    SAD_REQUIRE(sites && grad && m && v, SAD_ERR_INVALID_ARGUMENT,
+                "sad_adam_step_state: NULL pointer");
+    SAD_REQUIRE(!rec || aligned16(rec), SAD_ERR_INVALID_ARGUMENT,
+                "sad_adam_step_state: rec not 16-byte aligned");
+    launch_adam(img, s, sites, grad, m, v, params, 1, &state->adam_step, rec,
+                (flags & SAD_ADAM_ZERO_GRAD) != 0, (flags & SAD_ADAM_GRAD_SITE_MAJOR) != 0,
+                state, st);
+    return check_launch("sad_adam_step_state");
+}

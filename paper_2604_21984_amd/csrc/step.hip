@@ -81,6 +81,10 @@ __global__ void k_state_advance(sad_step_state *__restrict__ s) {
 
 using namespace sad;
 
+void sad::launch_state_advance(sad_step_state *state, hipStream_t st) {
+    hipLaunchKernelGGL(k_state_advance, dim3(1), dim3(64), 0, st, state);
+}
+
 static sad_status image_pass(const sad_image *img, const sad_train_config *cfg,
                              const float *target, const float *rec, const uint32_t *topk_in,
                              uint32_t *topk_out, float *grad_sites, float *rendered,
@@ -173,7 +177,7 @@ extern "C" sad_status sad_train_step(const sad_image *img, const sad_train_confi
     if (img->n_slots == 0) {  // nothing to optimise: fold the loss, advance the counters
         SAD_TRY(image_pass(img, cfg, target, rec, topk_in, topk_out, grad_sites, rendered,
                            grad_img, state, true, true, st));
-        hipLaunchKernelGGL(k_state_advance, dim3(1), dim3(64), 0, st, state);
+        launch_state_advance(state, st);
         return check_launch("sad_train_step");
     }
     // the image pass leaves its loss partials; the last Adam block folds them and

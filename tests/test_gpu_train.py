@@ -174,3 +174,68 @@ def test_fused_image_pass_equals_separate_kernels(mods):
     gs = gs.reshape(10, -1)
     scale = gs.abs().amax(dim=1, keepdim=True) + 1e-30
     assert ((gf - gs).abs() / scale).max().item() < 1e-5
+
+
+def test_state_entry_points_match_host_counter_forms(mods):
+    """sad_propagate_topk_state / sad_adam_step_state against the host-counter calls at
+    the same pass index and Adam step: lists, sites, moments and records bit-identical;
+    the Adam form advances the counters."""
+    S, A, E = mods
+    enc = _enc(E, seed=5)
+    for _ in range(3):
+        enc.step()
+    torch.cuda.synchronize()
+    img, H, W = enc.img, enc.H, enc.W
+    state = S.step_state()
+    for t in (0, 1, 5, 40):
+        state[0] = t
+        a = enc.topk.clone()
+        b1, b2 = torch.empty_like(a), torch.empty_like(a)
+        S.propagate_topk(img, enc.rec, a, b1, S.jump_step(t, H, W), 4, 99, t)
+        S.propagate_topk_state(img, enc.rec, a, b2, 4, 99, state)
+        torch.cuda.synchronize()
+        assert torch.equal(b1, b2), t
+    state.zero_()
+    state[1] = 6
+    g = torch.randn(10, img.cap, device=DEV) * 1e-3
+    s1, s2 = enc.sites.clone(), enc.sites.clone()
+    m1, m2 = torch.full_like(s1, 0.01), torch.full_like(s1, 0.01)
+    v1, v2 = torch.full_like(s1, 0.02), torch.full_like(s1, 0.02)
+    r1, r2 = enc.rec.clone(), enc.rec.clone()
+    g1, g2 = g.clone(), g.clone()
+    S.adam_step(img, s1, g1, m1, v1, enc.adam, 7, r1, zero_grad=True)
+    S.adam_step_state(img, s2, g2, m2, v2, enc.adam, r2, state, zero_grad=True)
+    torch.cuda.synchronize()
+    for x, y in ((s1, s2), (m1, m2), (v1, v2), (r1, r2), (g1, g2)):
+        assert torch.equal(x, y)
+    assert S.state_counters(state).tolist() == [1, 7]
+
+
+def test_autograd_trainer_graph_matches_eager(mods):
+    """The autograd iteration recorded as a HIP graph against the same iterations run
+    eagerly from the same state; eager work and a synchronisation between replays."""
+    S, A, E = mods
+    enc = _enc(E, seed=6)
+    for _ in range(4):
+        enc.step()
+    torch.cuda.synchronize()
+    mk = lambda: A.AutogradTrainer(enc.img, enc.sites, enc.topk, enc.target, enc.adam,
+                                   n_inject=4, seed=11)
+    eager, graphed = mk(), mk()
+    graphed.capture(pairs=1, warmup=2)   # four eager iterations run, two recorded
+    for _ in range(4):
+        eager.step()
+    torch.cuda.synchronize()
+    assert graphed.counters() == eager.counters() == (4, 4)
+    for r in range(4):
+        graphed.replay(1)
+        eager.step()
+        eager.step()
+        torch.cuda.synchronize()
+        assert graphed.counters() == eager.counters() == (6 + 2 * r, 6 + 2 * r)
+        np.testing.assert_allclose(graphed.loss.item(), eager.loss.item(), rtol=1e-4)
+        _ = graphed.sites.detach().sum().item()
+        torch.testing.assert_close(graphed.sites.detach(), eager.sites.detach(),
+                                   rtol=1e-4, atol=1e-4)
+        same = (graphed.lists[0] == eager.lists[0]).float().mean().item()
+        assert same > 0.999, (r, same)
