@@ -28,10 +28,13 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources they were taken with: HBM bytes per launch from FETCH_SIZE + WRITE_SIZE
 # scaled by a copy kernel's readings, and the utilisation counters.
 PROFILED = {
-    "69b17799b4f632e7": {"traffic_bytes": 44986624,
+    "69b17799b4f632e7": {"traffic_bytes": 44986624, "valu_insts": 26343009,
                          "counters": {"VALUBusy_pct": 63.3, "LDSBankConflict_pct": 17.0,
                                       "OccupancyPercent": 48.9, "MemUnitStalled_pct": 0.07}},
 }
+# Vector-ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s (one
+# non-packed float32 operation per lane; packed FMA makes the 157.3 TFLOP/s headline).
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def kernel_fingerprint():
@@ -439,6 +442,15 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": prof["traffic_bytes"] if prof else None,
                 "algorithmic_bytes": dom_bytes, "kernel_fingerprint": fp}
+    # second view of the same launch: executed VALU instructions (profiled, 64 lanes each)
+    # against the vector-ALU issue peak
+    roofline_alu = None
+    if prof and "valu_insts" in prof:
+        tops = prof["valu_insts"] * 64 / (per_kernel_us[dom] * 1e-6) / 1e12
+        roofline_alu = {"bound": "alu", "kernel": dom, "achieved": round(tops, 2),
+                        "peak": round(VALU_PEAK_TOPS, 2), "unit": "T lane-op/s",
+                        "frac": round(tops / VALU_PEAK_TOPS, 4),
+                        "executed_valu_insts": prof["valu_insts"]}
     step_bytes = sum(algorithmic_bytes(k, P, N_SITES, K) for k in names)
 
     result = {
@@ -458,6 +470,7 @@ def main():
                                "+ forward + MSE gradient + backward + Adam per step, HIP graph",
                    "H": H, "W": W, "n_sites": N_SITES, "K": K, "J": J},
         "roofline": roofline,
+        "roofline_alu": roofline_alu,
         "counters": prof["counters"] if prof else None,
         "per_kernel_us": {k: round(v, 2) for k, v in per_kernel_us.items()},
         "step_algorithmic_bytes": step_bytes,
