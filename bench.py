@@ -160,10 +160,12 @@ def large_image(steps, seed=1):
     """Whole iterations (graph replay, as the headline) on 2048x2048 images: K = 16 at
     100 000 and at 400 000 sites (the start and the cap of the large-image encode with
     budget control), and K = 8 at 32 768 sites (1 bit per pixel, the workload of the
-    paper's per-epoch training time)."""
+    paper's per-epoch training time); then decoding from each one's cached lists: a full
+    render and one million random point queries."""
     import torch
 
     import synth
+    from paper_2604_21984_amd import _lib as S
     from paper_2604_21984_amd.encode import EncodeConfig, Encoder
     Hl = Wl = 2048
     target = torch.from_numpy(synth.image_large(seed, Hl, Wl)).cuda()
@@ -188,15 +190,43 @@ def large_image(steps, seed=1):
         out[name] = {"H": Hl, "W": Wl, "K": k, "n_sites": n, "steps": 4 * reps,
                      "ms_per_step": round(ms, 4), "mpix_s": round(Hl * Wl / (ms * 1e3), 1),
                      "psnr_db": round(enc.psnr(), 3)}
+        # decoding from the cached lists: a full render, and one million random points
+        img_out = torch.empty((3, Hl, Wl), device="cuda")
+        M = 1 << 20
+        g = torch.Generator(device="cuda").manual_seed(seed)
+        xy = torch.rand(M, 2, device="cuda", generator=g) * torch.tensor(
+            [Wl - 1.0, Hl - 1.0], device="cuda")
+        col = torch.empty(M, 3, device="cuda")
+        for _ in range(3):
+            S.render_fwd(enc.img, enc.rec, enc.topk, img_out)
+            S.query_points(enc.img, enc.rec, enc.topk, xy, col)
+        e0.record()
+        for _ in range(20):
+            S.render_fwd(enc.img, enc.rec, enc.topk, img_out)
+        e1.record()
+        torch.cuda.synchronize()
+        r_us = e0.elapsed_time(e1) * 1e3 / 20
+        e0.record()
+        for _ in range(20):
+            S.query_points(enc.img, enc.rec, enc.topk, xy, col)
+        e1.record()
+        torch.cuda.synchronize()
+        q_us = e0.elapsed_time(e1) * 1e3 / 20
+        out[name]["render_us"] = round(r_us, 1)
+        out[name]["render_gpix_s"] = round(Hl * Wl / r_us / 1e3, 2)
+        out[name]["query_1m_points_us"] = round(q_us, 1)
         del enc
         torch.cuda.empty_cache()
     return out
 
 
 def batched_vs_loop(steps, seed=0):
-    """64 images of uneven size (0.05 sites/px, K = 8): one persistent launch per
-    iteration (autotuned, HIP graph) against a loop of per-image encoders (each one
-    graph-replayed), same seeds, same number of iterations; PSNR compared per image."""
+    """64 images of uneven size (0.05 sites/px, K = 8), `steps` iterations from scratch:
+    the batched step (one launch per iteration over every image's tiles, the launch
+    picked by the autotuner, HIP graph) against a loop of per-image encoders (each one
+    graph-replayed), both propagating every iteration, same seeds: PSNR compared per
+    image.  Then the batched run again from the same start with the candidate update
+    period the autotuner picked (when it is not 1), with its PSNR."""
     import torch
 
     import synth
@@ -213,40 +243,58 @@ def batched_vs_loop(steps, seed=0):
     tg = [torch.from_numpy(im).cuda() for im in imgs]
     ns = [n for _, _, n in shapes]
     P = sum(H * W for H, W, _ in shapes)
+    pairs = max(1, steps // 2)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(run):
+        torch.cuda.synchronize()
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
     be = BatchEncoder(tg, ns, cfg)
     grid, chunked, timings = Autotuner().tune(be, pairs=2, reps=2, schedules=(1, 2, 4))
+    f_best = timings.get("prop_every_best", 1)
+    start = be.snapshot()
+    be.set_prop_every(1)
     be.capture()
-    pairs = max(1, steps // 2)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    be.replay(pairs)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_b = e0.elapsed_time(e1)
+    ms_b = timed(lambda: be.replay(pairs))
     ps_b = [be.psnr(i) for i in range(len(shapes))]
-    del be
+    tuned = None
+    if f_best != 1:
+        be.restore(start)
+        be.set_prop_every(f_best)
+        be.capture()
+        ms_f = timed(lambda: be.replay(pairs))
+        ps_f = [be.psnr(i) for i in range(len(shapes))]
+        tuned = {"prop_every": f_best, "batched_mpix_s": round(P * 2 * pairs / (ms_f * 1e3), 1),
+                 "mean_psnr_db": round(sum(ps_f) / len(ps_f), 3)}
+    del be, start
     encs = [Encoder(t, n, cfg) for t, n in zip(tg, ns)]
     for e in encs:
         e.capture()
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(pairs):
-        for e in encs:
-            e.replay(1)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_l = e0.elapsed_time(e1)
+
+    def loop():
+        for _ in range(pairs):
+            for e in encs:
+                e.replay(1)
+    ms_l = timed(loop)
     ps_l = [e.psnr() for e in encs]
     dps = max(abs(x - y) for x, y in zip(ps_b, ps_l))
     return {"images": len(shapes), "pixels": P, "sites": sum(ns), "iterations": 2 * pairs,
             "batched_mpix_s": round(P * 2 * pairs / (ms_b * 1e3), 1),
             "loop_mpix_s": round(P * 2 * pairs / (ms_l * 1e3), 1),
             "speedup": round(ms_l / ms_b, 3),
-            "mean_psnr_db": round(sum(ps_b) / len(ps_b), 3), "max_abs_dpsnr_db": round(dps, 4),
-            "launch": {"grid": grid, "chunked": chunked,
-                       "prop_every": timings.get("prop_every_best", 1)},
-            "autotune": timings}
+            "mean_psnr_db": round(sum(ps_b) / len(ps_b), 3),
+            "loop_mean_psnr_db": round(sum(ps_l) / len(ps_l), 3),
+            "mean_dpsnr_db": round(sum(x - y for x, y in zip(ps_b, ps_l)) / len(ps_b), 4),
+            "max_abs_dpsnr_db": round(dps, 4),
+            "psnr_note": "the float atomics of the gradient sums add in a different order on "
+                         "every run, so long encodes of one image drift apart; compare means",
+            "launch": {"grid": grid, "chunked": chunked, "prop_every": 1},
+            "tuned_schedule": tuned, "autotune": timings}
 
 
 def serving(rates, seconds, seed=0):
@@ -342,7 +390,7 @@ def main():
                     help="iterations of the whole-encode timing from scratch (0: skip)")
     ap.add_argument("--large-steps", type=int, default=40,
                     help="iterations per 2048x2048 workload of the large-image timing (0: skip)")
-    ap.add_argument("--batch-steps", type=int, default=100,
+    ap.add_argument("--batch-steps", type=int, default=1000,
                     help="iterations of the 64-image batched vs per-image comparison (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="seconds of Poisson arrivals per rate (0: skip serving)")

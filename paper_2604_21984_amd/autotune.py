@@ -5,8 +5,11 @@ Picks the persistent grid size (workgroups per compute unit) and the work assign
 or round robin) by timing graph-replayed iterations of the actual batch, then the
 propagation schedule: the candidate update period f (propagate every f-th iteration,
 App. B.3), the fastest f whose batch loss after a trial window stays within `tol` of
-the loss with f = 1 from the same state.  The batch's state is restored after the
-trials, so tuning does not change the encode.  Results are cached per workload
+the loss with f = 1 from the same state.  The trials start from the state reached after
+`warm` iterations past the current one (the first iterations of an encode take the
+long jumps of the schedule with unsettled lists and cost many times the steady state,
+so timing them would tune for the wrong regime).  The batch's state is restored after
+the trials, so tuning does not change the encode.  Results are cached per workload
 signature (image shapes, site counts, K) in memory and optionally in a JSON file.
 """
 import json
@@ -36,10 +39,11 @@ class Autotuner:
             with open(cache_path) as f:
                 self.cache = json.load(f)
 
-    def tune(self, enc, pairs=3, reps=2, schedules=(1,), window=16, tol=0.01):
+    def tune(self, enc, pairs=3, reps=2, schedules=(1,), window=16, tol=0.01, warm=12):
         """Return (grid, chunked, timings) for a BatchEncoder and apply the best launch;
         with more than one candidate update period in `schedules` also pick and apply
-        the period (reported under timings["prop_every"])."""
+        the period (reported under timings["prop_every"]).  `warm` (even) iterations
+        are run first; every trial starts from the state they reach."""
         sig = _signature(enc) + f"|f{','.join(map(str, schedules))}"
         if sig in self.cache:
             grid, chunked = self.cache[sig]["best"]
@@ -48,6 +52,9 @@ class Autotuner:
                 enc.set_prop_every(self.cache[sig]["prop_every"])
             return grid, chunked, self.cache[sig]["timings"]
         n_cu = torch.cuda.get_device_properties(enc.device).multi_processor_count
+        orig = enc.snapshot()
+        for _ in range(2 * ((max(0, warm) + 1) // 2)):
+            enc.step()
         snap = enc.snapshot()
         timings = {}
         for grid, chunked in candidates(enc.T_tot, n_cu):
@@ -66,7 +73,7 @@ class Autotuner:
                 torch.cuda.synchronize()
                 best = min(best, e0.elapsed_time(e1) / (2 * pairs))
             timings[f"{grid}/{chunked}"] = best
-        enc.restore(snap)
+        enc.restore(orig)
         key = min(timings, key=timings.get)
         grid, chunked = (int(x) for x in key.split("/"))
         enc.set_launch(grid, chunked)
@@ -89,7 +96,7 @@ class Autotuner:
             base = sched[schedules[0]][1]
             ok = [f for f in schedules if sched[f][1] <= base * (1.0 + tol)]
             best_f = min(ok, key=lambda f: sched[f][0])
-            enc.restore(snap)
+            enc.restore(orig)
             enc.set_prop_every(best_f)
             timings["prop_every"] = {str(f): {"ms": v[0], "loss": v[1]} for f, v in sched.items()}
             timings["prop_every_best"] = best_f
