@@ -156,6 +156,36 @@ def _whole_encode(n_sites, iterations, seed):
             "psnr_db": round(enc.psnr(), 3)}
 
 
+def deterministic_mode(steps, seed=0):
+    """The headline iteration with bit-reproducible gradient sums (int64 fixed point):
+    time per iteration after the long jumps, and whether two encodes of 4 + steps
+    iterations from the same seed end bit-identical."""
+    import torch
+
+    import synth
+    from paper_2604_21984_amd.encode import EncodeConfig, Encoder
+    target = torch.from_numpy(synth.image_encode(seed, H, W)).cuda()
+    cfg = EncodeConfig(K=K, n_inject=J, seed=seed, deterministic=True)
+    runs = []
+    for _ in range(2):
+        enc = Encoder(target, N_SITES, cfg)
+        for _ in range(20):
+            enc.step()
+        enc.capture(5)
+        reps = max(1, steps // 10)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        enc.replay(reps)
+        e1.record()
+        torch.cuda.synchronize()
+        runs.append((enc, e0.elapsed_time(e1) / (10 * reps)))
+    (a, ms), (b, _) = runs
+    same = all(torch.equal(x, y) for x, y in ((a.sites, b.sites), (a.m, b.m), (a.v, b.v),
+                                              (a.topk, b.topk)))
+    return {"ms_per_step": round(ms, 4), "mpix_s": round(H * W / (ms * 1e3), 1),
+            "iterations": 20 + 10 * max(1, steps // 10), "two_runs_bit_identical": same}
+
+
 def large_image(steps, seed=1):
     """Whole iterations (graph replay, as the headline) on 2048x2048 images: K = 16 at
     100 000 and at 400 000 sites (the start and the cap of the large-image encode with
@@ -388,6 +418,8 @@ def main():
                     help="iterations through the autograd wrappers (0: skip)")
     ap.add_argument("--encode-iterations", type=int, default=2000,
                     help="iterations of the whole-encode timing from scratch (0: skip)")
+    ap.add_argument("--det-steps", type=int, default=100,
+                    help="timed iterations of the deterministic-mode check (0: skip)")
     ap.add_argument("--large-steps", type=int, default=40,
                     help="iterations per 2048x2048 workload of the large-image timing (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=1000,
@@ -539,6 +571,8 @@ def main():
         extra("autograd", autograd_path, enc, args.autograd_steps)
     if args.encode_iterations > 0:
         extra("whole_encode", whole_encode, args.encode_iterations)
+    if args.det_steps > 0:
+        extra("deterministic", deterministic_mode, args.det_steps)
     if args.large_steps > 0:
         extra("large_image", large_image, args.large_steps)
     if args.batch_steps > 0:

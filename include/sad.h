@@ -175,9 +175,12 @@ sad_status sad_exact_topk(const sad_image *img, const float *rec, const int64_t 
  * sad_prepare_sites.  With flags & SAD_ADAM_ZERO_GRAD the gradient is cleared after it
  * has been read (the next backward accumulates into zeros); with flags &
  * SAD_ADAM_GRAD_SITE_MAJOR the gradient is the training step's site-major [cap][10]
- * accumulator instead of [10][cap].  params: host. */
+ * accumulator instead of [10][cap]; with flags & SAD_ADAM_GRAD_FIXED its elements are
+ * int64 fixed point (the deterministic accumulator of a training step run with
+ * SAD_TRAIN_DETERMINISTIC, 8 bytes per element) instead of float.  params: host. */
 #define SAD_ADAM_ZERO_GRAD 1u
 #define SAD_ADAM_GRAD_SITE_MAJOR 2u
+#define SAD_ADAM_GRAD_FIXED 4u
 sad_status sad_adam_step(const sad_image *img, float *sites, float *grad, float *m, float *v,
                          const sad_adam_params *params, int64_t step, float *rec, uint32_t flags,
                          void *stream);
@@ -245,8 +248,16 @@ typedef struct {
      * iterations re-score and sort each pixel's own list (a pass with no neighbours and
      * no injections).  0 or 1: propagate every iteration. */
     int32_t prop_every;
-    int32_t pad;
+    /* SAD_TRAIN_DETERMINISTIC: bit-reproducible gradient sums.  grad_sites then holds
+     * int64 fixed point, int64_t[cap][10] (80 bytes per site, zero on entry): every
+     * gradient term is rounded once into units of 2^-(20 + e), 2^e the power of two
+     * just below P = H*W (2^e >= P/2), and only integers are added after that (per
+     * 16x16 tile in LDS, then into grad_sites), so the sums do not depend on the order
+     * in which threads and tiles run.  Without it each tile's exact fixed-point sum is
+     * converted to float and added with a float atomic, in whatever order tiles finish. */
+    uint32_t flags;
 } sad_train_config;
+#define SAD_TRAIN_DETERMINISTIC 1u
 
 /* One iteration (Sec. 5: no host work inside the loop), enqueued as:
  *   1. propagation pass topk_in -> topk_out with pass index state->pass;
@@ -337,7 +348,9 @@ typedef struct {
  * image; image b uses states[b]): one persistent image-space kernel over all tiles of
  * all images, then per-image loss folds, one Adam kernel over all site slots and one
  * state update, whatever the number of images.  batch: host struct whose `images`
- * points to device memory; states: device [n_images]; rendered, grad_img nullable. */
+ * points to device memory; states: device [n_images]; rendered, grad_img nullable.
+ * With cfg->flags & SAD_TRAIN_DETERMINISTIC the gradient pool holds int64 elements
+ * (image b's rows at element 10*site0, in units of 2^-(20 + e_b) for its own P_b). */
 sad_status sad_batch_train_step(const sad_batch *batch, const sad_train_config *cfg,
                                 const float *target, float *sites, float *rec,
                                 const uint32_t *topk_in, uint32_t *topk_out, float *grad_sites,

@@ -40,7 +40,7 @@ class SadAdamParams(C.Structure):
 
 class SadTrainConfig(C.Structure):
     _fields_ = [("n_inject", C.c_int32), ("fixed_jump", C.c_int32), ("seed", C.c_uint64),
-                ("adam", SadAdamParams), ("prop_every", C.c_int32), ("pad", C.c_int32)]
+                ("adam", SadAdamParams), ("prop_every", C.c_int32), ("flags", C.c_uint32)]
 
 
 class SadBatchImage(C.Structure):
@@ -248,19 +248,29 @@ def adam_params(lr, beta1=0.9, beta2=0.999, eps=1e-8):
 
 ADAM_ZERO_GRAD = 1
 ADAM_GRAD_SITE_MAJOR = 2
+ADAM_GRAD_FIXED = 4
+TRAIN_DETERMINISTIC = 1
+
+
+def _grad_dtype(cfg):
+    """Element type of a training step's gradient accumulator under cfg."""
+    return torch.int64 if cfg.flags & TRAIN_DETERMINISTIC else torch.float32
 
 
 def adam_step(img, sites, grad, m, v, params, step, rec=None, zero_grad=False,
-              grad_site_major=False):
+              grad_site_major=False, grad_fixed=False):
     """sad_adam_step; grad is [10][cap], or the training step's [cap][10] accumulator
-    with grad_site_major=True."""
+    with grad_site_major=True; int64 fixed point (a deterministic step's accumulator)
+    with grad_fixed=True."""
     n = NPARAM * img.cap
     _check(lib.sad_adam_step(C.byref(img), _ptr(sites, torch.float32, n, "sites"),
-                             _ptr(grad, torch.float32, n, "grad"), _ptr(m, torch.float32, n, "m"),
+                             _ptr(grad, torch.int64 if grad_fixed else torch.float32, n, "grad"),
+                             _ptr(m, torch.float32, n, "m"),
                              _ptr(v, torch.float32, n, "v"), C.byref(params), int(step),
                              _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
                              (ADAM_ZERO_GRAD if zero_grad else 0) |
-                             (ADAM_GRAD_SITE_MAJOR if grad_site_major else 0), _stream()),
+                             (ADAM_GRAD_SITE_MAJOR if grad_site_major else 0) |
+                             (ADAM_GRAD_FIXED if grad_fixed else 0), _stream()),
            "sad_adam_step")
 
 
@@ -358,10 +368,13 @@ def version():
     return lib.sad_version().decode()
 
 
-def train_config(n_inject, seed, adam, fixed_jump=0, prop_every=1):
+def train_config(n_inject, seed, adam, fixed_jump=0, prop_every=1, deterministic=False):
+    """sad_train_config; deterministic=True makes the gradient accumulator int64 fixed
+    point (allocate it as torch.int64, same shape) and the sums bit-reproducible."""
     c = SadTrainConfig()
     c.n_inject, c.fixed_jump, c.seed, c.adam = int(n_inject), int(fixed_jump), int(seed) & (2 ** 64 - 1), adam
     c.prop_every = int(prop_every)
+    c.flags = TRAIN_DETERMINISTIC if deterministic else 0
     return c
 
 
@@ -390,7 +403,7 @@ def train_step(img, cfg, target, sites, rec, topk_in, topk_out, grad, m, v, rend
                               _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
                               _ptr(topk_in, torch.int32, img.K * P, "topk_in"),
                               _ptr(topk_out, torch.int32, img.K * P, "topk_out"),
-                              _ptr(grad, torch.float32, n, "grad"), _ptr(m, torch.float32, n, "m"),
+                              _ptr(grad, _grad_dtype(cfg), n, "grad"), _ptr(m, torch.float32, n, "m"),
                               _ptr(v, torch.float32, n, "v"),
                               _ptr(rendered, torch.float32, 3 * P, "rendered"),
                               _ptr(grad_img, torch.float32, 3 * P, "grad_img"),
@@ -405,7 +418,7 @@ def train_image_pass(img, cfg, target, rec, topk_in, topk_out, grad, rendered, g
                                     _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
                                     _ptr(topk_in, torch.int32, img.K * P, "topk_in"),
                                     _ptr(topk_out, torch.int32, img.K * P, "topk_out"),
-                                    _ptr(grad, torch.float32, NPARAM * img.cap, "grad"),
+                                    _ptr(grad, _grad_dtype(cfg), NPARAM * img.cap, "grad"),
                                     _ptr(rendered, torch.float32, 3 * P, "rendered"),
                                     _ptr(grad_img, torch.float32, 3 * P, "grad_img"),
                                     _ptr(state, torch.int64, STEP_STATE_INT64, "state"), _stream()),
@@ -422,7 +435,7 @@ def batch_train_step(batch, cfg, target, sites, rec, topk_in, topk_out, grad, m,
                                     _ptr(rec, torch.float32, REC_FLOATS * batch.n_site_slots, "rec"),
                                     _ptr(topk_in, torch.int32, None, "topk_in"),
                                     _ptr(topk_out, torch.int32, None, "topk_out"),
-                                    _ptr(grad, torch.float32, n, "grad"), _ptr(m, torch.float32, n, "m"),
+                                    _ptr(grad, _grad_dtype(cfg), n, "grad"), _ptr(m, torch.float32, n, "m"),
                                     _ptr(v, torch.float32, n, "v"),
                                     _ptr(rendered, torch.float32, None, "rendered"),
                                     _ptr(grad_img, torch.float32, None, "grad_img"),

@@ -49,7 +49,8 @@ class BatchEncoder:
             self.target[3 * px0[b]:3 * (px0[b] + H * W)].copy_(t.reshape(-1))
         self.sites = torch.empty(10 * S_tot, **f32)
         self.rec = torch.empty(max(S_tot, 1) * S.REC_FLOATS, **f32)
-        self.grad = torch.zeros(10 * S_tot, **f32)
+        self.grad = torch.zeros(10 * S_tot, device=dev,
+                                dtype=torch.int64 if cfg.deterministic else torch.float32)
         self.m = torch.zeros(10 * S_tot, **f32)
         self.v = torch.zeros(10 * S_tot, **f32)
         self.lists = [torch.empty(K * P_tot, dtype=torch.int32, device=dev) for _ in range(2)]
@@ -78,7 +79,8 @@ class BatchEncoder:
         lr = [cfg.lr * mlt for mlt in cfg.lr_mult]
         self.adam = S.adam_params(lr, cfg.beta1, cfg.beta2, cfg.eps)
         self.train_cfg = S.train_config(cfg.n_inject, cfg.seed ^ 0x5AD5AD, self.adam,
-                                        prop_every=cfg.prop_every)
+                                        prop_every=cfg.prop_every,
+                                        deterministic=cfg.deterministic)
         self.graph = None
         self.steps = 0
 

@@ -24,12 +24,12 @@ __device__ __forceinline__ int upper_index(int n, int64_t x, F key) {
 }
 
 __device__ __forceinline__ FixScale fix_scale_dev(int64_t P) {
-    int e = 0;
-    while ((int64_t)1 << (e + 1) < P) ++e;
+    const int e = fix_exponent(P);
     FixScale fx;
     fx.to_fix = ldexp(1.0, 40 + e);
     fx.from_fix = ldexp(1.0, -(40 + e));
     fx.limit = (float)ldexp(1.0, 15 - e);
+    fx.to_det = ldexp(1.0, 40 + e - kGlobShift);
     return fx;
 }
 
@@ -42,7 +42,7 @@ struct BatchArgs {
 // One (image, tile) work item: propagate, render, loss gradient and backward of its 256
 // pixels, flushed into the image's site-major gradient.  The queue and the accumulators
 // share one LDS buffer (used in turn, as in the single-image training kernel).
-template <int K>
+template <int K, bool kDet>
 __device__ __forceinline__ void batch_item(const BatchArgs &ba, int item,
                                            const float4 *__restrict__ rec,
                                            const uint4 *__restrict__ lin,
@@ -90,7 +90,9 @@ __device__ __forceinline__ void batch_item(const BatchArgs &ba, int item,
     const uint4 *li = lin + (int64_t)(K / 4) * im.px0;
     uint4 *lo = lout + (int64_t)(K / 4) * im.px0;
     const float *tg = tgt + 3 * im.px0;
-    float *gr = grad + 10 * im.site0;
+    // the image's gradient rows (int64 elements in the deterministic mode)
+    float *gr = kDet ? reinterpret_cast<float *>(reinterpret_cast<long long *>(grad) + 10 * im.site0)
+                     : grad + 10 * im.site0;
 
     const bool live = im.n_slots > 0 && px.i < im.H && px.j < im.W;
     const int64_t p = (int64_t)px.i * im.W + px.j;
@@ -120,8 +122,8 @@ __device__ __forceinline__ void batch_item(const BatchArgs &ba, int item,
             if (gimg) gimg[3 * im.px0 + ch * P + p] = g[ch];
             if (rendered) rendered[3 * im.px0 + ch * P + p] = bl.c[ch];
         }
-        bwd_pixel<K, false, true>(r4, bl, X, Y, g[0], g[1], g[2], 0.f, 0.f, 0.f, hkey, hacc,
-                            fx, inv_P, im.cap, gr, nullptr);
+        bwd_pixel<K, false, true, kDet>(r4, bl, X, Y, g[0], g[1], g[2], 0.f, 0.f, 0.f, hkey,
+                                        hacc, fx, inv_P, im.cap, gr, nullptr);
     } else if (im.n_slots == 0 && px.i < im.H && px.j < im.W) {
         // no sites: empty list, colour 0
 #pragma unroll
@@ -139,7 +141,7 @@ __device__ __forceinline__ void batch_item(const BatchArgs &ba, int item,
     const float tot = block_sum(sq);  // includes a barrier
     if (threadIdx.x == 0)
         atomic_add_f32(&states[b].loss.part[item % SAD_LOSS_PARTS], tot * inv_P);
-    bwd_flush<false, true>(hkey, hacc, fx, im.cap, gr, nullptr, occ);
+    bwd_flush<false, true, kDet>(hkey, hacc, fx, im.cap, gr, nullptr, occ);
 }
 
 template <int K>
@@ -151,7 +153,7 @@ constexpr int batch_lds_words() {
 // range) or round robin.  The loop costs registers: for K <= 8 the kernel is held to 128
 // VGPRs (four waves per SIMD, no spill); larger K would spill under that cap and is left
 // uncapped.
-template <int K>
+template <int K, bool kDet>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8 ? 4 : 1, 8))) void k_batch_train(
     BatchArgs ba, const float4 *__restrict__ rec, const uint4 *__restrict__ lin,
     uint4 *__restrict__ lout, const float *__restrict__ tgt, float *__restrict__ rendered,
@@ -173,22 +175,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8 ? 4 
         step = G;
     }
     for (int item = first; item < last; item += step) {
-        batch_item<K>(ba, item, rec, lin, lout, tgt, rendered, gimg, states, grad, lds, hkey, occ);
+        batch_item<K, kDet>(ba, item, rec, lin, lout, tgt, rendered, gimg, states, grad, lds, hkey,
+                            occ);
         __syncthreads();  // the next item re-initialises the table
     }
 }
 
 // One block per item (no loop, no register cap).
-template <int K>
-__global__ __launch_bounds__(256) void k_batch_train_1(
+template <int K, bool kDet>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K == 16 ? 4 : 1, 8))) void k_batch_train_1(
     BatchArgs ba, const float4 *__restrict__ rec, const uint4 *__restrict__ lin,
     uint4 *__restrict__ lout, const float *__restrict__ tgt, float *__restrict__ rendered,
     float *__restrict__ gimg, sad_step_state *__restrict__ states, float *__restrict__ grad) {
     __shared__ __align__(16) uint32_t lds[batch_lds_words<K>()];
     __shared__ uint32_t hkey[kHashSlots];
     __shared__ uint32_t occ[kHashSlots + 1];
-    batch_item<K>(ba, (int)blockIdx.x, rec, lin, lout, tgt, rendered, gimg, states, grad, lds, hkey,
-                  occ);
+    batch_item<K, kDet>(ba, (int)blockIdx.x, rec, lin, lout, tgt, rendered, gimg, states, grad, lds,
+                        hkey, occ);
 }
 
 __global__ __launch_bounds__(64) void k_batch_loss_fold(sad_step_state *__restrict__ states) {
@@ -214,7 +217,11 @@ __device__ __forceinline__ void batch_adam_slot(int n_images,
     const float s = im.score_scale != 0.0f ? im.score_scale
                                            : 1.0f / (float)(im.H > im.W ? im.H : im.W);
     const int64_t o = 10 * im.site0;
-    adam_site(sites + o, grad + o, m + o, v + o, im.cap, i, im.H, im.W, A, &states[b].adam_step, s,
+    float *g = A.grad_fixed ? reinterpret_cast<float *>(reinterpret_cast<long long *>(grad) + o)
+                            : grad + o;
+    AdamArgs Ai = A;
+    Ai.grad_from = det_grad_unit((int64_t)im.H * im.W);
+    adam_site(sites + o, g, m + o, v + o, im.cap, i, im.H, im.W, Ai, &states[b].adam_step, s,
               rec + 4 * im.site0);
 }
 
@@ -266,6 +273,9 @@ extern "C" sad_status sad_batch_train_step(const sad_batch *batch, const sad_tra
                 "sad_batch_train_step: n_inject must be in [0, 16]");
     SAD_REQUIRE(cfg->prop_every >= 0 && cfg->prop_every <= 1024, SAD_ERR_INVALID_ARGUMENT,
                 "training pass: prop_every must be in [0, 1024]");
+    SAD_REQUIRE((cfg->flags & ~SAD_TRAIN_DETERMINISTIC) == 0, SAD_ERR_INVALID_ARGUMENT,
+                "sad_batch_train_step: unknown flags 0x%x", cfg->flags);
+    const bool det = (cfg->flags & SAD_TRAIN_DETERMINISTIC) != 0;
     hipStream_t st = as_stream(stream);
     BatchArgs ba;
     ba.n_images = batch->n_images;
@@ -281,14 +291,20 @@ extern "C" sad_status sad_batch_train_step(const sad_batch *batch, const sad_tra
     const float4 *r4 = reinterpret_cast<const float4 *>(rec);
     const uint4 *li = reinterpret_cast<const uint4 *>(topk_in);
     uint4 *lo = reinterpret_cast<uint4 *>(topk_out);
+#define SAD_BATCH_LAUNCH(KK, DET)                                                              \
+    if (batch->grid > 0 && grid < batch->n_items)                                              \
+        hipLaunchKernelGGL((k_batch_train<KK, DET>), dim3(grid), dim3(256), 0, st, ba, r4, li,   \
+                           lo, target, rendered, grad_img, states, grad_sites);               \
+    else                                                                                       \
+        hipLaunchKernelGGL((k_batch_train_1<KK, DET>), dim3(ba.n_items), dim3(256), 0, st, ba,   \
+                           r4, li, lo, target, rendered, grad_img, states, grad_sites);
 #define SAD_BATCH_CASE(KK)                                                                     \
     case KK:                                                                                   \
-        if (batch->grid > 0 && grid < batch->n_items)                                          \
-            hipLaunchKernelGGL(k_batch_train<KK>, dim3(grid), dim3(256), 0, st, ba, r4, li, lo,  \
-                               target, rendered, grad_img, states, grad_sites);               \
-        else                                                                                   \
-            hipLaunchKernelGGL(k_batch_train_1<KK>, dim3(ba.n_items), dim3(256), 0, st, ba, r4,  \
-                               li, lo, target, rendered, grad_img, states, grad_sites);       \
+        if (det) {                                                                             \
+            SAD_BATCH_LAUNCH(KK, true)                                                         \
+        } else {                                                                               \
+            SAD_BATCH_LAUNCH(KK, false)                                                        \
+        }                                                                                      \
         break;
     switch (batch->K) {
         SAD_BATCH_CASE(4)
@@ -302,6 +318,7 @@ extern "C" sad_status sad_batch_train_step(const sad_batch *batch, const sad_tra
         default: break;
     }
 #undef SAD_BATCH_CASE
+#undef SAD_BATCH_LAUNCH
     AdamArgs A;
     for (int p = 0; p < SAD_NPARAM; ++p) A.lr[p] = cfg->adam.lr[p];
     A.b1 = cfg->adam.beta1;
@@ -310,6 +327,8 @@ extern "C" sad_status sad_batch_train_step(const sad_batch *batch, const sad_tra
     A.c1 = A.c2 = 1.0f;  // formed on the device from each image's step
     A.zero_grad = 1;
     A.grad_site_major = 1;
+    A.grad_fixed = det ? 1 : 0;
+    A.grad_from = 0.0;  // set per image on the device
     hipLaunchKernelGGL(k_batch_loss_fold, dim3(batch->n_images), dim3(64), 0, st, states);
     if (batch->n_site_slots > 0)
         hipLaunchKernelGGL(k_batch_adam, dim3((unsigned)((batch->n_site_slots + 255) / 256)),

@@ -45,6 +45,19 @@ __device__ __forceinline__ float score(const float4 q0, const float4 q1, float X
     return __fadd_rn(__fmul_rn(q1.y, __fsub_rn(q1.z, n)), 0.0f);
 }
 
+// Fixed-point scales of the backward for an image of P pixels, 2^e ~ P / 2 (every
+// gradient term carries the 1/P of dL/dc): the LDS tile table counts in 2^-(40 + e),
+// the deterministic global accumulator in det_grad_unit(P) = 2^-(40 + e - kGlobShift).
+constexpr int kGlobShift = 20;
+__host__ __device__ inline int fix_exponent(int64_t P) {
+    int e = 0;
+    while ((int64_t)1 << (e + 1) < P) ++e;
+    return e;
+}
+__host__ __device__ inline double det_grad_unit(int64_t P) {
+    return ldexp(1.0, -(40 + fix_exponent(P) - kGlobShift));
+}
+
 // Total order (score descending, ID ascending) as one unsigned 64-bit key: the high
 // word is the score's bits made monotone, the low word ~ID.  Key 0 is "empty" (no
 // finite or infinite score maps to 0) and ~0 of an empty key's low word is the

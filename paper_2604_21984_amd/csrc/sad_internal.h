@@ -31,9 +31,12 @@ void launch_bwd(const sad_image *img, const float *rec, const uint32_t *topk, co
 // The gradient is [10][cap], or [cap][10] with grad_site_major (the training step's).
 // If fin != NULL the last block also folds fin's loss partials and advances its
 // counters (the end of a training iteration).  Nothing is launched if n_slots == 0.
+// With grad_fixed the gradient elements are int64 in units of det_grad_unit(H * W) (the
+// deterministic accumulator of the training step).
 void launch_adam(const sad_image *img, float s, float *sites, float *grad, float *m, float *v,
                  const sad_adam_params *p, int64_t step, const int64_t *step_dev, float *rec,
-                 bool zero_grad, bool grad_site_major, sad_step_state *fin, hipStream_t st);
+                 bool zero_grad, bool grad_site_major, sad_step_state *fin, hipStream_t st,
+                 bool grad_fixed = false);
 void launch_fill_f32(float *p, int64_t n, float v, hipStream_t st);
 // state->pass += 1 and state->adam_step += 1 (one thread).
 void launch_state_advance(sad_step_state *state, hipStream_t st);

@@ -415,7 +415,29 @@ struct FixScale {
     double to_fix;     // 2^(40 + e)
     double from_fix;   // 2^-(40 + e)
     float limit;       // |v| must be below 2^(15 - e)
+    double to_det;     // 2^(40 + e - kGlobShift): the deterministic mode's unit
 };
+
+// Deterministic gradient sums (training steps with SAD_TRAIN_DETERMINISTIC): every
+// term is rounded once into units of det_grad_unit(P) (2^kGlobShift times the default
+// tile resolution) and from there on only integers are added: in the LDS tile table,
+// by the flush into the int64 global accumulator, and directly for the terms that
+// bypass the table.  The sums therefore depend neither on the order in which tiles
+// finish nor on which terms found a table slot.  Range: |sum| < 2^63 holds for
+// |gradient| < 2^(43 - e) (> 10^7 for a 4096 x 4096 image).
+
+__device__ __forceinline__ long long *grad64_at(float *grad, int q, uint32_t id, int64_t cap,
+                                                bool site_major) {
+    long long *g = reinterpret_cast<long long *>(grad);
+    return site_major ? g + (int64_t)id * SAD_NPARAM + q : g + q * cap + id;
+}
+
+// A term straight into the deterministic accumulator (clamped to the int64 range).
+__device__ __forceinline__ void det_add(long long *dst, float v, const FixScale &fx) {
+    double x = rint((double)v * fx.to_det);
+    x = fmin(fmax(x, -0x1p62), 0x1p62);
+    atomicAdd(reinterpret_cast<unsigned long long *>(dst), (unsigned long long)(long long)x);
+}
 
 __device__ __forceinline__ unsigned long long to_fixed(float v, double scale) {
     const double x = rint((double)v * scale);
@@ -451,7 +473,7 @@ __device__ __forceinline__ int hash_slot(uint32_t *__restrict__ hkey, uint32_t i
 // With kRD also the removal delta against the target colour (I0, I1, I2).  Each
 // entry's record is gathered again here (colour, metric, direction) rather than kept
 // in registers from the blend.
-template <int K, bool kRD, bool kSiteMajor = false>
+template <int K, bool kRD, bool kSiteMajor = false, bool kDet = false>
 __device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const PixelBlend<K> &b,
                                           float X, float Y, float g0, float g1, float g2,
                                           float I0, float I1, float I2,
@@ -575,14 +597,18 @@ __device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const 
         for (int q = 0; q < nq; ++q) {
             const bool in = slot >= 0 && fabsf(acc[q]) < fx.limit;
             spill |= !in && acc[q] != 0.0f;
-            atomicAdd(&hacc[q][sl], in ? to_fixed(acc[q], fx.to_fix) : 0ull);
+            atomicAdd(&hacc[q][sl], in ? to_fixed(acc[q], kDet ? fx.to_det : fx.to_fix) : 0ull);
         }
         if (spill) {
 #pragma unroll
             for (int q = 0; q < nq; ++q) {
                 const bool in = slot >= 0 && fabsf(acc[q]) < fx.limit;
-                float *dst = q < 10 ? grad_at<kSiteMajor>(grad, q, id, cap) : rdel + id;
-                if (!in && acc[q] != 0.0f) atomic_add_f32(dst, acc[q]);
+                if (in || acc[q] == 0.0f) continue;
+                if (kDet && q < 10)
+                    det_add(grad64_at(grad, q, id, cap, kSiteMajor), acc[q], fx);
+                else
+                    atomic_add_f32(q < 10 ? grad_at<kSiteMajor>(grad, q, id, cap) : rdel + id,
+                                   acc[q]);
             }
         }
     }
@@ -603,7 +629,7 @@ __device__ __forceinline__ void bwd_tile_init(uint32_t *__restrict__ hkey,
 // i % nq), so that consecutive lanes add into consecutive parameters of one site (one
 // cache line in the site-major layout).  Every thread of the block must call it.
 // occ: LDS scratch of kHashSlots + 1 words (the list and its length).
-template <bool kRD, bool kSiteMajor = false>
+template <bool kRD, bool kSiteMajor = false, bool kDet = false>
 __device__ __forceinline__ void bwd_flush(const uint32_t *__restrict__ hkey,
                                           unsigned long long (*hacc)[kHashSlots],
                                           const FixScale &fx, int64_t cap,
@@ -623,6 +649,12 @@ __device__ __forceinline__ void bwd_flush(const uint32_t *__restrict__ hkey,
         const uint32_t id = hkey[sl];
         const unsigned long long u = hacc[q][sl];
         if (!u) continue;
+        if (kDet && !(kRD && q == 10)) {  // already in the accumulator's units
+            atomicAdd(reinterpret_cast<unsigned long long *>(
+                          grad64_at(grad, q, id, cap, kSiteMajor)),
+                      u);
+            continue;
+        }
         float *dst = (kRD && q == 10) ? rdel + id
                      : (kSiteMajor ? grad + (int64_t)id * SAD_NPARAM + q : grad + q * cap + id);
         atomic_add_f32(dst, from_fixed(u, fx.from_fix));
@@ -631,12 +663,12 @@ __device__ __forceinline__ void bwd_flush(const uint32_t *__restrict__ hkey,
 
 // Fixed-point scale for an image of P pixels: 2^(40 + e) with 2^e ~ P / 2.
 inline FixScale fix_scale(int64_t P) {
-    int e = 0;
-    while ((int64_t)1 << (e + 1) < P) ++e;
+    const int e = fix_exponent(P);
     FixScale fx;
     fx.to_fix = std::ldexp(1.0, 40 + e);
     fx.from_fix = std::ldexp(1.0, -(40 + e));
     fx.limit = (float)std::ldexp(1.0, 15 - e);
+    fx.to_det = std::ldexp(1.0, 40 + e - kGlobShift);
     return fx;
 }
 

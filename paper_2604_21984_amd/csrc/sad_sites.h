@@ -87,6 +87,9 @@ struct AdamArgs {
     float b1, b2, eps, c1, c2;  // c1 = 1 - b1^t, c2 = 1 - b2^t (host step)
     int zero_grad;              // clear the gradient after reading it
     int grad_site_major;        // gradient [cap][10] (training step) instead of [10][cap]
+    int grad_fixed;             // gradient elements are int64 fixed point (deterministic
+                                // sums) worth grad_from each, instead of float
+    double grad_from;
 };
 
 // Adam on slot i of one image's [10][cap] buffers (site order of App. B.2), then clamps
@@ -100,9 +103,15 @@ __device__ __forceinline__ void adam_site(float *__restrict__ sites, float *__re
                                           float4 *__restrict__ rec) {
     const int64_t gs = A.grad_site_major ? 1 : cap;             // parameter stride
     const int64_t g0 = A.grad_site_major ? i * SAD_NPARAM : i;  // first element of site i
+    long long *g64 = reinterpret_cast<long long *>(grad);
     if (!(sites[i] >= 0.0f)) {  // inactive slot: parameters untouched
         if (A.zero_grad)
-            for (int p = 0; p < SAD_NPARAM; ++p) grad[g0 + p * gs] = 0.0f;
+            for (int p = 0; p < SAD_NPARAM; ++p) {
+                if (A.grad_fixed)
+                    g64[g0 + p * gs] = 0;
+                else
+                    grad[g0 + p * gs] = 0.0f;
+            }
         if (rec) write_record(sites, cap, i, s, rec);
         return;
     }
@@ -119,8 +128,14 @@ __device__ __forceinline__ void adam_site(float *__restrict__ sites, float *__re
 #pragma unroll
     for (int p = 0; p < SAD_NPARAM; ++p) {
         const int64_t o = p * cap + i;
-        const float g = grad[g0 + p * gs];
-        if (A.zero_grad) grad[g0 + p * gs] = 0.0f;
+        float g;
+        if (A.grad_fixed) {
+            g = (float)((double)g64[g0 + p * gs] * A.grad_from);
+            if (A.zero_grad) g64[g0 + p * gs] = 0;
+        } else {
+            g = grad[g0 + p * gs];
+            if (A.zero_grad) grad[g0 + p * gs] = 0.0f;
+        }
         const float mm = A.b1 * m[o] + (1.0f - A.b1) * g;
         const float vv = A.b2 * v[o] + (1.0f - A.b2) * g * g;
         m[o] = mm;

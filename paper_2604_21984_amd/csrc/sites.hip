@@ -136,7 +136,7 @@ extern "C" sad_status sad_seed_topk(const sad_image *img, const float *rec, uint
 void sad::launch_adam(const sad_image *img, float s, float *sites, float *grad, float *m,
                       float *v, const sad_adam_params *params, int64_t step,
                       const int64_t *step_dev, float *rec, bool zero_grad, bool grad_site_major,
-                      sad_step_state *fin, hipStream_t st) {
+                      sad_step_state *fin, hipStream_t st, bool grad_fixed) {
     if (img->n_slots == 0) return;
     AdamArgs A;
     for (int p = 0; p < SAD_NPARAM; ++p) A.lr[p] = params->lr[p];
@@ -147,6 +147,8 @@ void sad::launch_adam(const sad_image *img, float s, float *sites, float *grad, 
     A.c2 = (float)(1.0 - std::pow((double)params->beta2, (double)step));
     A.zero_grad = zero_grad ? 1 : 0;
     A.grad_site_major = grad_site_major ? 1 : 0;
+    A.grad_fixed = grad_fixed ? 1 : 0;
+    A.grad_from = det_grad_unit((int64_t)img->H * img->W);
     const int n = img->n_slots;
     hipLaunchKernelGGL(k_adam, dim3((n + 255) / 256), dim3(256), 0, st, sites, grad, m, v, img->cap,
                        n, img->H, img->W, A, step_dev, s, reinterpret_cast<float4 *>(rec), fin);
@@ -162,12 +164,13 @@ extern "C" sad_status sad_adam_step(const sad_image *img, float *sites, float *g
     if (img->n_slots == 0) return SAD_OK;
     SAD_REQUIRE(sites && grad && m && v, SAD_ERR_INVALID_ARGUMENT, "sad_adam_step: NULL pointer");
     SAD_REQUIRE(!rec || aligned16(rec), SAD_ERR_INVALID_ARGUMENT, "sad_adam_step: rec not 16-byte aligned");
-    SAD_REQUIRE((flags & ~(SAD_ADAM_ZERO_GRAD | SAD_ADAM_GRAD_SITE_MAJOR)) == 0,
+    SAD_REQUIRE((flags & ~(SAD_ADAM_ZERO_GRAD | SAD_ADAM_GRAD_SITE_MAJOR |
+                           SAD_ADAM_GRAD_FIXED)) == 0,
                 SAD_ERR_INVALID_ARGUMENT,
                 "sad_adam_step: unknown flags 0x%x", flags);
     launch_adam(img, s, sites, grad, m, v, params, step, nullptr, rec,
                 (flags & SAD_ADAM_ZERO_GRAD) != 0, (flags & SAD_ADAM_GRAD_SITE_MAJOR) != 0,
-                nullptr, as_stream(stream));
+                nullptr, as_stream(stream), (flags & SAD_ADAM_GRAD_FIXED) != 0);
     return check_launch("sad_adam_step");
 }
 
@@ -179,7 +182,8 @@ extern "C" sad_status sad_adam_step_state(const sad_image *img, float *sites, fl
     SAD_TRY(check_image(img, &s));
     SAD_REQUIRE(params && state, SAD_ERR_INVALID_ARGUMENT,
                 "sad_adam_step_state: params or state is NULL");
-    SAD_REQUIRE((flags & ~(SAD_ADAM_ZERO_GRAD | SAD_ADAM_GRAD_SITE_MAJOR)) == 0,
+    SAD_REQUIRE((flags & ~(SAD_ADAM_ZERO_GRAD | SAD_ADAM_GRAD_SITE_MAJOR |
+                           SAD_ADAM_GRAD_FIXED)) == 0,
                 SAD_ERR_INVALID_ARGUMENT, "sad_adam_step_state: unknown flags 0x%x", flags);
     hipStream_t st = as_stream(stream);
     if (img->n_slots == 0) {
@@ -192,6 +196,6 @@ extern "C" sad_status sad_adam_step_state(const sad_image *img, float *sites, fl
                 "sad_adam_step_state: rec not 16-byte aligned");
     launch_adam(img, s, sites, grad, m, v, params, 1, &state->adam_step, rec,
                 (flags & SAD_ADAM_ZERO_GRAD) != 0, (flags & SAD_ADAM_GRAD_SITE_MAJOR) != 0,
-                state, st);
+                state, st, (flags & SAD_ADAM_GRAD_FIXED) != 0);
     return check_launch("sad_adam_step_state");
 }

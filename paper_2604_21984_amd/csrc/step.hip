@@ -13,7 +13,7 @@
 
 namespace sad {
 
-template <int K>
+template <int K, bool kDet>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K == 16 ? 4 : 1, 8))) void k_train(PropArgs pa, ImgArgs a, FixScale fx,
                                                const float4 *__restrict__ rec,
                                                const uint4 *__restrict__ lin,
@@ -62,12 +62,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K == 16 ? 4
             if (gimg) gimg[ch * P + p] = g[ch];
             if (rendered) rendered[ch * P + p] = b.c[ch];
         }
-        bwd_pixel<K, false, true>(rec, b, X, Y, g[0], g[1], g[2], 0.f, 0.f, 0.f, hkey, hacc, fx,
-                            a.inv_P, a.cap, grad, nullptr);
+        bwd_pixel<K, false, true, kDet>(rec, b, X, Y, g[0], g[1], g[2], 0.f, 0.f, 0.f, hkey,
+                                        hacc, fx, a.inv_P, a.cap, grad, nullptr);
     }
     const float tot = block_sum(sq);  // contains the barrier the flush needs
     if (threadIdx.x == 0) atomic_add_f32(&loss->part[blockIdx.x % SAD_LOSS_PARTS], tot * a.inv_P);
-    bwd_flush<false, true>(hkey, hacc, fx, a.cap, grad, nullptr, occ);
+    bwd_flush<false, true, kDet>(hkey, hacc, fx, a.cap, grad, nullptr, occ);
 }
 
 __global__ void k_state_advance(sad_step_state *__restrict__ s) {
@@ -102,6 +102,8 @@ static sad_status image_pass(const sad_image *img, const sad_train_config *cfg,
                 "training pass: n_inject must be in [0, 16]");
     SAD_REQUIRE(cfg->prop_every >= 0 && cfg->prop_every <= 1024, SAD_ERR_INVALID_ARGUMENT,
                 "training pass: prop_every must be in [0, 1024]");
+    SAD_REQUIRE((cfg->flags & ~SAD_TRAIN_DETERMINISTIC) == 0, SAD_ERR_INVALID_ARGUMENT,
+                "training pass: unknown flags 0x%x", cfg->flags);
     if (img->n_slots == 0) {  // no sites: empty lists, colour 0, nothing to update
         launch_propagate(img, rec, topk_in, topk_out, 1, 0, 0, 0, nullptr, st);
         if (grad_img)
@@ -135,10 +137,17 @@ static sad_status image_pass(const sad_image *img, const sad_train_config *cfg,
     const float4 *r4 = reinterpret_cast<const float4 *>(rec);
     const uint4 *li = reinterpret_cast<const uint4 *>(topk_in);
     uint4 *lo = reinterpret_cast<uint4 *>(topk_out);
+    const bool det = (cfg->flags & SAD_TRAIN_DETERMINISTIC) != 0;
 #define SAD_TRAIN_CASE(KK)                                                                    \
     case KK:                                                                                  \
-        hipLaunchKernelGGL(k_train<KK>, dim3(a.n_blocks), dim3(256), 0, st, pa, a, fx, r4, li, lo, \
-                           target, rendered, grad_img, &state->loss, grad_sites);            \
+        if (det)                                                                              \
+            hipLaunchKernelGGL((k_train<KK, true>), dim3(a.n_blocks), dim3(256), 0, st, pa, a, fx, \
+                               r4, li, lo, target, rendered, grad_img, &state->loss,          \
+                               grad_sites);                                                   \
+        else                                                                                  \
+            hipLaunchKernelGGL((k_train<KK, false>), dim3(a.n_blocks), dim3(256), 0, st, pa, a,   \
+                               fx, r4, li, lo, target, rendered, grad_img, &state->loss,      \
+                               grad_sites);                                                   \
         break;
     switch (img->K) {
         SAD_TRAIN_CASE(4)
@@ -185,6 +194,6 @@ extern "C" sad_status sad_train_step(const sad_image *img, const sad_train_confi
     SAD_TRY(image_pass(img, cfg, target, rec, topk_in, topk_out, grad_sites, rendered, grad_img,
                        state, true, false, st));
     launch_adam(img, s, sites, grad_sites, adam_m, adam_v, &cfg->adam, 1, &state->adam_step, rec,
-                true, true, state, st);
+                true, true, state, st, (cfg->flags & SAD_TRAIN_DETERMINISTIC) != 0);
     return check_launch("sad_train_step");
 }

@@ -65,6 +65,7 @@ class EncodeConfig:
     score_scale: float = 0.0       # 0: 1 / max(H, W)
     budget: BudgetSchedule = None  # adaptive budget (None: fixed site count)
     prop_every: int = 1            # candidate update period f_cand (App. B.3)
+    deterministic: bool = False    # bit-reproducible gradient sums (int64 accumulator)
 
 
 def default_log_tau(H, W, N):
@@ -93,7 +94,9 @@ class Encoder:
         self.lists = [torch.empty((cfg.K // 4, H, W, 4), dtype=torch.int32, device=dev)
                       for _ in range(2)]
         self.cur = 0
-        self.grad = torch.zeros((cap, S.NPARAM), **f32)  # site-major accumulator
+        # site-major gradient accumulator (int64 fixed point in the deterministic mode)
+        self.grad = torch.zeros((cap, S.NPARAM), device=dev,
+                                dtype=torch.int64 if cfg.deterministic else torch.float32)
         self.m = torch.zeros((S.NPARAM, cap), **f32)
         self.v = torch.zeros((S.NPARAM, cap), **f32)
         self.rendered = torch.empty((3, H, W), **f32)
@@ -109,7 +112,8 @@ class Encoder:
         lr = [cfg.lr * mlt for mlt in cfg.lr_mult]
         self.adam = S.adam_params(lr, cfg.beta1, cfg.beta2, cfg.eps)
         self.train_cfg = S.train_config(cfg.n_inject, cfg.seed ^ 0x5AD5AD, self.adam,
-                                        prop_every=cfg.prop_every)
+                                        prop_every=cfg.prop_every,
+                                        deterministic=cfg.deterministic)
         self.graph = None
         self.steps = 0
         self.budget_log = []

@@ -239,3 +239,49 @@ def test_autograd_trainer_graph_matches_eager(mods):
                                    rtol=1e-4, atol=1e-4)
         same = (graphed.lists[0] == eager.lists[0]).float().mean().item()
         assert same > 0.999, (r, same)
+
+
+def test_deterministic_training_is_reproducible(mods):
+    """Deterministic gradient sums: two encodes from the same seed are bit-identical after
+    many iterations (graph replay included); one pass's int64 sums agree with the float
+    sums of the default mode within the rounding of the units."""
+    S, A, E = mods
+    target = torch.from_numpy(synth.image_encode(8, 96, 130, n_polygons=25, patch=24)).to(DEV)
+    cfg = E.EncodeConfig(K=8, n_inject=4, seed=8, deterministic=True)
+    a, b = E.Encoder(target, 600, cfg), E.Encoder(target, 600, cfg)
+    for _ in range(10):
+        a.step()
+        b.step()
+    b.capture(5)
+    for _ in range(10):
+        a.step()
+    b.replay(1)
+    torch.cuda.synchronize()
+    assert a.counters() == b.counters()
+    for x, y in ((a.sites, b.sites), (a.m, b.m), (a.v, b.v), (a.topk, b.topk), (a.rec, b.rec)):
+        assert torch.equal(x, y)
+    assert a.grad.dtype == torch.int64 and (a.grad == 0).all()
+    # one image pass from a's state in both modes
+    fcfg = S.train_config(4, 99, a.adam)
+    dcfg = S.train_config(4, 99, a.adam, deterministic=True)
+    gf = torch.zeros((a.img.cap, 10), dtype=torch.float32, device=DEV)
+    gd = torch.zeros((a.img.cap, 10), dtype=torch.int64, device=DEV)
+    outs = [torch.empty_like(a.topk) for _ in range(2)]
+    for cfg_, g_, o_ in ((fcfg, gf, outs[0]), (dcfg, gd, outs[1])):
+        st = S.step_state()
+        S.train_image_pass(a.img, cfg_, a.target, a.rec, a.topk, o_, g_, None, None, st)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1])
+    H, W = a.H, a.W
+    e = 0
+    while (1 << (e + 1)) < H * W:
+        e += 1
+    unit = 2.0 ** -(20 + e)
+    got = gd.cpu().numpy().astype(np.float64) * unit
+    ref = gf.cpu().numpy().astype(np.float64)
+    # each (pixel, entry) term of a site is rounded once to the unit (<= unit / 2 each);
+    # the float sums of the default mode are exact per tile, rounded per tile sum
+    ids = outs[0].cpu().numpy().astype(np.int64).reshape(-1) & 0xFFFFFFFF
+    terms = np.bincount(ids[ids < a.img.n_slots], minlength=a.img.cap)[:, None]
+    scale = np.abs(ref).max(axis=0, keepdims=True)
+    assert (np.abs(got - ref) <= 0.5 * terms * unit + 1e-6 * scale).all()
