@@ -60,3 +60,33 @@ def test_host_validation_without_device(lib):
                               C.c_float(0), None, None, C.byref(n), None) == 0
     assert n.value >= 8 * 64
     assert lib.sad_status_string(3) == b"workspace too small"
+
+
+def test_host_validation_of_state_forms_and_flags(lib):
+    """The device-counter entry points and the training / Adam flags are checked on the
+    host before anything is enqueued (no device is touched)."""
+    from paper_2604_21984_amd import _lib as S
+    ok = Img(8, 8, 8, 4, 4, 0.0)
+    buf = (C.c_uint32 * 4096)()
+    base = (C.addressof(buf) + 15) & ~15
+    p, q = C.c_void_p(base), C.c_void_p(base + 4096)
+    # propagation from a state: NULL state, aliasing lists
+    assert lib.sad_propagate_topk_state(C.byref(ok), p, p, q, C.c_int32(4), C.c_uint64(0),
+                                        None, None) == 1
+    assert lib.sad_propagate_topk_state(C.byref(ok), p, p, p, C.c_int32(4), C.c_uint64(0),
+                                        p, None) == 1
+    # Adam: unknown flag bits, NULL state
+    params = S.adam_params([1e-3] * 10, 0.9, 0.999, 1e-8)
+    assert lib.sad_adam_step(C.byref(ok), p, p, p, p, C.byref(params), C.c_int64(1), None,
+                             C.c_uint32(8), None) == 1
+    assert b"unknown flags" in lib.sad_last_error()
+    assert lib.sad_adam_step_state(C.byref(ok), p, p, p, p, C.byref(params), None,
+                                   C.c_uint32(0), None, None) == 1
+    # training pass: unknown training flags
+    cfg = S.train_config(4, 0, params)
+    cfg.flags = 2
+    assert lib.sad_train_image_pass(C.byref(ok), C.byref(cfg), p, p, p, q, p, None, None, p,
+                                    None) == 1
+    assert b"unknown flags" in lib.sad_last_error()
+    assert S.train_config(4, 0, params, deterministic=True).flags == S.TRAIN_DETERMINISTIC
+    assert S.train_config(4, 0, params).flags == 0
