@@ -565,6 +565,9 @@ def main():
         "roofline_alu": roofline_alu,
         "counters": prof["counters"] if prof else None,
         "per_kernel_us": {k: round(v, 2) for k, v in per_kernel_us.items()},
+        # propagation + forward + loss gradient + backward alone (the fused pass, Adam
+        # excluded), from the back-to-back launches of the breakdown
+        "fwd_bwd_only_mpix_s": round(P / per_kernel_us["train_pass"], 1),
         "step_algorithmic_bytes": step_bytes,
         "step_hbm_frac": round(step_bytes / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "loss": loss,
