@@ -365,28 +365,34 @@ def serving(rates, seconds, seed=0):
         xy = torch.rand((1000, 2), device="cuda") * torch.tensor([rs.W - 1.0, rs.H - 1.0],
                                                                  device="cuda")
         warm.append(V.Request(len(warm), rs.set_id, V.QUERY, xy=xy, M=1000))
-    srv = V.Server(V.GpuBackend(), sets)
+    srv = V.Server(V.GpuBackend(), sets, on_result=lambda r, out: None)
     V.run_open_loop(srv, warm, [0.0] * len(warm))
     torch.cuda.synchronize()
     del srv, warm
+    # point-query inputs: one pool of 2^20 uniform points per set; a request of M
+    # points takes a slice of its set's pool (device memory stays bounded however many
+    # requests a rate generates; the cost of a query does not depend on the values)
+    pool = []
+    for rs in sets:
+        xy = torch.rand((1 << 20, 2), device="cuda")
+        xy[:, 0] *= rs.W - 1
+        xy[:, 1] *= rs.H - 1
+        pool.append(xy)
     rng = np.random.default_rng(seed)
     for rate in rates:
         times = V.poisson_arrivals(rate, seconds, rng)
         reqs = []
         for rid, _ in enumerate(times):
             sid = int(rng.integers(0, len(sets)))
-            rs = sets[sid]
             if rng.uniform() < 0.2:
                 reqs.append(V.Request(rid, sid, V.RENDER))
                 continue
             M = int(np.exp(rng.uniform(np.log(1e3), np.log(1e6))))
-            xy = torch.rand((M, 2), device="cuda")
-            xy[:, 0] *= rs.W - 1
-            xy[:, 1] *= rs.H - 1
-            reqs.append(V.Request(rid, sid, V.QUERY, xy=xy, M=M))
+            off = int(rng.integers(0, (1 << 20) - M + 1))
+            reqs.append(V.Request(rid, sid, V.QUERY, xy=pool[sid][off:off + M], M=M))
         torch.cuda.synchronize()
-        srv = V.Server(V.GpuBackend(), sets)
-        V.run_open_loop(srv, reqs, times)
+        srv = V.Server(V.GpuBackend(), sets, on_result=lambda r, out: None)
+        V.run_open_loop(srv, reqs, times, timeout=max(120.0, 4.0 * seconds))
         torch.cuda.synchronize()
         st = srv.stats()
         out["by_rate"][str(rate)] = {k: (round(v, 3) if isinstance(v, float) else v)
@@ -396,24 +402,27 @@ def serving(rates, seconds, seed=0):
 
 
 def topk_quality(trials):
-    """Propagated field vs exact top-K at 256 random pixels (Sec. 6.5 protocol): 1024^2
-    domain, sites at distinct pixel cells, 8 / 12 / 16 passes, J = 4, K = 8."""
+    """Propagated field vs exact top-K at 256 random pixels (Sec. 6.5 protocol, its two
+    domains 1024^2 and 2048^2): sites at distinct pixel cells, 8 / 12 / 16 passes,
+    J = 4, K = 8."""
     import synth
     from paper_2604_21984_amd import quality as Q
-    qt = {}
-    for n in (16384, 65536, 131072):
-        acc = {t: [0.0, 0.0] for t in (8, 12, 16)}
-        for trial in range(trials):
-            sites = synth.cell_sites(1000 + trial, 1024, 1024, n)
-            r = Q.convergence(sites, 1024, 1024, K=K, J=J, passes=(8, 12, 16), n_pix=256,
-                              seed=trial)
-            for t in acc:
-                acc[t][0] += r[t][0] / trials
-                acc[t][1] += r[t][1] / trials
-        qt[str(n)] = {str(t): {"exact_match": round(v[0], 4), "recall": round(v[1], 4)}
-                      for t, v in acc.items()}
-    return {"domain": "1024x1024", "K": K, "J": J, "pixels": 256, "trials": trials,
-            "by_sites_and_passes": qt}
+    out = {"K": K, "J": J, "pixels": 256, "trials": trials, "by_domain": {}}
+    for side in (1024, 2048):
+        qt = {}
+        for n in (16384, 65536, 131072):
+            acc = {t: [0.0, 0.0] for t in (8, 12, 16)}
+            for trial in range(trials):
+                sites = synth.cell_sites(1000 + trial, side, side, n)
+                r = Q.convergence(sites, side, side, K=K, J=J, passes=(8, 12, 16), n_pix=256,
+                                  seed=trial)
+                for t in acc:
+                    acc[t][0] += r[t][0] / trials
+                    acc[t][1] += r[t][1] / trials
+            qt[str(n)] = {str(t): {"exact_match": round(v[0], 4), "recall": round(v[1], 4)}
+                          for t, v in acc.items()}
+        out["by_domain"][f"{side}x{side}"] = qt
+    return out
 
 
 def main():

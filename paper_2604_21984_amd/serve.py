@@ -143,8 +143,13 @@ class GpuBackend:
 
 class Server:
     def __init__(self, backend, sets, mem_budget=None, max_batch_points=1 << 22, max_inflight=8,
-                 reserve_frac=0.5):
+                 reserve_frac=0.5, on_result=None):
+        """on_result(request, output): called for every completed request; the default
+        keeps the output on request.result.  A caller that keeps its requests but not
+        their outputs (a load generator) passes one that drops it, so completed outputs
+        do not pile up in device memory."""
         self.backend = backend
+        self.on_result = on_result
         self.sets = {s.set_id: s for s in sets}
         if mem_budget is None:
             mem_budget = int(backend.free_bytes() * reserve_frac)
@@ -246,7 +251,10 @@ class Server:
             if self.backend.done(h):
                 t = self.backend.now()
                 for r, out in self.backend.results(h):
-                    r.result = out
+                    if self.on_result is None:
+                        r.result = out
+                    else:
+                        self.on_result(r, out)
                     r.t_done = t
                     self._release(r)
                     self.completed.append(r)

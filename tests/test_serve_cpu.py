@@ -144,3 +144,19 @@ def test_latency_percentiles():
         srv.completed.append(r)
     st = srv.stats()
     assert st["p50_ms"] == pytest.approx(50.0) and st["p99_ms"] == pytest.approx(99.0)
+
+
+def test_result_callback_replaces_retention():
+    """With on_result the outputs go to the callback and are not kept on the requests
+    (a load generator keeps its requests for the statistics, not their outputs)."""
+    clock = Clock()
+    got = []
+    srv = Server(FakeBackend(clock), [FakeSet(0)], mem_budget=1 << 20,
+                 on_result=lambda r, out: got.append((r.rid, out)))
+    for i in range(4):
+        srv.submit(_q(i, 0, 10))
+    srv.submit(Request(4, 0, RENDER, t_arrival=0.0))
+    _run(srv, clock)
+    assert sorted(rid for rid, _ in got) == [0, 1, 2, 3, 4]
+    assert all(r.result is None and r.error is None for r in srv.completed)
+    assert dict(got)[4] == ("r", 0, 4)
