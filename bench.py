@@ -451,8 +451,8 @@ def main():
                     help="trials of the top-K convergence measurement (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU design is described, not built)", file=sys.stderr)
+        print(f"bench.py: the implementation runs on one GPU; --gpus {args.gpus} is not "
+              "supported (sharding across GPUs is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
