@@ -181,7 +181,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8 ? 4 
     }
 }
 
-// One block per item (no loop, no register cap).
+// One block per item (no loop), items remapped so that each XCD takes a contiguous run
+// of them (neighbouring tiles of an image share that XCD's L2).
 template <int K, bool kDet>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K == 16 ? 4 : 1, 8))) void k_batch_train_1(
     BatchArgs ba, const float4 *__restrict__ rec, const uint4 *__restrict__ lin,
@@ -190,7 +191,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K == 16 ? 4
     __shared__ __align__(16) uint32_t lds[batch_lds_words<K>()];
     __shared__ uint32_t hkey[kHashSlots];
     __shared__ uint32_t occ[kHashSlots + 1];
-    batch_item<K, kDet>(ba, (int)blockIdx.x, rec, lin, lout, tgt, rendered, gimg, states, grad, lds,
+    batch_item<K, kDet>(ba, xcd_tile(blockIdx.x, gridDim.x), rec, lin, lout, tgt, rendered, gimg, states, grad, lds,
                         hkey, occ);
 }
 
