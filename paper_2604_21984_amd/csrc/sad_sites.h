@@ -10,15 +10,11 @@ namespace sad {
 
 // Derived record of slot i (Sec. 4.1: G = e^a u u^T + e^-a v v^T, v = (-u_y, u_x);
 // tau = exp(log_tau); kappa = tau * s).  Transcendentals in double, rounded once.
-__device__ __forceinline__ void write_record(const float *__restrict__ sites, int64_t cap,
-                                             int64_t i, float s, float4 *__restrict__ rec) {
-    float v[SAD_NPARAM];
+__device__ __forceinline__ void record_of(const float (&v)[SAD_NPARAM], int64_t i, float s,
+                                          float4 *__restrict__ rec) {
     bool finite = true;
 #pragma unroll
-    for (int p = 0; p < SAD_NPARAM; ++p) {
-        v[p] = sites[p * cap + i];
-        finite = finite && isfinite(v[p]);
-    }
+    for (int p = 0; p < SAD_NPARAM; ++p) finite = finite && isfinite(v[p]);
     const float x = v[0], y = v[1], lt = v[2], r = v[3], ux = v[7], uy = v[8], a = v[9];
     float4 q0 = make_float4(x, y, 0.f, 0.f), q1 = make_float4(0.f, 0.f, r, 0.f);
     float4 q2 = make_float4(v[4], v[5], v[6], ux), q3 = make_float4(uy, 0.f, 0.f, 0.f);
@@ -47,6 +43,14 @@ __device__ __forceinline__ void write_record(const float *__restrict__ sites, in
     rec[4 * i + 1] = q1;
     rec[4 * i + 2] = q2;
     rec[4 * i + 3] = q3;
+}
+
+__device__ __forceinline__ void write_record(const float *__restrict__ sites, int64_t cap,
+                                             int64_t i, float s, float4 *__restrict__ rec) {
+    float v[SAD_NPARAM];
+#pragma unroll
+    for (int p = 0; p < SAD_NPARAM; ++p) v[p] = sites[p * cap + i];
+    record_of(v, i, s, rec);
 }
 
 // ---- end of a training iteration ---------------------------------------------------
@@ -115,6 +119,17 @@ __device__ __forceinline__ void adam_site(float *__restrict__ sites, float *__re
         if (rec) write_record(sites, cap, i, s, rec);
         return;
     }
+    // every operand is loaded before the bias corrections are formed, so the double
+    // pow of a device-side step overlaps the loads' latency
+    float g[SAD_NPARAM], m0[SAD_NPARAM], v0[SAD_NPARAM], x0[SAD_NPARAM];
+#pragma unroll
+    for (int p = 0; p < SAD_NPARAM; ++p) {
+        const int64_t o = p * cap + i;
+        g[p] = A.grad_fixed ? (float)((double)g64[g0 + p * gs] * A.grad_from) : grad[g0 + p * gs];
+        m0[p] = m[o];
+        v0[p] = v[o];
+        x0[p] = sites[o];
+    }
     float c1 = A.c1, c2 = A.c2;
     if (step_dev) {
         const double t = (double)(*step_dev + 1);
@@ -128,20 +143,18 @@ __device__ __forceinline__ void adam_site(float *__restrict__ sites, float *__re
 #pragma unroll
     for (int p = 0; p < SAD_NPARAM; ++p) {
         const int64_t o = p * cap + i;
-        float g;
-        if (A.grad_fixed) {
-            g = (float)((double)g64[g0 + p * gs] * A.grad_from);
-            if (A.zero_grad) g64[g0 + p * gs] = 0;
-        } else {
-            g = grad[g0 + p * gs];
-            if (A.zero_grad) grad[g0 + p * gs] = 0.0f;
+        if (A.zero_grad) {
+            if (A.grad_fixed)
+                g64[g0 + p * gs] = 0;
+            else
+                grad[g0 + p * gs] = 0.0f;
         }
-        const float mm = A.b1 * m[o] + (1.0f - A.b1) * g;
-        const float vv = A.b2 * v[o] + (1.0f - A.b2) * g * g;
+        const float mm = A.b1 * m0[p] + (1.0f - A.b1) * g[p];
+        const float vv = A.b2 * v0[p] + (1.0f - A.b2) * g[p] * g[p];
         m[o] = mm;
         v[o] = vv;
         const float mh = mm / c1, vh = vv / c2;
-        float x = sites[o] - A.lr[p] * mh / (sqrtf(vh) + A.eps);
+        float x = x0[p] - A.lr[p] * mh / (sqrtf(vh) + A.eps);
         x = fminf(fmaxf(x, lo[p]), hi[p]);
         th[p] = x;
     }
@@ -155,7 +168,7 @@ __device__ __forceinline__ void adam_site(float *__restrict__ sites, float *__re
     }
 #pragma unroll
     for (int p = 0; p < SAD_NPARAM; ++p) sites[p * cap + i] = th[p];
-    if (rec) write_record(sites, cap, i, s, rec);
+    if (rec) record_of(th, i, s, rec);  // from the registers, not re-read
 }
 
 }  // namespace sad
