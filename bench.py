@@ -84,7 +84,7 @@ def cpu_baseline(target_np, sites_np, lists_np, budget_s):
 def autograd_path(enc, steps):
     """Iterations through the torch.autograd.Function wrappers (propagation pass, lists
     not differentiable; SADRender forward; SADMSELoss; backward; Adam on sites.grad),
-    counters in a device step state: eagerly, and recorded as a HIP graph of ten
+    counters in a device step state: eagerly, and recorded as one HIP graph of up to 50
     iterations and replayed."""
     import torch
 
@@ -102,21 +102,23 @@ def autograd_path(enc, steps):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / n
-    tr.capture(pairs=5)
+    gp = max(1, min(25, n // 2))
+    tr.capture(pairs=gp)
     tr.replay(1)
     torch.cuda.synchronize()
-    reps = max(1, n // 10)
+    reps = max(1, n // (2 * gp))
     e0.record()
     tr.replay(reps)
     e1.record()
     torch.cuda.synchronize()
-    gms = e0.elapsed_time(e1) / (10 * reps)
+    gms = e0.elapsed_time(e1) / (2 * gp * reps)
     return {"ms_per_step": round(ms, 4), "mpix_s": round(enc.H * enc.W / (ms * 1e3), 1),
             "steps": n, "graph_ms_per_step": round(gms, 4),
-            "graph_mpix_s": round(enc.H * enc.W / (gms * 1e3), 1), "graph_steps": 10 * reps,
+            "graph_mpix_s": round(enc.H * enc.W / (gms * 1e3), 1),
+            "graph_steps": 2 * gp * reps, "iterations_per_graph": 2 * gp,
             "loss": round(float(tr.loss.item()), 6),
             "path": "propagate_topk_state + SADRender.apply + SADMSELoss.apply + backward "
-                    "+ adam_step_state (eager, and as a HIP graph of ten iterations)"}
+                    "+ adam_step_state (eager, and recorded as one HIP graph)"}
 
 
 def whole_encode(iterations, seed=0):
