@@ -241,13 +241,14 @@ def test_autograd_trainer_graph_matches_eager(mods):
         assert same > 0.999, (r, same)
 
 
-def test_deterministic_training_is_reproducible(mods):
+@pytest.mark.parametrize("K,every", [(8, 1), (16, 2)])
+def test_deterministic_training_is_reproducible(mods, K, every):
     """Deterministic gradient sums: two encodes from the same seed are bit-identical after
     many iterations (graph replay included); one pass's int64 sums agree with the float
     sums of the default mode within the rounding of the units."""
     S, A, E = mods
     target = torch.from_numpy(synth.image_encode(8, 96, 130, n_polygons=25, patch=24)).to(DEV)
-    cfg = E.EncodeConfig(K=8, n_inject=4, seed=8, deterministic=True)
+    cfg = E.EncodeConfig(K=K, n_inject=4, seed=8, deterministic=True, prop_every=every)
     a, b = E.Encoder(target, 600, cfg), E.Encoder(target, 600, cfg)
     for _ in range(10):
         a.step()
