@@ -481,6 +481,7 @@ __device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const 
                                           unsigned long long (*hacc)[kHashSlots],
                                           const FixScale &fx, float inv_P, int64_t cap,
                                           float *__restrict__ grad, float *__restrict__ rdel) {
+    static_assert(!(kRD && kDet), "the deterministic mode has no removal-delta channel");
     if (!b.nv) return;
     const float invS = __builtin_amdgcn_rcpf(b.S);
     // c_k - c = (c_k - c_r) - dc with dc = sum_j w_j (c_j - c_r), r the reference entry
@@ -635,6 +636,7 @@ __device__ __forceinline__ void bwd_flush(const uint32_t *__restrict__ hkey,
                                           const FixScale &fx, int64_t cap,
                                           float *__restrict__ grad, float *__restrict__ rdel,
                                           uint32_t *__restrict__ occ) {
+    static_assert(!(kRD && kDet), "the deterministic mode has no removal-delta channel");
     const int t = threadIdx.x;
     uint32_t &n_occ = occ[kHashSlots];
     if (t == 0) n_occ = 0;
