@@ -28,9 +28,9 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources they were taken with: HBM bytes per launch from FETCH_SIZE + WRITE_SIZE
 # scaled by a copy kernel's readings, and the utilisation counters.
 PROFILED = {
-    "79a270ad51c1b83f": {"traffic_bytes": 44985321, "valu_insts": 26341482,
-                         "counters": {"VALUBusy_pct": 63.6, "LDSBankConflict_pct": 17.0,
-                                      "OccupancyPercent": 49.6, "MemUnitStalled_pct": 0.08}},
+    "f29c90e070c620f1": {"traffic_bytes": 44995762, "valu_insts": 26340834,
+                         "counters": {"VALUBusy_pct": 62.5, "LDSBankConflict_pct": 16.8,
+                                      "OccupancyPercent": 48.8, "MemUnitStalled_pct": 0.07}},
 }
 # Vector-ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s (one
 # non-packed float32 operation per lane; packed FMA makes the 157.3 TFLOP/s headline).
