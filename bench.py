@@ -381,26 +381,98 @@ def serving(rates, seconds, seed=0):
         xy[:, 1] *= rs.H - 1
         pool.append(xy)
     rng = np.random.default_rng(seed)
-    for rate in rates:
-        times = V.poisson_arrivals(rate, seconds, rng)
+
+    def make(specs):
         reqs = []
-        for rid, _ in enumerate(times):
-            sid = int(rng.integers(0, len(sets)))
-            if rng.uniform() < 0.2:
+        for rid, (sid, M, off) in enumerate(specs):
+            if M == 0:
                 reqs.append(V.Request(rid, sid, V.RENDER))
-                continue
-            M = int(np.exp(rng.uniform(np.log(1e3), np.log(1e6))))
-            off = int(rng.integers(0, (1 << 20) - M + 1))
-            reqs.append(V.Request(rid, sid, V.QUERY, xy=pool[sid][off:off + M], M=M))
+            else:
+                reqs.append(V.Request(rid, sid, V.QUERY, xy=pool[sid][off:off + M], M=M))
+        return reqs
+
+    def rounded(st):
+        return {k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()}
+
+    def served(specs, times):
+        reqs = make(specs)
         torch.cuda.synchronize()
         srv = V.Server(V.GpuBackend(), sets, on_result=lambda r, out: None)
         V.run_open_loop(srv, reqs, times, timeout=max(120.0, 4.0 * seconds))
         torch.cuda.synchronize()
-        st = srv.stats()
-        out["by_rate"][str(rate)] = {k: (round(v, 3) if isinstance(v, float) else v)
-                                     for k, v in st.items()}
-        del reqs, srv
+        return srv.stats()
+
+    for rate in rates:
+        times = V.poisson_arrivals(rate, seconds, rng)
+        specs = []
+        for _ in times:
+            sid = int(rng.integers(0, len(sets)))
+            if rng.uniform() < 0.2:
+                specs.append((sid, 0, 0))
+                continue
+            M = int(np.exp(rng.uniform(np.log(1e3), np.log(1e6))))
+            specs.append((sid, M, int(rng.integers(0, (1 << 20) - M + 1))))
+        out["by_rate"][str(rate)] = rounded(served(specs, times))
+        print(f"bench: serving at {rate} req/s done", file=sys.stderr, flush=True)
+    # the same request stream (the highest rate's) served by a plain loop: each request
+    # alone, in arrival order, launched and synchronised before the next; then both
+    # with every request arriving at once (capacity)
+    if not specs:
+        return out
+    burst = [0.0] * len(times)
+    loop = plain_loop(sets, make(specs), times)
+    print("bench: plain loop done", file=sys.stderr, flush=True)
+    cap_srv = served(specs, burst)
+    cap_loop = plain_loop(sets, make(specs), burst)
+    out["plain_loop"] = {
+        "rate": rates[-1], "requests": len(specs), "open_loop": rounded(loop),
+        "burst": {"server_rps": round(cap_srv["throughput_rps"], 1),
+                  "loop_rps": round(cap_loop["throughput_rps"], 1),
+                  "speedup": round(cap_srv["throughput_rps"] / cap_loop["throughput_rps"], 3),
+                  "server_p99_ms": round(cap_srv["p99_ms"], 3),
+                  "loop_p99_ms": round(cap_loop["p99_ms"], 3)}}
     return out
+
+
+def plain_loop(sets, reqs, times):
+    """Baseline for the server: every request alone, in arrival order, on the current
+    stream (``sad_query_points`` or ``sad_render_fwd``), synchronised before the next
+    one starts.  A request's latency runs from its arrival time to its completion."""
+    import torch
+
+    from paper_2604_21984_amd import _lib as S
+    from paper_2604_21984_amd import serve as V
+    by = {rs.set_id: rs for rs in sets}
+    imgs = {rs.set_id: S.image(rs.H, rs.W, rs.K, rs.n_slots, rs.n_slots, rs.score_scale)
+            for rs in sets}
+    lat, pts, px = [], 0, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_last = t0
+    for r, t in zip(reqs, times):
+        V.wait_until(t0 + t)  # the server's driver waits the same way
+        rs = by[r.set_id]
+        if r.M:
+            o = torch.empty((r.M, 3), dtype=torch.float32, device="cuda")
+            S.query_points(imgs[r.set_id], rs.rec, rs.topk, r.xy, o)
+            pts += r.M
+        else:
+            o = torch.empty((3, rs.H, rs.W), dtype=torch.float32, device="cuda")
+            S.render_fwd(imgs[r.set_id], rs.rec, rs.topk, o)
+            px += rs.H * rs.W
+        torch.cuda.synchronize()
+        t_last = time.perf_counter()
+        lat.append(t_last - (t0 + t))
+        del o
+    lat.sort()
+    span = max(t_last - t0 - times[0], 1e-9)
+
+    def pct(q):
+        return lat[min(len(lat) - 1, max(0, math.ceil(q * len(lat)) - 1))]
+
+    return {"completed": len(lat), "p50_ms": 1e3 * pct(0.5), "p99_ms": 1e3 * pct(0.99),
+            "mean_ms": 1e3 * sum(lat) / len(lat), "throughput_rps": len(lat) / span,
+            "points_per_s": pts / span, "render_px_per_s": px / span}
 
 
 def topk_quality(trials):

@@ -8,7 +8,8 @@ cached top-K lists is the fast path).
   A request that could never fit is rejected.
 * Continuous batching: every scheduler turn launches whatever has been admitted since
   the last turn -- point queries of many requests across many sets as one
-  ``sad_query_batch`` launch, renders as their own launches -- on a pool of streams,
+  ``sad_query_batch`` launch (a lone query: ``sad_query_points``, with no job table to
+  upload), renders as their own launches -- on a pool of streams,
   without waiting for earlier launches; completions are found by polling events.
   Requests that arrive while others run are admitted as memory frees up and their work
   overlaps on the device with the work already there.
@@ -87,6 +88,7 @@ class GpuBackend:
         self.device = torch.device(device or "cuda")
         self.streams = [torch.cuda.Stream(self.device) for _ in range(n_streams)]
         self._next = 0
+        self._images = {}  # (set id, shape, K, slots, scale) -> sad_image descriptor
 
     def now(self):
         return time.perf_counter()
@@ -100,10 +102,27 @@ class GpuBackend:
         self._next += 1
         return s
 
+    def _image(self, rs):
+        key = (rs.set_id, rs.H, rs.W, rs.K, rs.n_slots, rs.score_scale)
+        img = self._images.get(key)
+        if img is None:
+            img = self.S.image(rs.H, rs.W, rs.K, rs.n_slots, rs.n_slots, rs.score_scale)
+            self._images[key] = img
+        return img
+
     def launch_queries(self, reqs, sets):
         torch, S = self.torch, self.S
         K = sets[reqs[0].set_id].K
         n = len(reqs)
+        if n == 1:  # one request: sad_query_points, with no job table to upload
+            r, rs = reqs[0], sets[reqs[0].set_id]
+            st = self._stream()
+            with torch.cuda.stream(st):
+                out = torch.empty((r.M, 3), dtype=torch.float32, device=self.device)
+                S.query_points(self._image(rs), rs.rec, rs.topk, r.xy, out)
+                ev = torch.cuda.Event()
+                ev.record(st)
+            return {"event": ev, "reqs": reqs, "outs": [out], "keep": ()}
         arr = (S.SadQueryJob * n)()
         outs = []
         q0 = 0
@@ -127,9 +146,8 @@ class GpuBackend:
         torch, S = self.torch, self.S
         st = self._stream()
         with torch.cuda.stream(st):
-            img = S.image(rset.H, rset.W, rset.K, rset.n_slots, rset.n_slots, rset.score_scale)
             out = torch.empty((3, rset.H, rset.W), dtype=torch.float32, device=self.device)
-            S.render_fwd(img, rset.rec, rset.topk, out)
+            S.render_fwd(self._image(rset), rset.rec, rset.topk, out)
             ev = torch.cuda.Event()
             ev.record(st)
         return {"event": ev, "reqs": [req], "outs": [out], "keep": ()}
@@ -314,27 +332,37 @@ def poisson_arrivals(rate, duration, rng):
         out.append(t)
 
 
-def run_open_loop(server, requests, times, poll_sleep=0.0, timeout=120.0):
-    """Submit requests at their arrival times (seconds from now) from a feeder thread
-    while this thread runs the scheduler; returns when every request has completed
+def wait_until(t, spin=5e-4):
+    """Sleep until perf_counter() reaches t: a coarse sleep, then a spin for the last
+    `spin` seconds (a plain sleep overshoots by tens of microseconds)."""
+    dt = t - time.perf_counter()
+    if dt > spin:
+        time.sleep(dt - spin)
+    while time.perf_counter() < t:
+        pass
+
+
+def run_open_loop(server, requests, times, timeout=120.0):
+    """Open-loop driver: request i arrives `times[i]` seconds after the start.  The
+    scheduler's own thread submits every request whose arrival time has passed, with
+    that arrival time as its t_arrival (so the wait until the scheduler notices it is
+    part of its latency), runs scheduler turns while work is in flight, and sleeps until
+    the next arrival when idle.  One thread: no feeder thread contends with the
+    scheduler for the interpreter lock.  Returns when every request has completed
     (TimeoutError after `timeout` seconds)."""
-    t_start = time.perf_counter()
-
-    def feed():
-        for r, t in zip(requests, times):
-            dt = t_start + t - time.perf_counter()
-            if dt > 0:
-                time.sleep(dt)
-            r.t_arrival = time.perf_counter()
-            server.submit(r)
-
-    th = threading.Thread(target=feed, daemon=True)
-    th.start()
+    order = sorted(range(len(requests)), key=lambda i: times[i])
     n = len(requests)
-    while th.is_alive() or len(server.completed) < n:
-        server.step()
-        if time.perf_counter() - t_start > timeout:
+    t_start = time.perf_counter()
+    nxt = 0
+    while nxt < n or len(server.completed) < n:
+        now = time.perf_counter()
+        while nxt < n and t_start + times[order[nxt]] <= now:
+            r = requests[order[nxt]]
+            r.t_arrival = t_start + times[order[nxt]]
+            server.submit(r)
+            nxt += 1
+        busy = server.step()
+        if now - t_start > timeout:
             raise TimeoutError(f"open loop: {len(server.completed)} of {n} requests done")
-        if poll_sleep:
-            time.sleep(poll_sleep)
-    th.join()
+        if not busy and nxt < n:
+            wait_until(t_start + times[order[nxt]])

@@ -1,8 +1,10 @@
 """Serving scheduler on the CPU with a fake backend: simulated clock, memory budget,
 launch durations and injected launch errors."""
+import time
+
 import pytest
 
-from paper_2604_21984_amd.serve import QUERY, RENDER, Request, Server
+from paper_2604_21984_amd.serve import QUERY, RENDER, Request, Server, run_open_loop
 
 
 class Clock:
@@ -160,3 +162,40 @@ def test_result_callback_replaces_retention():
     assert sorted(rid for rid, _ in got) == [0, 1, 2, 3, 4]
     assert all(r.result is None and r.error is None for r in srv.completed)
     assert dict(got)[4] == ("r", 0, 4)
+
+
+class WallBackend(FakeBackend):
+    """The fake backend on the wall clock: every launch takes `per_launch` seconds."""
+
+    def __init__(self, per_launch=2e-4):
+        super().__init__(None, per_launch=per_launch)
+
+    def now(self):
+        return time.perf_counter()
+
+    def launch_queries(self, reqs, sets):
+        self.launched.append([r.rid for r in reqs])
+        return {"t_end": time.perf_counter() + self.per_launch, "reqs": reqs,
+                "outs": [None] * len(reqs)}
+
+    def launch_render(self, req, rset):
+        return self.launch_queries([req], None)
+
+    def done(self, h):
+        return time.perf_counter() >= h["t_end"]
+
+
+def test_open_loop_arrivals_are_scheduled_times():
+    """The open-loop driver stamps each request with its scheduled arrival (start +
+    times[i], in any submission order) and counts latency from there."""
+    be = WallBackend()
+    srv = Server(be, [FakeSet(0)], mem_budget=1 << 20, on_result=lambda r, out: None)
+    times = [0.004, 0.0, 0.002, 0.006]
+    reqs = [_q(i, 0, 10) for i in range(4)]
+    t0 = time.perf_counter()
+    run_open_loop(srv, reqs, times, timeout=10.0)
+    starts = [r.t_arrival - times[i] for i, r in enumerate(reqs)]
+    assert max(starts) - min(starts) < 1e-9 and starts[0] >= t0
+    assert all(r.t_done >= r.t_arrival + be.per_launch for r in reqs)
+    assert all(r.latency < 1.0 and r.error is None for r in reqs)
+    assert sorted(sum(be.launched, [])) == [0, 1, 2, 3]
