@@ -374,6 +374,24 @@ sad_status sad_batch_train_step(const sad_batch *batch, const sad_train_config *
 sad_status sad_site_stats(const sad_image *img, const float *rec, const uint32_t *topk,
                           const float *target, float *stats, void *stream);
 
+/* Order-independent form of sad_site_stats (Sec. 4.5, App. B.5: the same statistics),
+ * for deterministic encodes.  Every term is rounded once to its statistic's unit 2^-s
+ * (s = 40, 40, 36, 36, 30, 30, 30 for stats[0..6] and 40 + e for stats[7], 2^e the
+ * largest power of two below H W), and all sums are integer: per tile in LDS, over
+ * tiles exactly in 128 bits.  So the statistics depend only on the inputs, not on
+ * scheduling; they differ from sad_site_stats's by the per-term rounding (at most
+ * 2^-(s+1) per term).
+ * acc: DEVICE int64[2][8][cap] workspace (16 * 8 * cap bytes, 8-byte aligned), cleared
+ *   by the call; on return acc[0][q][i] + 2^64 acc[1][q][i] is the sum of
+ *   stats[q][i] in units of 2^-s.
+ * stats: float[8][cap], WRITTEN (=) for every slot 0..cap-1 (zero where no pixel
+ *   lists the slot), not accumulated.
+ * Errors: SAD_ERR_INVALID_ARGUMENT for NULL target, acc or stats, NULL or unaligned
+ * rec / topk when n_slots > 0, a misaligned acc, or a bad descriptor. */
+sad_status sad_site_stats_fixed(const sad_image *img, const float *rec, const uint32_t *topk,
+                                const float *target, int64_t *acc, float *stats,
+                                void *stream);
+
 /* One budget step on slots 0..cap-1 (img->n_slots is not used; img->K only for
  * seeding).  With n_active the number of active slots:
  *   SAD_DP_PRUNE: the floor(p_prune n_active) active sites with the smallest removal

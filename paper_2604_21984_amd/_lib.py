@@ -90,6 +90,7 @@ def _load():
         "sad_train_image_pass": [IMG, C.POINTER(SadTrainConfig), P, P, P, P, P, P, P, P, P],
         "sad_query_batch": [P, I32, I64, I32, P],
         "sad_site_stats": [IMG, P, P, P, P, P],
+        "sad_site_stats_fixed": [IMG, P, P, P, P, P, P],
         "sad_exact_topk": [IMG, P, P, I64, P, P],
         "sad_densify_prune": [IMG, P, P, P, P, P, C.POINTER(SadBudgetParams), P, P, P,
                               C.POINTER(SZ), P],
@@ -334,6 +335,20 @@ def site_stats(img, rec, topk, target, stats):
                               _ptr(target, torch.float32, 3 * P, "target"),
                               _ptr(stats, torch.float32, NSTAT * img.cap, "stats"), _stream()),
            "sad_site_stats")
+
+
+def site_stats_fixed(img, rec, topk, target, acc, stats):
+    """Write the per-site statistics into stats [8, cap] with integer sums that do not
+    depend on scheduling (sad_site_stats_fixed); acc: int64 workspace of 16 * cap."""
+    P = img.H * img.W
+    _check(lib.sad_site_stats_fixed(C.byref(img),
+                                    _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                                    _ptr(topk, torch.int32, img.K * P, "topk"),
+                                    _ptr(target, torch.float32, 3 * P, "target"),
+                                    _ptr(acc, torch.int64, 2 * NSTAT * img.cap, "acc"),
+                                    _ptr(stats, torch.float32, NSTAT * img.cap, "stats"),
+                                    _stream()),
+           "sad_site_stats_fixed")
 
 
 def budget_params(p_prune, p_split, flags, alpha=0.7, eps=1e-8, min_mass=1.0):

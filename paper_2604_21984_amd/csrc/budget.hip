@@ -45,12 +45,36 @@ static StatScale stat_scale(int64_t P) {
     return sc;
 }
 
-template <int K>
+// Exact 128-bit sum in two 64-bit planes: lo accumulates modulo 2^64 and hi takes each
+// add's carry out of lo plus the sign extension of the term, so hi * 2^64 + lo is the
+// integer sum of the terms whatever the order of the adds.
+__device__ __forceinline__ void wide_add(unsigned long long *__restrict__ lo,
+                                         unsigned long long *__restrict__ hi, int64_t idx,
+                                         long long u) {
+    const unsigned long long old = atomicAdd(lo + idx, (unsigned long long)u);
+    const long long hd = (old + (unsigned long long)u < old ? 1 : 0) + (u < 0 ? -1 : 0);
+    if (hd) atomicAdd(hi + idx, (unsigned long long)hd);
+}
+
+// A term in units of 2^-s, rounded once (clamped to +-2^62; below the LDS limit this is
+// the same integer to_fixed forms).
+__device__ __forceinline__ long long fixed_term(float v, double to) {
+    double x = rint((double)v * to);
+    x = fmin(fmax(x, -0x1p62), 0x1p62);
+    return (long long)x;
+}
+
+// kFixed: every term is rounded once to its statistic's unit and every sum is an
+// integer (tile sums in LDS, the sum over tiles exact in acc = lo[8][cap], hi[8][cap]),
+// so the sums do not depend on the order in which tiles and lanes add.
+template <int K, bool kFixed>
 __global__ __launch_bounds__(256) void k_stats(ImgArgs a, StatScale sc,
                                                const float4 *__restrict__ rec,
                                                const uint4 *__restrict__ topk,
                                                const float *__restrict__ tgt,
-                                               float *__restrict__ stats) {
+                                               float *__restrict__ stats,
+                                               unsigned long long *__restrict__ acc) {
+    unsigned long long *acc_hi = acc + (int64_t)kNStat * a.cap;
     __shared__ uint32_t hkey[kHashSlots];
     __shared__ unsigned long long hacc[kNStat][kHashSlots];
     const int t = threadIdx.x;
@@ -137,8 +161,12 @@ __global__ __launch_bounds__(256) void k_stats(ImgArgs a, StatScale sc,
                 for (int q = 0; q < kNStat; ++q) {
                     if (slot >= 0 && fabsf(v[q]) < sc.limit[q])
                         atomicAdd(&hacc[q][slot], to_fixed(v[q], sc.to[q]));
-                    else if (v[q] != 0.0f)
-                        atomic_add_f32(stats + q * a.cap + id, v[q]);
+                    else if (v[q] != 0.0f) {
+                        if (kFixed)
+                            wide_add(acc, acc_hi, q * a.cap + id, fixed_term(v[q], sc.to[q]));
+                        else
+                            atomic_add_f32(stats + q * a.cap + id, v[q]);
+                    }
                 }
             }
         }
@@ -149,8 +177,29 @@ __global__ __launch_bounds__(256) void k_stats(ImgArgs a, StatScale sc,
 #pragma unroll
     for (int q = 0; q < kNStat; ++q) {
         const unsigned long long u = hacc[q][t];
-        if (u) atomic_add_f32(stats + q * a.cap + id, from_fixed(u, sc.from[q]));
+        if (!u) continue;
+        if (kFixed)  // a tile sum is below 2^62 in magnitude: one signed 64-bit term
+            wide_add(acc, acc_hi, q * a.cap + id, (long long)u);
+        else
+            atomic_add_f32(stats + q * a.cap + id, from_fixed(u, sc.from[q]));
     }
+}
+
+__global__ __launch_bounds__(256) void k_zero_u64(unsigned long long *__restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// stats[q][i] = (hi * 2^64 + lo) * 2^-s_q, rounded to float (through double: the same
+// exact sum always gives the same float).
+__global__ __launch_bounds__(256) void k_stats_out(StatScale sc, const unsigned long long *__restrict__ acc,
+                                                  int64_t cap, float *__restrict__ stats) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kNStat * cap) return;
+    const int q = (int)(i / cap);
+    const double hi = (double)(long long)acc[kNStat * cap + i];
+    const double lo = (double)acc[i];
+    stats[i] = (float)(fma(hi, 0x1p64, lo) * sc.from[q]);
 }
 
 // ---- budget step --------------------------------------------------------------------
@@ -475,9 +524,40 @@ extern "C" sad_status sad_site_stats(const sad_image *img, const float *rec, con
     hipStream_t st = as_stream(stream);
     const float4 *r4 = reinterpret_cast<const float4 *>(rec);
     const uint4 *l4 = reinterpret_cast<const uint4 *>(topk);
-    SAD_K_SWITCH(img->K, hipLaunchKernelGGL(k_stats<KK>, dim3(a.n_blocks), dim3(256), 0, st, a, sc,
-                                            r4, l4, target, stats));
+    SAD_K_SWITCH(img->K, hipLaunchKernelGGL((k_stats<KK, false>), dim3(a.n_blocks), dim3(256), 0,
+                                            st, a, sc, r4, l4, target, stats, nullptr));
     return check_launch("sad_site_stats");
+}
+
+extern "C" sad_status sad_site_stats_fixed(const sad_image *img, const float *rec,
+                                           const uint32_t *topk, const float *target,
+                                           int64_t *acc, float *stats, void *stream) {
+    SAD_TRY(check_image(img, nullptr));
+    SAD_REQUIRE(stats && target && acc, SAD_ERR_INVALID_ARGUMENT,
+                "sad_site_stats_fixed: NULL pointer");
+    SAD_REQUIRE(((uintptr_t)acc & 7) == 0, SAD_ERR_INVALID_ARGUMENT,
+                "sad_site_stats_fixed: acc must be 8-byte aligned");
+    if (img->n_slots > 0)
+        SAD_REQUIRE(rec && topk && aligned16(rec) && aligned16(topk), SAD_ERR_INVALID_ARGUMENT,
+                    "sad_site_stats_fixed: rec and topk must be non-NULL and 16-byte aligned");
+    const ImgArgs a = img_args(img);
+    const StatScale sc = stat_scale((int64_t)img->H * img->W);
+    hipStream_t st = as_stream(stream);
+    unsigned long long *acc64 = reinterpret_cast<unsigned long long *>(acc);
+    const int64_t n = 2ll * kNStat * img->cap, n_out = (int64_t)kNStat * img->cap;
+    if (n > 0)
+        hipLaunchKernelGGL(k_zero_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, acc64,
+                           n);
+    if (img->n_slots > 0) {
+        const float4 *r4 = reinterpret_cast<const float4 *>(rec);
+        const uint4 *l4 = reinterpret_cast<const uint4 *>(topk);
+        SAD_K_SWITCH(img->K, hipLaunchKernelGGL((k_stats<KK, true>), dim3(a.n_blocks), dim3(256),
+                                                0, st, a, sc, r4, l4, target, stats, acc64));
+    }
+    if (n_out > 0)
+        hipLaunchKernelGGL(k_stats_out, dim3((unsigned)((n_out + 255) / 256)), dim3(256), 0, st,
+                           sc, acc64, (int64_t)img->cap, stats);
+    return check_launch("sad_site_stats_fixed");
 }
 
 extern "C" sad_status sad_densify_prune(const sad_image *img, const float *target, float *sites,

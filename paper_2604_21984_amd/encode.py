@@ -65,7 +65,7 @@ class EncodeConfig:
     score_scale: float = 0.0       # 0: 1 / max(H, W)
     budget: BudgetSchedule = None  # adaptive budget (None: fixed site count)
     prop_every: int = 1            # candidate update period f_cand (App. B.3)
-    deterministic: bool = False    # bit-reproducible gradient sums (int64 accumulator)
+    deterministic: bool = False    # bit-reproducible gradient and statistics sums (integer)
 
 
 def default_log_tau(H, W, N):
@@ -119,6 +119,8 @@ class Encoder:
         self.budget_log = []
         if cfg.budget:
             self.stats = torch.zeros((S.NSTAT, cap), **f32)
+            if cfg.deterministic:
+                self.stats_acc = torch.empty(2 * S.NSTAT * cap, dtype=torch.int64, device=dev)
             self.counts = torch.zeros(6, dtype=torch.int64, device=dev)
             self.dp_ws = torch.empty(S.densify_workspace_bytes(self.img), dtype=torch.uint8,
                                      device=dev)
@@ -154,8 +156,12 @@ class Encoder:
         flags = (S.DP_SPLIT if densify else 0) | (S.DP_PRUNE if prune else 0)
         if bs.seed_lists and densify:
             flags |= S.DP_SEED
-        self.stats.zero_()
-        S.site_stats(self.img, self.rec, self.topk, self.target, self.stats)
+        if self.cfg.deterministic:  # integer sums: the budget step is reproducible too
+            S.site_stats_fixed(self.img, self.rec, self.topk, self.target, self.stats_acc,
+                               self.stats)
+        else:
+            self.stats.zero_()
+            S.site_stats(self.img, self.rec, self.topk, self.target, self.stats)
         prm = S.budget_params(bs.p_prune, bs.p_split, flags, bs.alpha, bs.eps, bs.min_mass)
         S.densify_prune(self.img, self.target, self.sites, self.m, self.v, self.stats, prm,
                         self.topk, self.counts, self.dp_ws)

@@ -88,5 +88,9 @@ def test_host_validation_of_state_forms_and_flags(lib):
     assert lib.sad_train_image_pass(C.byref(ok), C.byref(cfg), p, p, p, q, p, None, None, p,
                                     None) == 1
     assert b"unknown flags" in lib.sad_last_error()
+    # fixed-point statistics: NULL or misaligned workspace
+    assert lib.sad_site_stats_fixed(C.byref(ok), p, p, p, None, p, None) == 1
+    assert lib.sad_site_stats_fixed(C.byref(ok), p, p, p, C.c_void_p(base + 4), p, None) == 1
+    assert b"8-byte aligned" in lib.sad_last_error()
     assert S.train_config(4, 0, params, deterministic=True).flags == S.TRAIN_DETERMINISTIC
     assert S.train_config(4, 0, params).flags == 0

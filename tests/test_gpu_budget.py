@@ -61,6 +61,62 @@ def test_site_stats_match_oracle(S, H, W, N, K, holes):
     assert (got[:, N:] == 0).all()                      # slots beyond n_slots untouched
 
 
+@pytest.mark.parametrize("H,W,N,K,holes", [(48, 64, 120, 4, 0), (70, 45, 200, 8, 17),
+                                           (33, 50, 90, 16, 5), (16, 16, 3, 8, 0)])
+def test_site_stats_fixed_match_oracle_and_repeat(S, H, W, N, K, holes):
+    """Integer-sum statistics: within the float32 bound of the oracle plus the per-term
+    rounding to each statistic's unit, written (not accumulated) for every slot, and
+    bit-identical from call to call."""
+    sites, tg, s, lists = _case(H + W, H, W, N, K, cap=N + 7, holes=holes)
+    ref, sabs, sens = O.site_stats(H, W, K, s, sites, N, lists, tg, scales=True)
+    cap = N + 7
+    img = S.image(H, W, K, N, cap)
+    rec = torch.empty(max(N, 1) * S.REC_FLOATS, dtype=torch.float32, device=DEV)
+    S.prepare_sites(img, torch.from_numpy(sites).to(DEV), rec)
+    topk = torch.from_numpy(rows_to_planar(lists, H, W, K)).to(DEV)
+    tgt = torch.from_numpy(tg).to(DEV)
+    outs = []
+    for fill in (float("nan"), 7.0):   # stale contents of stats and acc are overwritten
+        stats = torch.full((S.NSTAT, cap), fill, dtype=torch.float32, device=DEV)
+        acc = torch.full((2 * S.NSTAT * cap,), 12345, dtype=torch.int64, device=DEV)
+        S.site_stats_fixed(img, rec, topk, tgt, acc, stats)
+        torch.cuda.synchronize()
+        outs.append(stats.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+    got = outs[0].astype(np.float64)
+    e = 0
+    while (1 << (e + 1)) < H * W:
+        e += 1
+    unit = 2.0 ** -np.array([40, 40, 36, 36, 30, 30, 30, 40 + e], dtype=np.float64)
+    floor = 1e-7 * np.abs(ref).max(axis=1, keepdims=True)
+    tol = (1e-4 * np.abs(ref) + 2e-5 * sabs + 1e-5 * sens + floor +
+           0.5 * H * W * unit[:, None])
+    bad = np.abs(got - ref) > tol
+    assert not bad.any(), [(q, i, got[q, i], ref[q, i], tol[q, i]) for q, i in zip(*np.where(bad))][:5]
+    assert (got[:, N:] == 0).all()                      # slots beyond n_slots written zero
+
+
+def test_deterministic_encode_with_budget_is_reproducible(S):
+    """A deterministic encode with prune / split events: two runs from the same seed end
+    with bit-identical sites, lists and budget counts."""
+    from paper_2604_21984_amd import encode as E
+    H, W = 96, 128
+    tg = torch.from_numpy(synth.image_encode(4, H, W, n_polygons=25, patch=16)).to(DEV)
+    sched = E.BudgetSchedule(densify_every=10, densify_start=10, densify_end=40, p_split=0.1,
+                             prune_every=20, prune_start=20, prune_end=40, p_prune=0.05)
+    cfg = E.EncodeConfig(K=8, n_inject=4, seed=3, budget=sched, deterministic=True)
+    a, b = (E.Encoder(tg, 300, cfg, cap=900) for _ in range(2))
+    for _ in range(45):
+        a.step()
+        b.step()
+    torch.cuda.synchronize()
+    assert [h["counts"] for h in a.budget_log] == [h["counts"] for h in b.budget_log]
+    assert len(a.budget_log) == 4
+    assert torch.equal(a.stats, b.stats)
+    for x, y in ((a.sites, b.sites), (a.m, b.m), (a.v, b.v), (a.topk, b.topk)):
+        assert torch.equal(x, y)
+
+
 def _run_dp(S, H, W, K, sites, tg, stats, p_prune, p_split, flags, lists=None):
     cap = sites.shape[1]
     img = S.image(H, W, K, cap, cap)
