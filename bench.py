@@ -434,6 +434,37 @@ def serving(rates, seconds, seed=0):
     return out
 
 
+def paper_context(result):
+    """The paper's own timings (Sec. 6; other hardware, for context only, never a
+    target) beside this run's figures for the same workloads, where this run measured
+    them."""
+    def get(*keys):
+        d = result
+        for k in keys:
+            if not isinstance(d, dict) or k not in d:
+                return None
+            d = d[k]
+        return d
+
+    def ms(us):
+        return None if us is None else round(us / 1e3, 4)
+
+    return {
+        "note": "the paper's figures are on an NVIDIA RTX 5090 (Sec. 6) unless marked; "
+                "context, not targets",
+        "train_iteration_2048x2048_1bpp_K8_ms": {
+            "paper": 3.6, "paper_hw": "RTX 5090 (one training epoch)",
+            "here": get("large_image", "k8_n32768", "ms_per_step")},
+        "render_only_2048x2048_ms": {
+            "paper": 0.132, "paper_hw": "RTX 5090",
+            "here": ms(get("large_image", "k8_n32768", "render_us"))},
+        "encode_768x512_50k_sites_4000_iterations_s": {
+            "paper": 2.2, "paper_hw": "not stated (Kodak, densify and prune included)",
+            "here": (None if get("whole_encode", "n50000", "iterations_ms") is None else
+                     round(get("whole_encode", "n50000", "iterations_ms") / 1e3, 4)),
+            "here_note": "synthetic 768x512 target, no budget schedule"}}
+
+
 def plain_loop(sets, reqs, times):
     """Baseline for the server: every request alone, in arrival order, on the current
     stream (``sad_query_points`` or ``sad_render_fwd``), synchronised before the next
@@ -704,6 +735,7 @@ def main():
                                             f"same 768x512 workload in {el:.1f} s, single thread",
                                   "cpu": cpu, "host_threads": os.cpu_count(),
                                   "platform": platform.machine()}
+    result["paper_context"] = paper_context(result)
     print(json.dumps(result), flush=True)
 
 
