@@ -216,6 +216,41 @@ def deterministic_mode(steps, seed=0):
             "iterations": 20 + 10 * max(1, steps // 10), "two_runs_bit_identical": same}
 
 
+def large_encode_budget(steps, seed=1):
+    """The large-image encode with budget control, whole: 2048x2048, K = 16, 100 000
+    sites at the start, capacity 400 000, a prune / split event every 100 iterations
+    (prune 1 %, split 6 % of the active sites, as many as free slots allow), `steps`
+    iterations from scratch, eager (each event changes the slot range), initialisation
+    included."""
+    import torch
+
+    import synth
+    from paper_2604_21984_amd.encode import BudgetSchedule, EncodeConfig, Encoder
+    Hl = Wl = 2048
+    target = torch.from_numpy(synth.image_large(seed, Hl, Wl)).cuda()
+    sched = BudgetSchedule(densify_every=100, densify_start=100, densify_end=steps,
+                           p_split=0.06, prune_every=100, prune_start=100,
+                           prune_end=steps + 1, p_prune=0.01)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    enc = Encoder(target, 100_000, EncodeConfig(K=16, n_inject=J, seed=seed, budget=sched),
+                  cap=400_000)
+    for i in range(steps):
+        enc.step()
+        if (i + 1) % 1000 == 0:
+            torch.cuda.synchronize()
+            print(f"bench: large encode iteration {i + 1}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    active = [h["counts"][3] for h in enc.budget_log]
+    return {"H": Hl, "W": Wl, "K": 16, "n_sites_start": 100_000, "cap": 400_000,
+            "iterations": steps, "budget_events": len(enc.budget_log),
+            "active_sites_end": active[-1] if active else 100_000,
+            "active_sites_max": max(active) if active else 100_000,
+            "total_s": round(el, 3), "ms_per_iteration": round(1e3 * el / steps, 4),
+            "mpix_s": round(Hl * Wl * steps / (el * 1e6), 1), "psnr_db": round(enc.psnr(), 3)}
+
+
 def large_image(steps, seed=1):
     """Whole iterations (graph replay, as the headline) on 2048x2048 images: K = 16 at
     100 000 and at 400 000 sites (the start and the cap of the large-image encode with
@@ -571,6 +606,9 @@ def main():
                     help="only run 5 plain device copies of MIB MiB (calibrates HBM counters)")
     ap.add_argument("--autograd-steps", type=int, default=50,
                     help="iterations through the autograd wrappers (0: skip)")
+    ap.add_argument("--large-encode-steps", type=int, default=3000,
+                    help="iterations of the 2048x2048 K = 16 encode with budget control "
+                         "(0: skip)")
     ap.add_argument("--encode-iterations", type=int, default=2000,
                     help="iterations of the whole-encode timing from scratch (0: skip)")
     ap.add_argument("--det-steps", type=int, default=100,
@@ -736,6 +774,8 @@ def main():
         extra("deterministic", deterministic_mode, args.det_steps)
     if args.large_steps > 0:
         extra("large_image", large_image, args.large_steps)
+    if args.large_encode_steps > 0:
+        extra("large_encode_budget", large_encode_budget, args.large_encode_steps)
     if args.batch_steps > 0:
         extra("batched", batched_vs_loop, args.batch_steps)
     if args.serve_seconds > 0:
