@@ -98,37 +98,40 @@ struct AdamArgs {
 
 // Adam on slot i of one image's [10][cap] buffers (site order of App. B.2), then clamps
 // and renormalised u; inactive slots are left untouched.  The gradient is [10][cap] or,
-// with A.grad_site_major, [cap][10].  step_dev, if set, holds the number of steps taken
-// so far.
-__device__ __forceinline__ void adam_site(float *__restrict__ sites, float *__restrict__ grad,
-                                          float *__restrict__ m, float *__restrict__ v,
-                                          int64_t cap, int64_t i, int H, int W, const AdamArgs &A,
-                                          const int64_t *step_dev, float s,
-                                          float4 *__restrict__ rec) {
+// with A.grad_site_major, [cap][10]; kFixed: int64 elements worth A.grad_from each.
+// step_dev, if set, holds the number of steps taken so far.  Every operand is loaded
+// before anything depends on one (the activity test included), so the loads share one
+// memory latency, and the double pow of a device-side step overlaps it.
+template <bool kFixed>
+__device__ __forceinline__ void adam_site_impl(float *__restrict__ sites,
+                                               float *__restrict__ grad,
+                                               float *__restrict__ m, float *__restrict__ v,
+                                               int64_t cap, int64_t i, int H, int W,
+                                               const AdamArgs &A, const int64_t *step_dev,
+                                               float s, float4 *__restrict__ rec) {
     const int64_t gs = A.grad_site_major ? 1 : cap;             // parameter stride
     const int64_t g0 = A.grad_site_major ? i * SAD_NPARAM : i;  // first element of site i
     long long *g64 = reinterpret_cast<long long *>(grad);
-    if (!(sites[i] >= 0.0f)) {  // inactive slot: parameters untouched
-        if (A.zero_grad)
-            for (int p = 0; p < SAD_NPARAM; ++p) {
-                if (A.grad_fixed)
-                    g64[g0 + p * gs] = 0;
-                else
-                    grad[g0 + p * gs] = 0.0f;
-            }
-        if (rec) write_record(sites, cap, i, s, rec);
-        return;
-    }
-    // every operand is loaded before the bias corrections are formed, so the double
-    // pow of a device-side step overlaps the loads' latency
     float g[SAD_NPARAM], m0[SAD_NPARAM], v0[SAD_NPARAM], x0[SAD_NPARAM];
 #pragma unroll
     for (int p = 0; p < SAD_NPARAM; ++p) {
         const int64_t o = p * cap + i;
-        g[p] = A.grad_fixed ? (float)((double)g64[g0 + p * gs] * A.grad_from) : grad[g0 + p * gs];
+        g[p] = kFixed ? (float)((double)g64[g0 + p * gs] * A.grad_from) : grad[g0 + p * gs];
         m0[p] = m[o];
         v0[p] = v[o];
         x0[p] = sites[o];
+    }
+    if (A.zero_grad)
+#pragma unroll
+        for (int p = 0; p < SAD_NPARAM; ++p) {
+            if (kFixed)
+                g64[g0 + p * gs] = 0;
+            else
+                grad[g0 + p * gs] = 0.0f;
+        }
+    if (!(x0[0] >= 0.0f)) {  // inactive slot: parameters untouched
+        if (rec) record_of(x0, i, s, rec);
+        return;
     }
     float c1 = A.c1, c2 = A.c2;
     if (step_dev) {
@@ -143,12 +146,6 @@ __device__ __forceinline__ void adam_site(float *__restrict__ sites, float *__re
 #pragma unroll
     for (int p = 0; p < SAD_NPARAM; ++p) {
         const int64_t o = p * cap + i;
-        if (A.zero_grad) {
-            if (A.grad_fixed)
-                g64[g0 + p * gs] = 0;
-            else
-                grad[g0 + p * gs] = 0.0f;
-        }
         const float mm = A.b1 * m0[p] + (1.0f - A.b1) * g[p];
         const float vv = A.b2 * v0[p] + (1.0f - A.b2) * g[p] * g[p];
         m[o] = mm;
@@ -169,6 +166,17 @@ __device__ __forceinline__ void adam_site(float *__restrict__ sites, float *__re
 #pragma unroll
     for (int p = 0; p < SAD_NPARAM; ++p) sites[p * cap + i] = th[p];
     if (rec) record_of(th, i, s, rec);  // from the registers, not re-read
+}
+
+__device__ __forceinline__ void adam_site(float *__restrict__ sites, float *__restrict__ grad,
+                                          float *__restrict__ m, float *__restrict__ v,
+                                          int64_t cap, int64_t i, int H, int W, const AdamArgs &A,
+                                          const int64_t *step_dev, float s,
+                                          float4 *__restrict__ rec) {
+    if (A.grad_fixed)  // uniform: one straight-line copy per gradient type
+        adam_site_impl<true>(sites, grad, m, v, cap, i, H, W, A, step_dev, s, rec);
+    else
+        adam_site_impl<false>(sites, grad, m, v, cap, i, H, W, A, step_dev, s, rec);
 }
 
 }  // namespace sad
