@@ -256,7 +256,8 @@ def large_image(steps, seed=1):
     100 000 and at 400 000 sites (the start and the cap of the large-image encode with
     budget control), and K = 8 at 32 768 sites (1 bit per pixel, the workload of the
     paper's per-epoch training time); then decoding from each one's cached lists: a full
-    render and one million random point queries."""
+    render and one million random point queries; and the budget's statistics pass over
+    them."""
     import torch
 
     import synth
@@ -310,7 +311,22 @@ def large_image(steps, seed=1):
         out[name]["render_us"] = round(r_us, 1)
         out[name]["render_gpix_s"] = round(Hl * Wl / r_us / 1e3, 2)
         out[name]["query_1m_points_us"] = round(q_us, 1)
-        del enc
+        # the budget's statistics pass over the same lists, float and integer sums
+        n_cap = enc.img.cap
+        stats = torch.zeros((S.NSTAT, n_cap), dtype=torch.float32, device="cuda")
+        acc = torch.empty(2 * S.NSTAT * n_cap, dtype=torch.int64, device="cuda")
+        for key, fn in (("stats_us", lambda: S.site_stats(enc.img, enc.rec, enc.topk,
+                                                          enc.target, stats)),
+                        ("stats_fixed_us", lambda: S.site_stats_fixed(
+                            enc.img, enc.rec, enc.topk, enc.target, acc, stats))):
+            fn()
+            e0.record()
+            for _ in range(10):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            out[name][key] = round(e0.elapsed_time(e1) * 1e3 / 10, 1)
+        del enc, stats, acc
         torch.cuda.empty_cache()
     return out
 
