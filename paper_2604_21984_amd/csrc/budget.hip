@@ -67,11 +67,12 @@ __device__ __forceinline__ long long fixed_term(float v, double to) {
 // kFixed: every term is rounded once to its statistic's unit and every sum is an
 // integer (tile sums in LDS, the sum over tiles exact in acc = lo[8][cap], hi[8][cap]),
 // so the sums do not depend on the order in which tiles and lanes add.
-// For K = 12..16 the register budget is held to two waves per SIMD (K = 16 needs 262
-// registers uncapped, one wave per SIMD; capped it keeps 254 and spills 6): twice the
-// waves to hide the record gathers, 42 % less time at 2048x2048.
+// Register budgets: four waves per SIMD up to K = 8 (K = 8 needs 132 registers
+// uncapped, three waves; capped 128 and 5 spilled: 12 % less time at 2048x2048) and
+// two for K = 12..16 (K = 16 needs 262 uncapped, one wave; capped 254 and 6 spilled:
+// 42 % less time at 2048x2048) -- more waves to hide the record gathers.
 template <int K, bool kFixed>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K >= 12 && K <= 16 ? 2 : 1, 8))) void k_stats(ImgArgs a, StatScale sc,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8 ? 4 : (K <= 16 ? 2 : 1), 8))) void k_stats(ImgArgs a, StatScale sc,
                                                const float4 *__restrict__ rec,
                                                const uint4 *__restrict__ topk,
                                                const float *__restrict__ tgt,
