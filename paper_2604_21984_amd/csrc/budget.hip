@@ -195,15 +195,19 @@ __global__ __launch_bounds__(256) void k_zero_u64(unsigned long long *__restrict
 }
 
 // stats[q][i] = (hi * 2^64 + lo) * 2^-s_q, rounded to float (through double: the same
-// exact sum always gives the same float).
+// exact sum always gives the same float).  With lo read as signed, the sum is
+// (hi + [lo < 0]) * 2^64 + lo_signed; a sum that fits in 64 bits (high part 0) is
+// converted from the signed low word directly, so small negative sums do not cancel
+// against 2^64 (unsigned lo just below 2^64 would round to a multiple of 2^12 units).
 __global__ __launch_bounds__(256) void k_stats_out(StatScale sc, const unsigned long long *__restrict__ acc,
                                                   int64_t cap, float *__restrict__ stats) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= kNStat * cap) return;
     const int q = (int)(i / cap);
-    const double hi = (double)(long long)acc[kNStat * cap + i];
-    const double lo = (double)acc[i];
-    stats[i] = (float)(fma(hi, 0x1p64, lo) * sc.from[q]);
+    const long long lo = (long long)acc[i];
+    const long long hi = (long long)acc[kNStat * cap + i] + (lo < 0 ? 1 : 0);
+    const double sum = hi == 0 ? (double)lo : fma((double)hi, 0x1p64, (double)lo);
+    stats[i] = (float)(sum * sc.from[q]);
 }
 
 // ---- budget step --------------------------------------------------------------------
