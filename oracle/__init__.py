@@ -75,8 +75,16 @@ def lib():
         L.ora_densify_prune.argtypes = [i32, i32, i32, _f32p, _f32p, i64, _opt(_f32p),
                                         _opt(_f32p), _f32p, f64, f64, f64, f64, f64, i32,
                                         _opt(_u32p), _i64p]
+        L.ora_set_threads.argtypes = [i32]
+        L.ora_set_threads.restype = i32
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """Threads of the oracle's per-pixel loops (1 = one core); returns the previous
+    number.  n <= 0 only queries it."""
+    return int(lib().ora_set_threads(int(n)))
 
 
 def _sites(sites):

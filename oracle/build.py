@@ -12,12 +12,12 @@ SRC = os.path.join(HERE, "sad_oracle.c")
 LIB = os.path.join(HERE, "liboracle_sad.so")
 
 CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-          "-frounding-math", "-fno-strict-aliasing", "-Wall", "-Wno-unused-function"]
+          "-frounding-math", "-fno-strict-aliasing", "-fopenmp", "-Wall", "-Wno-unused-function"]
 
 
 def build(verbose: bool = False) -> str:
     """Compile the oracle library; return its path."""
-    cmd = ["gcc", *CFLAGS, "-o", LIB + ".tmp", SRC, "-lm"]
+    cmd = ["gcc", *CFLAGS, "-o", LIB + ".tmp", SRC, "-lm", "-lgomp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -28,8 +28,15 @@
  * Pixel (row i, column j) is evaluated at the point x = (j, i).
  *
  * Parity status of each function is stated in its comment; the pins live in tests/.
+ *
+ * Threads: loops whose iterations are independent pixels (top-K, seed, propagation,
+ * blend, queries) are split over OpenMP threads; each pixel's result does not depend
+ * on the split.  The backward sums each thread's pixels into its own buffer and adds
+ * the buffers in thread order (double precision; the order of additions depends on the
+ * thread count only).  ora_set_threads(1) runs everything on one core.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -177,18 +184,23 @@ void ora_brute_topk(int H, int W, int K, float s, const float *sites, int64_t ca
                     const int64_t *pix, int64_t npix, uint32_t *out)
 {
     site_t *st = (site_t *)malloc(sizeof(site_t) * (size_t)(n > 0 ? n : 1));
-    cand_t *c = (cand_t *)malloc(sizeof(cand_t) * (size_t)(n > 0 ? n : 1));
     for (int64_t i = 0; i < n; ++i) st[i] = site_load(sites, cap, i, s);
     int64_t total = pix ? npix : (int64_t)H * W;
-    for (int64_t q = 0; q < total; ++q) {
-        int64_t p = pix ? pix[q] : q;
-        float X = (float)(p % W), Y = (float)(p / W);
-        int nc = 0;
-        for (int64_t i = 0; i < n; ++i)
-            if (st[i].valid) { c[nc].l = score_f32(&st[i], X, Y); c[nc].id = (uint32_t)i; ++nc; }
-        select_topk(c, nc, K, out + q * K);
+#pragma omp parallel
+    {
+        cand_t *c = (cand_t *)malloc(sizeof(cand_t) * (size_t)(n > 0 ? n : 1));
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t q = 0; q < total; ++q) {
+            int64_t p = pix ? pix[q] : q;
+            float X = (float)(p % W), Y = (float)(p / W);
+            int nc = 0;
+            for (int64_t i = 0; i < n; ++i)
+                if (st[i].valid) { c[nc].l = score_f32(&st[i], X, Y); c[nc].id = (uint32_t)i; ++nc; }
+            select_topk(c, nc, K, out + q * K);
+        }
+        free(c);
     }
-    free(st); free(c);
+    free(st);
 }
 
 /* Initial lists (the seed pass of App. B.3): each active site is mapped to the pixel
@@ -213,17 +225,22 @@ void ora_seed(int H, int W, int K, float s, const float *sites, int64_t cap, int
         where[i] = ii * W + jj;
         cnt[where[i]]++;
     }
-    cand_t *c = (cand_t *)malloc(sizeof(cand_t) * (size_t)(n > 0 ? n : 1));
     /* brute force per occupied pixel: gather its sites */
-    for (int64_t p = 0; p < P; ++p) {
-        if (!cnt[p]) continue;
-        float X = (float)(p % W), Y = (float)(p / W);
-        int nc = 0;
-        for (int64_t i = 0; i < n; ++i)
-            if (where[i] == p) { c[nc].l = score_f32(&st[i], X, Y); c[nc].id = (uint32_t)i; ++nc; }
-        select_topk(c, nc, K, lists + p * K);
+#pragma omp parallel
+    {
+        cand_t *c = (cand_t *)malloc(sizeof(cand_t) * (size_t)(n > 0 ? n : 1));
+#pragma omp for schedule(dynamic, 256)
+        for (int64_t p = 0; p < P; ++p) {
+            if (!cnt[p]) continue;
+            float X = (float)(p % W), Y = (float)(p / W);
+            int nc = 0;
+            for (int64_t i = 0; i < n; ++i)
+                if (where[i] == p) { c[nc].l = score_f32(&st[i], X, Y); c[nc].id = (uint32_t)i; ++nc; }
+            select_topk(c, nc, K, lists + p * K);
+        }
+        free(c);
     }
-    free(cnt); free(where); free(st); free(c);
+    free(cnt); free(where); free(st);
 }
 
 /* ------------------------------------------------------------------------------ */
@@ -280,8 +297,11 @@ void ora_prop_pass(int H, int W, int K, float s, const float *sites, int64_t cap
     int64_t P = (int64_t)H * W;
     site_t *st = (site_t *)malloc(sizeof(site_t) * (size_t)(n > 0 ? n : 1));
     for (int64_t i = 0; i < n; ++i) st[i] = site_load(sites, cap, i, s);
-    cand_t *c = (cand_t *)malloc(sizeof(cand_t) * (size_t)(5 * K + J + 1));
     int64_t total = pix ? npix : P;
+#pragma omp parallel
+    {
+    cand_t *c = (cand_t *)malloc(sizeof(cand_t) * (size_t)(5 * K + J + 1));
+#pragma omp for schedule(dynamic, 256)
     for (int64_t q = 0; q < total; ++q) {
         int64_t p = pix ? pix[q] : q;
         int64_t i = p / W, j = p % W;
@@ -306,7 +326,9 @@ void ora_prop_pass(int H, int W, int K, float s, const float *sites, int64_t cap
         }
         select_topk(c, nc, K, out + q * K);
     }
-    free(st); free(c);
+    free(c);
+    }
+    free(st);
 }
 
 /* ------------------------------------------------------------------------------ */
@@ -358,8 +380,9 @@ void ora_render(int H, int W, int K, float s, const float *sites, int64_t cap, i
     int64_t P = (int64_t)H * W;
     site_t *st = (site_t *)malloc(sizeof(site_t) * (size_t)(n > 0 ? n : 1));
     for (int64_t i = 0; i < n; ++i) st[i] = site_load(sites, cap, i, s);
-    pix_t px;
+#pragma omp parallel for schedule(dynamic, 256)
     for (int64_t p = 0; p < P; ++p) {
+        pix_t px;
         blend_pixel(st, n, lists + p * K, K, (double)(p % W), (double)(p / W), s, mode, &px);
         for (int ch = 0; ch < 3; ++ch) out[ch * P + p] = px.c[ch];
     }
@@ -375,8 +398,9 @@ void ora_query(int H, int W, int K, float s, const float *sites, int64_t cap, in
 {
     site_t *st = (site_t *)malloc(sizeof(site_t) * (size_t)(n > 0 ? n : 1));
     for (int64_t i = 0; i < n; ++i) st[i] = site_load(sites, cap, i, s);
-    pix_t px;
+#pragma omp parallel for schedule(dynamic, 256)
     for (int64_t m = 0; m < M; ++m) {
+        pix_t px;
         float x = xy[2 * m], y = xy[2 * m + 1];
         float fi = rintf(y), fj = rintf(x);
         int64_t ii = !(fi > 0) ? 0 : (fi > (float)(H - 1) ? H - 1 : (int64_t)fi);
@@ -469,8 +493,26 @@ void ora_render_bwd(int H, int W, int K, float s, const float *sites, int64_t ca
     int64_t P = (int64_t)H * W;
     site_t *st = (site_t *)malloc(sizeof(site_t) * (size_t)(n > 0 ? n : 1));
     for (int64_t i = 0; i < n; ++i) st[i] = site_load(sites, cap, i, s);
-    pix_t px;
+    int nt = omp_get_max_threads();
+    /* per-thread sums: thread 0 adds into the caller's buffers, the others into their
+     * own, added in thread order at the end */
+    double **tg = (double **)calloc((size_t)nt, sizeof(double *));
+    double **ta = (double **)calloc((size_t)nt, sizeof(double *));
+    double **tr = (double **)calloc((size_t)nt, sizeof(double *));
+    for (int th = 1; th < nt; ++th) {
+        tg[th] = (double *)calloc((size_t)(NPARAM * cap), sizeof(double));
+        if (gabs) ta[th] = (double *)calloc((size_t)(NPARAM * cap), sizeof(double));
+        if (rdelta) tr[th] = (double *)calloc((size_t)cap, sizeof(double));
+    }
+    tg[0] = grad; ta[0] = gabs; tr[0] = rdelta;
+#pragma omp parallel num_threads(nt)
+    {
+    const int th = omp_get_thread_num();
+    double *grad_t = tg[th], *gabs_t = ta[th], *rdelta_t = tr[th];
+#pragma omp for schedule(static)
     for (int64_t p = 0; p < P; ++p) {
+        pix_t px;
+        double *grad = grad_t, *gabs = gabs_t, *rdelta = rdelta_t;
         double X = (double)(p % W), Y = (double)(p / W);
         blend_pixel(st, n, lists + p * K, K, X, Y, s, mode, &px);
         if (!px.nv) continue;
@@ -508,7 +550,24 @@ void ora_render_bwd(int H, int W, int K, float s, const float *sites, int64_t ca
             for (int v = 0; v < px.nv; ++v) rdelta[px.idx[v]] += dl[v] / (double)P;
         }
     }
+    }
+    for (int th = 1; th < nt; ++th) {
+        for (int64_t o = 0; o < NPARAM * cap; ++o) grad[o] += tg[th][o];
+        if (gabs) for (int64_t o = 0; o < NPARAM * cap; ++o) gabs[o] += ta[th][o];
+        if (rdelta) for (int64_t o = 0; o < cap; ++o) rdelta[o] += tr[th][o];
+        free(tg[th]); free(ta[th]); free(tr[th]);
+    }
+    free(tg); free(ta); free(tr);
     free(st);
+}
+
+/* Number of OpenMP threads of the loops above (1 = a single core); returns the number
+ * in force before the call.  n <= 0 only queries it. */
+int ora_set_threads(int n)
+{
+    int old = omp_get_max_threads();
+    if (n > 0) omp_set_num_threads(n);
+    return old;
 }
 
 /* ------------------------------------------------------------------------------ */
