@@ -41,6 +41,17 @@ def test_jump_schedule_context_of_convergence_table():
     assert O.jump(9, 2048, 2048) == 2 and O.jump(10, 2048, 2048) == 1
 
 
+def test_injection_ids_golden():
+    """The counter mapping of the injection draws (which output of the stream, its high
+    word, the multiply-shift to a slot) against IDs derived from the published
+    SplitMix64 outputs."""
+    rows = _golden("inject_ids.txt")
+    assert len(rows) >= 10
+    for seed, t, P, p, J, j, n, want in rows:
+        got = O.inject_id(int(seed), int(t), int(P), int(p), int(J), int(j), int(n))
+        assert got == int(want), (seed, t, P, p, J, j, n, got, want)
+
+
 def test_injection_ids_in_range_and_uniform():
     n = 37
     ids = np.array([O.inject_id(99, t, 1000, p, 4, j, n)
