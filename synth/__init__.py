@@ -251,3 +251,26 @@ def serve_shapes(seed, n_sets=32, lo=512, hi=4096, density=0.05):
     sides = [lo, hi] + [int(round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
                         for _ in range(n_sets - 2)]
     return [(sd, sd, int(round(density * sd * sd))) for sd in sides]
+
+
+def perturb_sites(seed, sites, n, H, W, jitter=0.5, on_centre=0.1, a_range=(-1.5, 1.5),
+                  log_tau_jitter=0.5, r_range=(1.0, 3.0)):
+    """A copy of sites [10, cap] whose first n slots look like a state part-way through
+    an encode: centres moved by U[-jitter, jitter]^2 (a share `on_centre` left exactly
+    on their pixel), random directions, anisotropy uniform in a_range, log_tau moved by
+    U[-log_tau_jitter, log_tau_jitter], r uniform in r_range.  Positions stay inside
+    [0, W-1] x [0, H-1]."""
+    rng = _rng(seed)
+    s = np.array(sites, dtype=np.float32, copy=True)
+    move = rng.uniform(size=n) >= on_centre
+    s[0, :n] = np.where(move, np.clip(s[0, :n] + rng.uniform(-jitter, jitter, n), 0, W - 1),
+                        s[0, :n])
+    s[1, :n] = np.where(move, np.clip(s[1, :n] + rng.uniform(-jitter, jitter, n), 0, H - 1),
+                        s[1, :n])
+    s[2, :n] += rng.uniform(-log_tau_jitter, log_tau_jitter, n)
+    s[3, :n] = rng.uniform(*r_range, n)
+    th = rng.uniform(0, 2 * np.pi, n)
+    s[7, :n] = np.cos(th)
+    s[8, :n] = np.sin(th)
+    s[9, :n] = rng.uniform(*a_range, n)
+    return s

@@ -50,3 +50,20 @@ def grad_report(got, ref, absum=None, rel=1e-4, floor=1e-3):
 
 def grad_close(got, ref, absum=None, rel=1e-4, floor=1e-3):
     return grad_report(got, ref, absum, rel, floor)[0]
+
+
+def grad_check(got, ref, absum, label):
+    """The gradient parity rule of the tests (grad_report with the conditioning term),
+    and beside it the worst ratio under the plain per-group rule without that term.
+    Prints both (and appends them to the JSON-lines file named by SAD_PARITY_LOG, if
+    set); returns (widened, plain, description of the widened worst entries)."""
+    import json
+    import os
+    w, rep = grad_report(got, ref, absum)
+    plain, _ = grad_report(got, ref, None)
+    print(f"PARITY {label}: widened {w:.3g} plain {plain:.3g}", flush=True)
+    path = os.environ.get("SAD_PARITY_LOG")
+    if path:
+        with open(path, "a") as f:
+            f.write(json.dumps({"case": label, "widened": w, "plain": plain}) + "\n")
+    return w, plain, rep
