@@ -42,6 +42,7 @@ class Request:
     result: object = None
     error: str = None
     nbytes: int = 0
+    ready: object = None         # backend marker: the request's inputs are written
 
     @property
     def latency(self):
@@ -78,7 +79,11 @@ def request_bytes(req, rset):
 
 
 class GpuBackend:
-    """Launches on a pool of default-priority HIP streams; completion via events."""
+    """Launches on a pool of default-priority HIP streams; completion via events.
+
+    A request's inputs (the query points) may still be being written on the stream that
+    was current when it was submitted: submit() records an event there, and every launch
+    makes its stream wait for the events of its requests before reading their inputs."""
 
     def __init__(self, device=None, n_streams=4):
         import torch
@@ -92,6 +97,18 @@ class GpuBackend:
 
     def now(self):
         return time.perf_counter()
+
+    def on_submit(self, req):
+        ev = self.torch.cuda.Event()
+        ev.record(self.torch.cuda.current_stream(self.device))
+        req.ready = ev
+
+    def _wait_inputs(self, st, reqs):
+        for r in reqs:
+            if r.ready is not None:
+                st.wait_event(r.ready)
+            if r.xy is not None:
+                r.xy.record_stream(st)   # the allocator keeps xy until st is done with it
 
     def free_bytes(self):
         free, _ = self.torch.cuda.mem_get_info(self.device)
@@ -117,6 +134,7 @@ class GpuBackend:
         if n == 1:  # one request: sad_query_points, with no job table to upload
             r, rs = reqs[0], sets[reqs[0].set_id]
             st = self._stream()
+            self._wait_inputs(st, reqs)
             with torch.cuda.stream(st):
                 out = torch.empty((r.M, 3), dtype=torch.float32, device=self.device)
                 S.query_points(self._image(rs), rs.rec, rs.topk, r.xy, out)
@@ -134,6 +152,7 @@ class GpuBackend:
                                    out.data_ptr(), r.M, q0, rs.H, rs.W, rs.n_slots, 0)
             q0 += r.M
         st = self._stream()
+        self._wait_inputs(st, reqs)
         with torch.cuda.stream(st):
             host = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).pin_memory()
             jobs = host.to(self.device, non_blocking=True)
@@ -145,6 +164,7 @@ class GpuBackend:
     def launch_render(self, req, rset):
         torch, S = self.torch, self.S
         st = self._stream()
+        self._wait_inputs(st, [req])
         with torch.cuda.stream(st):
             out = torch.empty((3, rset.H, rset.W), dtype=torch.float32, device=self.device)
             S.render_fwd(self._image(rset), rset.rec, rset.topk, out)
@@ -186,8 +206,13 @@ class Server:
 
     # ---- intake -------------------------------------------------------------------
     def submit(self, req):
+        """Queue a request.  Its inputs may still be in flight on the submitting stream:
+        the backend (on_submit) marks that point, and launches wait for it."""
         if req.t_arrival == 0.0:
             req.t_arrival = self.backend.now()
+        hook = getattr(self.backend, "on_submit", None)
+        if hook is not None:
+            hook(req)
         with self._lock:
             self._arrivals.append(req)
 

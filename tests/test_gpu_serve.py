@@ -110,3 +110,31 @@ def test_query_batch_direct_with_empty_jobs(sets):
             assert (outs[j] == -7.0).all()       # untouched
         else:
             assert torch.equal(outs[j], _alone(S, rsets[j % len(rsets)], xs[j])), j
+
+
+def test_inputs_written_on_the_submitting_stream(sets):
+    """Query points produced by a kernel that is still queued on the submitting stream
+    (behind a spin kernel) when the request is submitted: every launch waits for them,
+    so each result equals the same query answered after a synchronisation."""
+    from paper_2604_21984_amd import serve as V
+    from paper_2604_21984_amd import _lib as S
+    rsets, _ = sets
+    srv = V.Server(V.GpuBackend(), rsets, mem_budget=64 << 20, max_inflight=4)
+    reqs = []
+    torch.manual_seed(3)
+    for rid in range(6):
+        rs = rsets[rid % len(rsets)]
+        torch.cuda._sleep(int(2e6))          # keeps the stream busy past the submit
+        scale = torch.tensor([rs.W - 1.0, rs.H - 1.0], device=DEV)
+        xy = torch.rand((513, 2), device=DEV) * scale
+        reqs.append(V.Request(rid, rs.set_id, V.QUERY, xy=xy, M=513))
+        srv.submit(reqs[-1])
+        if rid == 0:                         # the first one alone (sad_query_points)
+            srv.drain(timeout=30.0)
+    srv.drain(timeout=30.0)
+    assert max(n for _, n, _ in srv.launches) > 1   # the others shared a launch
+    torch.cuda.synchronize()
+    for r in reqs:
+        assert r.error is None, r.error
+        ref = _alone(S, rsets[r.set_id], r.xy)
+        assert torch.equal(r.result, ref), r.rid
