@@ -250,3 +250,37 @@ def test_densify_prune_large_image_scale(S):
     np.testing.assert_array_equal(gm, am)
     np.testing.assert_array_equal(gv, av)
     np.testing.assert_array_equal(gl, rl)
+
+
+def test_fixed_stats_small_negative_sum_keeps_sign(S):
+    """A cross-moment sum of a few units below zero, formed from two large terms in two
+    tiles: one site at (16, 1) owns every pixel of a 3 x 18 image (two 16 x 16 tiles);
+    the residual is zero except at (x, y) = (15, 0), d_x d_y = +1, e = 2^-8, and at
+    (17, 0), d_x d_y = -1, e = 2^-8 + 2^-28.  S_xy = e_A - e_B = -2^-28 = -4 units of
+    2^-30 exactly; the 128-bit sum over tiles must give it with its sign (a low word
+    read as unsigned would cancel it against 2^64)."""
+    H, W, K, N = 3, 18, 4, 1
+    sites = np.zeros((10, N), np.float32)
+    sites[:, 0] = [16.0, 1.0, 3.0, 1.0, 0.5, 0.5, 0.5, 1.0, 0.0, 0.0]
+    lists = np.full((H * W, K), 0xFFFFFFFF, np.uint32)
+    lists[:, 0] = 0
+    tg = np.full((3, H, W), 0.5, np.float32)
+    tg[0, 0, 15] = 0.5 + 2.0 ** -4
+    tg[0, 0, 17] = 0.5 + 2.0 ** -4
+    tg[1, 0, 17] = 0.5 + 2.0 ** -14
+    s = O.default_scale(H, W)
+    ref = O.site_stats(H, W, K, s, sites, N, lists, tg)
+    assert ref[5, 0] == -(2.0 ** -28)
+    img = S.image(H, W, K, N, N)
+    rec = torch.empty(16, dtype=torch.float32, device=DEV)
+    S.prepare_sites(img, torch.from_numpy(sites).to(DEV), rec)
+    topk = torch.from_numpy(rows_to_planar(lists, H, W, K)).to(DEV)
+    acc = torch.empty(2 * S.NSTAT * N, dtype=torch.int64, device=DEV)
+    stats = torch.empty((S.NSTAT, N), dtype=torch.float32, device=DEV)
+    S.site_stats_fixed(img, rec, topk, torch.from_numpy(tg).to(DEV), acc, stats)
+    torch.cuda.synchronize()
+    got = stats.cpu().numpy()
+    assert got[5, 0] == np.float32(-(2.0 ** -28)), got[5, 0]
+    a = acc.cpu().numpy().reshape(2, S.NSTAT, N)
+    assert a[0, 5, 0] == -4 and a[1, 5, 0] == -1     # low word -4, high word the sign
+    assert got[1, 0] == np.float32(2.0 ** -7 + 2.0 ** -28)   # energy: e_A + e_B
