@@ -38,22 +38,36 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def kernel_fingerprint():
-    """First 16 hex digits of the sha256 of the fused training kernel's sources."""
+    """First 16 hex digits of the sha256 of every library source (the HIP sources and
+    headers and the C ABI header): profiled figures are valid only for the sources they
+    were taken with."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("step.hip", "sad_kernels.h", "sad_device.h"):
-        with open(os.path.join(ROOT, "paper_2604_21984_amd", "csrc", f), "rb") as fh:
+    csrc = os.path.join(ROOT, "paper_2604_21984_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc)
+                   if f.endswith((".hip", ".h")))
+    for path in files + [os.path.join(ROOT, "include", "sad.h")]:
+        with open(path, "rb") as fh:
+            h.update(os.path.basename(path).encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def algorithmic_bytes(kernel, P, N, K):
-    """Bytes a kernel must move per launch, each unique byte once: list field reads and
-    writes, site records, images and gradients (neighbour-list re-reads and repeated
-    site gathers are cache traffic, not counted)."""
+    """Algorithmic bytes per launch, each unique byte once.
+
+    train_pass (one propagation pass + forward + loss gradient + backward, the fused
+    kernel) uses the byte model of the hot path as a step across the autograd boundary:
+    per pixel 8K (list read and written by the pass) + 4K + 12 (forward: list read,
+    colour written) + 4K + 12 (backward: list read, dL/dc read) = 12K + 24 bytes; per
+    site 3 x 40 (the site read by pass, forward and backward) + 44 (gradient row and
+    removal delta written) = 164 bytes.  Neighbour-list re-reads and repeated site
+    gathers are cache traffic, not counted."""
     if kernel == "train_pass":
-        # read the previous list, write the new one, read the target; per site one
-        # derived record in, one gradient row out
+        return P * (12 * K + 24) + N * 164
+    if kernel == "train_pass_unique":
+        # what the fused kernel itself must move: the previous list read, the new one
+        # written, the target read; per site one derived record in, one gradient row out
         return P * (8 * K + 12) + N * (64 + 40)
     if kernel == "adam":
         # sites, m, v read + written, gradient read + cleared, derived record written
@@ -61,23 +75,40 @@ def algorithmic_bytes(kernel, P, N, K):
     return 0
 
 
-def cpu_baseline(target_np, sites_np, lists_np, budget_s):
-    """The CPU oracle (single thread) on whole steps of the same workload."""
-    import numpy as np
-
+def cpu_baseline_inputs(target_np):
+    """Inputs of the CPU baseline, made on the CPU only: the oracle's gradient-weighted
+    initialisation of the workload's sites and its seed pass followed by the first ten
+    passes of the jump schedule (so the timed steps run at jump 1, the steady state)."""
     import oracle as O
     s = O.default_scale(H, W)
+    lt0 = min(max(math.log(2.0 * max(H, W) / math.sqrt(H * W / N_SITES)), 2.0), 20.0)
+    sites, _ = O.init_sites(target_np, N_SITES, 0.3, 0, lt0, 1.0, N_SITES)
+    lists = O.seed_lists(H, W, K, s, sites, N_SITES)
+    for t in range(10):
+        lists = O.prop_pass(H, W, K, s, sites, N_SITES, lists, O.jump(t, H, W), J, 99, t)
+    return sites, lists
+
+
+def cpu_baseline(target_np, sites_np, lists_np, budget_s, threads):
+    """The CPU oracle on whole steps of the same workload (pass + forward + loss +
+    backward), with `threads` OpenMP threads in its per-pixel loops."""
+    import oracle as O
+    s = O.default_scale(H, W)
+    old = O.set_threads(threads)
     lists = lists_np
     steps, t0 = 0, time.perf_counter()
-    while True:
-        lists = O.prop_pass(H, W, K, s, sites_np, N_SITES, lists, 1, J, 99, 1000 + steps)
-        img = O.render(H, W, K, s, sites_np, N_SITES, lists)
-        _, g = O.loss_grad(img, target_np)
-        O.render_bwd(H, W, K, s, sites_np, N_SITES, lists, g)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
+    try:
+        while True:
+            lists = O.prop_pass(H, W, K, s, sites_np, N_SITES, lists, 1, J, 99, 10 + steps)
+            img = O.render(H, W, K, s, sites_np, N_SITES, lists)
+            _, g = O.loss_grad(img, target_np)
+            O.render_bwd(H, W, K, s, sites_np, N_SITES, lists, g)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s:
+                break
+    finally:
+        O.set_threads(old)
     return H * W * steps / el / 1e6, steps, el
 
 
@@ -610,6 +641,33 @@ def topk_quality(trials):
     return out
 
 
+def profile_kernels(enc, n):
+    """The profiling program: n eager launches of the fused pass, then n of Adam, each
+    group between two events; one JSON line with the per-launch averages."""
+    import torch
+
+    from paper_2604_21984_amd import _lib as S
+    img, stream = enc.img, torch.cuda.current_stream()
+    st = enc.counters()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record(stream)
+    for _ in range(n):
+        a, b = enc.lists[enc.cur], enc.lists[1 - enc.cur]
+        S.train_image_pass(img, enc.train_cfg, enc.target, enc.rec, a, b, enc.grad, None, None,
+                           enc.state)
+        enc.cur = 1 - enc.cur
+    ev[1].record(stream)
+    for it in range(n):
+        S.adam_step(img, enc.sites, enc.grad, enc.m, enc.v, enc.adam, st[1] + it + 1, enc.rec,
+                    zero_grad=True, grad_site_major=True)
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    us = {k: round(1e3 * ev[i].elapsed_time(ev[i + 1]) / n, 2)
+          for i, k in enumerate(("train_pass", "adam"))}
+    print(json.dumps({"profile_kernels": n, "per_kernel_us": us,
+                      "kernel_fingerprint": kernel_fingerprint()}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -618,6 +676,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0,
                     help="seconds of single-thread oracle work for the CPU baseline (0: skip)")
     ap.add_argument("--breakdown-steps", type=int, default=20)
+    ap.add_argument("--profile-kernels", type=int, default=0, metavar="N",
+                    help="only the profiling program: eager warm-up iterations, then N "
+                         "launches of the fused pass and N of Adam (no graphs, no spin "
+                         "kernel), for counter collection")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (calibrates HBM counters)")
     ap.add_argument("--autograd-steps", type=int, default=50,
@@ -673,6 +735,9 @@ def main():
     if enc.cur == 1:
         enc.step()
     torch.cuda.synchronize()
+    if args.profile_kernels > 0:
+        profile_kernels(enc, args.profile_kernels)
+        return
     # one graph holds up to a hundred iterations (the list field ping-pongs, so an even
     # number; longer graphs amortise the graph launch), replayed once untimed first so
     # that the timed region holds no first-launch cost of the graph
@@ -732,7 +797,15 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": prof["traffic_bytes"] if prof else None,
-                "algorithmic_bytes": dom_bytes, "kernel_fingerprint": fp}
+                "algorithmic_bytes": dom_bytes,
+                "bytes_model": "per pixel 12K + 24, per site 164 (pass + forward + backward "
+                               "across the autograd boundary)",
+                "kernel_fingerprint": fp}
+    if dom == "train_pass":
+        ub = algorithmic_bytes("train_pass_unique", P, N_SITES, K)
+        roofline["fused_unique_bytes"] = ub
+        roofline["fused_unique_frac"] = round(ub / (per_kernel_us[dom] * 1e-6) / 1e9 /
+                                              HBM_PEAK_GBS, 4)
     # second view of the same launch: executed VALU instructions (profiled, 64 lanes each)
     # against the vector-ALU issue peak
     roofline_alu = None
@@ -800,11 +873,10 @@ def main():
         extra("topk_quality", topk_quality, args.quality_trials)
 
     if args.cpu_budget > 0:
-        lists_np = enc.topk.cpu().numpy()
-        lists_np = (lists_np.astype(np.int64) & 0xFFFFFFFF).reshape(K // 4, P, 4)
-        lists_np = lists_np.transpose(1, 0, 2).reshape(P, K).astype(np.uint32)
-        sites_np = enc.sites.cpu().numpy()
-        v, n, el = cpu_baseline(target_np, sites_np, lists_np, args.cpu_budget)
+        sites_np, lists_np = cpu_baseline_inputs(target_np)
+        v, n, el = cpu_baseline(target_np, sites_np, lists_np, args.cpu_budget, 1)
+        n_all = max(1, min(16, os.cpu_count() or 1))   # the host share of one GPU
+        va, na, ela = cpu_baseline(target_np, sites_np, lists_np, args.cpu_budget / 2, n_all)
         cpu = "unknown"
         try:
             with open("/proc/cpuinfo") as f:
@@ -817,9 +889,15 @@ def main():
         result["cpu_baseline"] = {"value": round(v, 3), "unit": "Mpix/s", "cores": 1,
                                   "kind": "oracle",
                                   "sample": f"{n} whole steps (pass + fwd + loss + bwd) of the "
-                                            f"same 768x512 workload in {el:.1f} s, single thread",
+                                            f"same 768x512 workload in {el:.1f} s, single thread "
+                                            "(oracle-initialised sites, lists after the seed "
+                                            "pass and ten passes, jump 1)",
                                   "cpu": cpu, "host_threads": os.cpu_count(),
                                   "platform": platform.machine()}
+        result["cpu_baseline_all_cores"] = {
+            "value": round(va, 3), "unit": "Mpix/s", "cores": n_all, "kind": "oracle",
+            "sample": f"{na} whole steps in {ela:.1f} s, the oracle's per-pixel loops split "
+                      f"over {n_all} OpenMP threads"}
     result["paper_context"] = paper_context(result)
     print(json.dumps(result), flush=True)
 
