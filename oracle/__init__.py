@@ -75,6 +75,18 @@ def lib():
         L.ora_densify_prune.argtypes = [i32, i32, i32, _f32p, _f32p, i64, _opt(_f32p),
                                         _opt(_f32p), _f32p, f64, f64, f64, f64, f64, i32,
                                         _opt(_u32p), _i64p]
+        L.ora_grid_points.argtypes = [i32, i32, i32, i32, _opt(_f32p), _opt(_i64p)]
+        L.ora_prop_pass_grid.argtypes = [i32, i32, i32, i32, i32, f32, _f32p, i64, i64, _u32p,
+                                         _u32p, i32, i32, u64, u64]
+        L.ora_seed_grid.argtypes = [i32, i32, i32, i32, i32, i32, f32, _f32p, i64, i64, _u32p]
+        L.ora_jfa_steps.argtypes = [i32, i32, C.POINTER(C.c_int)]
+        L.ora_jfa_steps.restype = i32
+        L.ora_jfa_flood.argtypes = [i32, i32, i32, i32, i32, f32, _f32p, i64, i64, _u32p, _u32p,
+                                    i32]
+        L.ora_jfa_prepass.argtypes = [i32, i32, i32, i32, i32, f32, _f32p, i64, i64, _u32p]
+        L.ora_refresh.argtypes = [i32, i32, i32, i32, i32, f32, _f32p, i64, i64, i32, i32, i32,
+                                  u64, _u32p]
+        L.ora_blend_points.argtypes = [i32, f32, _f32p, i64, i64, _u32p, _f32p, i64, _f64p]
         L.ora_set_threads.argtypes = [i32]
         L.ora_set_threads.restype = i32
         _lib = L
@@ -262,3 +274,76 @@ def densify_prune(target, sites, stats, p_prune, p_split, flags, K=8, adam_m=Non
     L.ora_densify_prune(H, W, K, target, sites, cap, adam_m, adam_v, st, p_prune, p_split, alpha,
                         eps, min_mass, flags, lists, counts)
     return [int(c) for c in counts]
+
+
+# ---- evaluation grids and the full refresh (App. B.3) ---------------------------------
+
+def grid_points(H, W, Hg, Wg):
+    """Points of the cells of an Hg x Wg grid over an H x W image: float32 [Hg*Wg, 2]
+    (x, y), and the cell of every image pixel: int64 [H*W]."""
+    xy = np.empty((Hg * Wg, 2), np.float32)
+    cell = np.empty(H * W, np.int64)
+    lib().ora_grid_points(H, W, Hg, Wg, xy, cell)
+    return xy, cell
+
+
+def prop_pass_grid(H, W, Hg, Wg, K, s, sites, n, lists, jump_, J, seed, t):
+    sites = _sites(sites)
+    out = np.empty((Hg * Wg, K), np.uint32)
+    lib().ora_prop_pass_grid(H, W, Hg, Wg, K, s, sites, sites.shape[1], n,
+                             _lists(lists, Hg * Wg, K), out, jump_, J, seed, t)
+    return out
+
+
+def seed_grid(H, W, Hg, Wg, K, n_entries, s, sites, n):
+    sites = _sites(sites)
+    out = np.empty((Hg * Wg, K), np.uint32)
+    lib().ora_seed_grid(H, W, Hg, Wg, K, n_entries, s, sites, sites.shape[1], n, out)
+    return out
+
+
+def jfa_steps(Hg, Wg):
+    buf = (C.c_int * 32)()
+    L = int(lib().ora_jfa_steps(Hg, Wg, buf))
+    return [int(buf[k]) for k in range(L)]
+
+
+def jfa_flood(H, W, Hg, Wg, K, s, sites, n, lists, step, out=None):
+    """One flood pass; entries 4..K-1 of the result are those of `out` (default: a copy
+    of the input lists), since the pass writes the first four entries only."""
+    sites = _sites(sites)
+    lin = _lists(lists, Hg * Wg, K)
+    res = lin.copy() if out is None else np.ascontiguousarray(out, dtype=np.uint32).copy()
+    lib().ora_jfa_flood(H, W, Hg, Wg, K, s, sites, sites.shape[1], n, lin, res, step)
+    return res
+
+
+def jfa_prepass(H, W, Hg, Wg, K, s, sites, n):
+    sites = _sites(sites)
+    out = np.empty((Hg * Wg, K), np.uint32)
+    lib().ora_jfa_prepass(H, W, Hg, Wg, K, s, sites, sites.shape[1], n, out)
+    return out
+
+
+def refresh(H, W, Hg, Wg, K, s, sites, n, jfa, n_pass, J, seed):
+    sites = _sites(sites)
+    out = np.empty((Hg * Wg, K), np.uint32)
+    lib().ora_refresh(H, W, Hg, Wg, K, s, sites, sites.shape[1], n, int(bool(jfa)), n_pass, J,
+                      seed, out)
+    return out
+
+
+def blend_points(K, s, sites, n, lists, xy):
+    sites = _sites(sites)
+    xy = np.ascontiguousarray(xy, dtype=np.float32).reshape(-1, 2)
+    out = np.empty((len(xy), 3), np.float64)
+    lib().ora_blend_points(K, s, sites, sites.shape[1], n, _lists(lists, len(xy), K), xy,
+                           len(xy), out)
+    return out
+
+
+def expand_grid_lists(H, W, Hg, Wg, lists):
+    """Per-pixel lists of an image whose list field lives on a candidate grid: pixel p
+    takes the list of its cell (the integer map of App. B.3)."""
+    _, cell = grid_points(H, W, Hg, Wg)
+    return np.ascontiguousarray(np.asarray(lists, np.uint32).reshape(Hg * Wg, -1)[cell])

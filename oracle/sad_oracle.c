@@ -283,18 +283,55 @@ uint32_t ora_inject_id(uint64_t seed, uint64_t t, int64_t P, int64_t p, int J, i
     return (uint32_t)((hi * (uint64_t)n_slots) >> 32);
 }
 
-/* One propagation pass (Sec. 4.3 update equation), Jacobi: every pixel reads the
- * previous field `in` and writes `out`.  Candidates: the pixel's own list, the lists
- * at (+-jump, 0) and (0, +-jump) that lie inside the image, and J injected IDs.  IDs
- * that are empty, out of range or inactive are dropped; the rest are scored with the
- * current sites and the top K of the set are kept.  If pix != NULL only those pixels
- * are computed (out is then [npix][K]).  Parity: pinned by invariants
- * (sortedness, uniqueness, monotonicity, convergence to brute force, dilation). */
-void ora_prop_pass(int H, int W, int K, float s, const float *sites, int64_t cap, int64_t n,
-                   const uint32_t *in, uint32_t *out, int jump, int J, uint64_t seed,
-                   uint64_t t, const int64_t *pix, int64_t npix)
+/* ------------------------------------------------------------------------------ */
+/* Evaluation grids (App. B.3 "Downscaled candidate grid")                          */
+/* ------------------------------------------------------------------------------ */
+
+/* A list field may live on a grid of Hg x Wg cells laid over the H x W image (the
+ * image's own pixels are the grid Hg = H, Wg = W).  Cell (i', j') is evaluated at the
+ * centre of its square in UV space, ((j' + 1/2)/Wg, (i' + 1/2)/Hg); with pixel j at
+ * x = j (UV u <-> x = u W - 1/2) that is x = ((2 j' + 1) W - Wg) / (2 Wg): a ratio of
+ * exact integers, divided in double and rounded once to float.  For Wg = W it is j'
+ * exactly.  Parity: pinned (integer centres on the image's own grid; the mean of the
+ * s covered pixel coordinates when W = s Wg; the closed form of a 2x finer grid). */
+static float grid_coord(int64_t j, int n_img, int n_grid)
 {
-    int64_t P = (int64_t)H * W;
+    double num = (double)(2 * j + 1) * (double)n_img - (double)n_grid;
+    return (float)(num / (2.0 * (double)n_grid));
+}
+
+/* The integer map from image pixels to cells: pixel j lies in the cell whose UV
+ * interval holds the pixel's centre, floor((2 j + 1) Wg / (2 W)); when W = s Wg that is
+ * floor(j / s), the integer mapping (no interpolation) of App. B.3. */
+static int64_t cell_of(int64_t j, int n_img, int n_grid)
+{
+    return ((2 * j + 1) * (int64_t)n_grid) / (2 * (int64_t)n_img);
+}
+
+/* Exposed for pins: xy[Hg*Wg][2] = the points of every cell; cell[H*W] = the cell of
+ * every image pixel (row-major cell index i' Wg + j'). */
+void ora_grid_points(int H, int W, int Hg, int Wg, float *xy, int64_t *cell)
+{
+    if (xy)
+        for (int64_t i = 0; i < Hg; ++i)
+            for (int64_t j = 0; j < Wg; ++j) {
+                xy[2 * (i * Wg + j)] = grid_coord(j, W, Wg);
+                xy[2 * (i * Wg + j) + 1] = grid_coord(i, H, Hg);
+            }
+    if (cell)
+        for (int64_t i = 0; i < H; ++i)
+            for (int64_t j = 0; j < W; ++j)
+                cell[i * W + j] = cell_of(i, H, Hg) * Wg + cell_of(j, W, Wg);
+}
+
+/* One propagation pass on a grid (the body of ora_prop_pass; ora_prop_pass is the
+ * image's own grid).  Lists are [Hg*Wg][K]; neighbours at +-jump cells; candidates are
+ * scored at the cell's point; injection counters use P = Hg Wg and the cell index. */
+static void prop_pass_impl(int H, int W, int Hg, int Wg, int K, float s, const float *sites,
+                           int64_t cap, int64_t n, const uint32_t *in, uint32_t *out, int jump,
+                           int J, uint64_t seed, uint64_t t, const int64_t *pix, int64_t npix)
+{
+    int64_t P = (int64_t)Hg * Wg;
     site_t *st = (site_t *)malloc(sizeof(site_t) * (size_t)(n > 0 ? n : 1));
     for (int64_t i = 0; i < n; ++i) st[i] = site_load(sites, cap, i, s);
     int64_t total = pix ? npix : P;
@@ -304,14 +341,14 @@ void ora_prop_pass(int H, int W, int K, float s, const float *sites, int64_t cap
 #pragma omp for schedule(dynamic, 256)
     for (int64_t q = 0; q < total; ++q) {
         int64_t p = pix ? pix[q] : q;
-        int64_t i = p / W, j = p % W;
-        float X = (float)j, Y = (float)i;
+        int64_t i = p / Wg, j = p % Wg;
+        float X = grid_coord(j, W, Wg), Y = grid_coord(i, H, Hg);
         int64_t src[5]; int ns = 0;
         src[ns++] = p;
-        if (j + jump < W) src[ns++] = p + jump;
+        if (j + jump < Wg) src[ns++] = p + jump;
         if (j - jump >= 0) src[ns++] = p - jump;
-        if (i + jump < H) src[ns++] = p + (int64_t)jump * W;
-        if (i - jump >= 0) src[ns++] = p - (int64_t)jump * W;
+        if (i + jump < Hg) src[ns++] = p + (int64_t)jump * Wg;
+        if (i - jump >= 0) src[ns++] = p - (int64_t)jump * Wg;
         int nc = 0;
         for (int a = 0; a < ns; ++a)
             for (int k = 0; k < K; ++k) {
@@ -329,6 +366,160 @@ void ora_prop_pass(int H, int W, int K, float s, const float *sites, int64_t cap
     free(c);
     }
     free(st);
+}
+
+/* One propagation pass (Sec. 4.3 update equation), Jacobi: every pixel reads the
+ * previous field `in` and writes `out`.  Candidates: the pixel's own list, the lists
+ * at (+-jump, 0) and (0, +-jump) that lie inside the image, and J injected IDs.  IDs
+ * that are empty, out of range or inactive are dropped; the rest are scored with the
+ * current sites and the top K of the set are kept.  If pix != NULL only those pixels
+ * are computed (out is then [npix][K]).  Parity: pinned by invariants
+ * (sortedness, uniqueness, monotonicity, convergence to brute force, dilation). */
+void ora_prop_pass(int H, int W, int K, float s, const float *sites, int64_t cap, int64_t n,
+                   const uint32_t *in, uint32_t *out, int jump, int J, uint64_t seed,
+                   uint64_t t, const int64_t *pix, int64_t npix)
+{
+    prop_pass_impl(H, W, H, W, K, s, sites, cap, n, in, out, jump, J, seed, t, pix, npix);
+}
+
+/* The same pass on a candidate grid of Hg x Wg cells (App. B.3): lists [Hg*Wg][K].
+ * Parity: pinned (equals ora_prop_pass on the image's own grid; converges to the exact
+ * top K at the cell points when K >= active sites; invariants as ora_prop_pass). */
+void ora_prop_pass_grid(int H, int W, int Hg, int Wg, int K, float s, const float *sites,
+                        int64_t cap, int64_t n, const uint32_t *in, uint32_t *out, int jump,
+                        int J, uint64_t seed, uint64_t t)
+{
+    prop_pass_impl(H, W, Hg, Wg, K, s, sites, cap, n, in, out, jump, J, seed, t, NULL, 0);
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Full refresh: seed pass and JFA flood prepass (App. B.3 "JFA prepass")            */
+/* ------------------------------------------------------------------------------ */
+
+/* Seed pass on a grid: every slot cleared; each active site goes to the cell of its
+ * nearest image pixel ((rint(p_y), rint(p_x)) clamped, then cell_of), and each cell
+ * keeps the best n_entries (<= K) of its sites by (score at the cell point descending,
+ * ID ascending).  On the image's own grid with n_entries = K this is ora_seed; the JFA
+ * prepass seeds n_entries = 4 (the first candidate texture).  Parity: pinned (equals
+ * ora_seed on the image grid; brute force over the sites of each cell). */
+void ora_seed_grid(int H, int W, int Hg, int Wg, int K, int n_entries, float s,
+                   const float *sites, int64_t cap, int64_t n, uint32_t *lists)
+{
+    int64_t P = (int64_t)Hg * Wg;
+    for (int64_t p = 0; p < P * K; ++p) lists[p] = ORA_INVALID;
+    if (n_entries > K) n_entries = K;
+    int64_t *where = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    site_t *st = (site_t *)malloc(sizeof(site_t) * (size_t)(n > 0 ? n : 1));
+    char *busy = (char *)calloc((size_t)P, 1);
+    for (int64_t i = 0; i < n; ++i) {
+        st[i] = site_load(sites, cap, i, s);
+        where[i] = -1;
+        if (!st[i].valid) continue;
+        float fi = rintf(st[i].y), fj = rintf(st[i].x);
+        int64_t ii = fi < 0 ? 0 : (fi > (float)(H - 1) ? H - 1 : (int64_t)fi);
+        int64_t jj = fj < 0 ? 0 : (fj > (float)(W - 1) ? W - 1 : (int64_t)fj);
+        where[i] = cell_of(ii, H, Hg) * Wg + cell_of(jj, W, Wg);
+        busy[where[i]] = 1;
+    }
+    cand_t *c = (cand_t *)malloc(sizeof(cand_t) * (size_t)(n > 0 ? n : 1));
+    uint32_t *tmp = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)K);
+    for (int64_t p = 0; p < P; ++p) {
+        if (!busy[p]) continue;
+        float X = grid_coord(p % Wg, W, Wg), Y = grid_coord(p / Wg, H, Hg);
+        int nc = 0;
+        for (int64_t i = 0; i < n; ++i)
+            if (where[i] == p) { c[nc].l = score_f32(&st[i], X, Y); c[nc].id = (uint32_t)i; ++nc; }
+        select_topk(c, nc, n_entries, tmp);
+        for (int k = 0; k < n_entries; ++k) lists[p * K + k] = tmp[k];
+    }
+    free(c); free(tmp); free(busy); free(where); free(st);
+}
+
+/* Steps of the JFA prepass on an Hg x Wg grid: L = ceil(log2 max(Hg, Wg)) flood passes
+ * with steps 2^(L-1), ..., 2, 1 (App. B.3: a seed pass and ceil(log2 max(W, H)) flood
+ * passes).  Writes up to 31 steps into steps[]; returns L. */
+int ora_jfa_steps(int Hg, int Wg, int *steps)
+{
+    int m = Hg > Wg ? Hg : Wg;
+    int L = 0;
+    while ((1LL << L) < m) ++L;
+    for (int k = 0; k < L; ++k) steps[k] = 1 << (L - 1 - k);
+    return L;
+}
+
+/* One JFA flood pass (App. B.3), Jacobi: cell p gathers the first four entries (the
+ * first candidate texture) of the cells at (dx, dy) step with dx, dy in {-1, 0, 1}
+ * inside the grid (its own included), drops empty, out-of-range and inactive IDs and
+ * repeats, scores the rest at its point and writes the best four, by (score
+ * descending, ID ascending), into entries 0..3 of out; entries 4..K-1 of out are not
+ * written.  Parity: pinned (a single site floods every cell; with at most four active
+ * sites the prepass ends with the exact lists; per-entry scores never fall pass to pass;
+ * never above the exact top 4; the diagonal neighbours matter). */
+void ora_jfa_flood(int H, int W, int Hg, int Wg, int K, float s, const float *sites,
+                   int64_t cap, int64_t n, const uint32_t *in, uint32_t *out, int step)
+{
+    int64_t P = (int64_t)Hg * Wg;
+    site_t *st = (site_t *)malloc(sizeof(site_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) st[i] = site_load(sites, cap, i, s);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t p = 0; p < P; ++p) {
+        int64_t i = p / Wg, j = p % Wg;
+        float X = grid_coord(j, W, Wg), Y = grid_coord(i, H, Hg);
+        cand_t c[36];
+        int nc = 0;
+        for (int di = -1; di <= 1; ++di)
+            for (int dj = -1; dj <= 1; ++dj) {
+                int64_t ii = i + (int64_t)di * step, jj = j + (int64_t)dj * step;
+                if (ii < 0 || ii >= Hg || jj < 0 || jj >= Wg) continue;
+                for (int k = 0; k < 4; ++k) {
+                    uint32_t id = in[(ii * Wg + jj) * K + k];
+                    if (id == ORA_INVALID || (int64_t)id >= n || !st[id].valid) continue;
+                    c[nc].l = score_f32(&st[id], X, Y); c[nc].id = id; ++nc;
+                }
+            }
+        select_topk(c, nc, 4, out + p * K);
+    }
+    free(st);
+}
+
+/* The JFA prepass of a full refresh (App. B.3): seed pass with four entries per cell,
+ * then the flood passes of ora_jfa_steps; lists [Hg*Wg][K] (entries 4..K-1 empty). */
+void ora_jfa_prepass(int H, int W, int Hg, int Wg, int K, float s, const float *sites,
+                     int64_t cap, int64_t n, uint32_t *lists)
+{
+    int64_t P = (int64_t)Hg * Wg;
+    uint32_t *tmp = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(P * K));
+    ora_seed_grid(H, W, Hg, Wg, K, 4, s, sites, cap, n, lists);
+    memcpy(tmp, lists, sizeof(uint32_t) * (size_t)(P * K));
+    int steps[32];
+    int L = ora_jfa_steps(Hg, Wg, steps);
+    for (int k = 0; k < L; ++k) {
+        ora_jfa_flood(H, W, Hg, Wg, K, s, sites, cap, n, lists, tmp, steps[k]);
+        memcpy(lists, tmp, sizeof(uint32_t) * (size_t)(P * K));
+    }
+    free(tmp);
+}
+
+/* A full refresh of a list field (Sec. 6.6 "full refresh"; App. B.3): the JFA prepass
+ * (jfa != 0) or the plain seed pass with K entries, then n_pass propagation passes with
+ * the Sec. 4.3 schedule of the grid, pass t = 0 .. n_pass - 1 (jump ora_jump(t, Hg, Wg),
+ * injection stream t).  lists [Hg*Wg][K] (written). */
+void ora_refresh(int H, int W, int Hg, int Wg, int K, float s, const float *sites,
+                 int64_t cap, int64_t n, int jfa, int n_pass, int J, uint64_t seed,
+                 uint32_t *lists)
+{
+    int64_t P = (int64_t)Hg * Wg;
+    if (jfa)
+        ora_jfa_prepass(H, W, Hg, Wg, K, s, sites, cap, n, lists);
+    else
+        ora_seed_grid(H, W, Hg, Wg, K, K, s, sites, cap, n, lists);
+    uint32_t *tmp = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(P * K));
+    for (int t = 0; t < n_pass; ++t) {
+        prop_pass_impl(H, W, Hg, Wg, K, s, sites, cap, n, lists, tmp, ora_jump(t, Hg, Wg), J,
+                       seed, (uint64_t)t, NULL, 0);
+        memcpy(lists, tmp, sizeof(uint32_t) * (size_t)(P * K));
+    }
+    free(tmp);
 }
 
 /* ------------------------------------------------------------------------------ */
@@ -406,6 +597,25 @@ void ora_query(int H, int W, int K, float s, const float *sites, int64_t cap, in
         int64_t ii = !(fi > 0) ? 0 : (fi > (float)(H - 1) ? H - 1 : (int64_t)fi);
         int64_t jj = !(fj > 0) ? 0 : (fj > (float)(W - 1) ? W - 1 : (int64_t)fj);
         blend_pixel(st, n, lists + (ii * W + jj) * K, K, (double)x, (double)y, s, SCORE_F32, &px);
+        for (int ch = 0; ch < 3; ++ch) out[3 * m + ch] = px.c[ch];
+    }
+    free(st);
+}
+
+/* Sec. 4.2 at arbitrary points with a list given per point: out[m] = the blend of
+ * lists[m] at xy[m] (the decode of a list field built on a new grid, Sec. 6.6: each
+ * output point of the grid takes its own cell's list).  lists: [M][K]; xy: float[M][2];
+ * out: double[M][3].  Parity: pinned (equals ora_render on the image's own grid). */
+void ora_blend_points(int K, float s, const float *sites, int64_t cap, int64_t n,
+                      const uint32_t *lists, const float *xy, int64_t M, double *out)
+{
+    site_t *st = (site_t *)malloc(sizeof(site_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) st[i] = site_load(sites, cap, i, s);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t m = 0; m < M; ++m) {
+        pix_t px;
+        blend_pixel(st, n, lists + m * K, K, (double)xy[2 * m], (double)xy[2 * m + 1], s,
+                    SCORE_F32, &px);
         for (int ch = 0; ch < 3; ++ch) out[3 * m + ch] = px.c[ch];
     }
     free(st);
