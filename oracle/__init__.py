@@ -87,6 +87,13 @@ def lib():
         L.ora_refresh.argtypes = [i32, i32, i32, i32, i32, f32, _f32p, i64, i64, i32, i32, i32,
                                   u64, _u32p]
         L.ora_blend_points.argtypes = [i32, f32, _f32p, i64, i64, _u32p, _f32p, i64, _f64p]
+        L.ora_f32_to_f16.argtypes = [f32]
+        L.ora_f32_to_f16.restype = C.c_uint16
+        L.ora_f16_to_f32.argtypes = [C.c_uint16]
+        L.ora_f16_to_f32.restype = f32
+        L.ora_pack_qparams.argtypes = [_f32p, i64, i64, _f32p]
+        L.ora_pack_sites.argtypes = [i32, i32, _f32p, i64, i64, _f32p, _u32p]
+        L.ora_unpack_sites.argtypes = [i32, i32, _u32p, i64, _f32p, _f32p, i64]
         L.ora_set_threads.argtypes = [i32]
         L.ora_set_threads.restype = i32
         _lib = L
@@ -347,3 +354,44 @@ def expand_grid_lists(H, W, Hg, Wg, lists):
     takes the list of its cell (the integer map of App. B.3)."""
     _, cell = grid_points(H, W, Hg, Wg)
     return np.ascontiguousarray(np.asarray(lists, np.uint32).reshape(Hg * Wg, -1)[cell])
+
+
+# ---- packed 16-byte inference record (App. B.2; Sec. 6.1) -------------------------------
+
+def f32_to_f16(x):
+    return int(lib().ora_f32_to_f16(float(x)))
+
+
+def f16_to_f32(h):
+    return float(lib().ora_f16_to_f32(int(h)))
+
+
+def pack_qparams(sites, n):
+    sites = _sites(sites)
+    q = np.zeros(10, np.float32)
+    lib().ora_pack_qparams(sites, sites.shape[1], n, q)
+    return q
+
+
+def pack_sites(H, W, sites, n, q=None):
+    """(packed uint32 [n, 4], qparams float32 [10])."""
+    sites = _sites(sites)
+    q = pack_qparams(sites, n) if q is None else np.ascontiguousarray(q, np.float32)
+    out = np.zeros((n, 4), np.uint32)
+    lib().ora_pack_sites(H, W, sites, sites.shape[1], n, q, out)
+    return out, q
+
+
+def unpack_sites(H, W, packed, q, cap=None):
+    packed = np.ascontiguousarray(packed, np.uint32).reshape(-1, 4)
+    n = len(packed)
+    cap = n if cap is None else cap
+    out = np.zeros((10, cap), np.float32)
+    out[0:2, :] = -1.0
+    lib().ora_unpack_sites(H, W, packed, n, np.ascontiguousarray(q, np.float32), out, cap)
+    return out
+
+
+def bpp(n, H, W):
+    """Parameter-space bits per pixel of n packed records (Sec. 6.1): n 16 8 / (H W)."""
+    return n * 16 * 8 / (H * W)

@@ -42,6 +42,7 @@
 #include <string.h>
 
 #define ORA_INVALID 0xFFFFFFFFu
+#define ORA_PI 3.14159265358979323846264338327950288
 enum { P_X, P_Y, P_LOGTAU, P_R, P_CR, P_CG, P_CB, P_UX, P_UY, P_A, NPARAM };
 
 /* ------------------------------------------------------------------------------ */
@@ -619,6 +620,169 @@ void ora_blend_points(int K, float s, const float *sites, int64_t cap, int64_t n
         for (int ch = 0; ch < 3; ++ch) out[3 * m + ch] = px.c[ch];
     }
     free(st);
+}
+
+/* ------------------------------------------------------------------------------ */
+/* Packed 16-byte inference record (App. B.2 "Packed storage for evaluation";        */
+/* Sec. 6.1 BPP accounting)                                                          */
+/* ------------------------------------------------------------------------------ */
+
+/* IEEE 754 binary32 -> binary16, round to nearest, ties to even (overflow to inf, NaN
+ * kept a NaN, subnormal halves rounded at their own spacing).  Written from the
+ * formats' definitions.  Parity: pinned (numpy's float16 conversion). */
+uint16_t ora_f32_to_f16(float f)
+{
+    uint32_t b;
+    memcpy(&b, &f, 4);
+    uint16_t sign = (uint16_t)((b >> 16) & 0x8000u);
+    uint32_t ex = (b >> 23) & 0xFFu, man = b & 0x7FFFFFu;
+    if (ex == 0xFFu) return (uint16_t)(sign | 0x7C00u | (man ? 0x200u : 0u));
+    int e = (int)ex - 127 + 15;                      /* biased half exponent */
+    if (e >= 31) return (uint16_t)(sign | 0x7C00u);  /* overflow */
+    uint32_t full, shift;
+    if (e <= 0) {                                    /* subnormal half (or zero) */
+        if (e < -10) return sign;                    /* below half the smallest subnormal */
+        full = man | 0x800000u;                      /* the implicit one */
+        shift = (uint32_t)(14 - e);                  /* 13 + (1 - e) */
+        uint32_t q = full >> shift, rem = full & ((1u << shift) - 1u), half = 1u << (shift - 1);
+        if (rem > half || (rem == half && (q & 1u))) ++q;
+        return (uint16_t)(sign | q);                 /* a carry into 0x400 is the smallest normal */
+    }
+    uint32_t q = man >> 13, rem = man & 0x1FFFu;
+    uint32_t h = ((uint32_t)e << 10) | q;
+    if (rem > 0x1000u || (rem == 0x1000u && (q & 1u))) ++h;   /* may carry into the exponent */
+    return (uint16_t)(sign | h);
+}
+
+/* binary16 -> binary32 (exact). */
+float ora_f16_to_f32(uint16_t h)
+{
+    uint32_t sign = ((uint32_t)h & 0x8000u) << 16, ex = ((uint32_t)h >> 10) & 0x1Fu,
+             man = (uint32_t)h & 0x3FFu, b;
+    if (ex == 0x1Fu) b = sign | 0x7F800000u | (man << 13);
+    else if (ex) b = sign | ((ex - 15 + 127) << 23) | (man << 13);
+    else if (!man) b = sign;
+    else {                                           /* subnormal: normalise */
+        int e = -1;
+        do { man <<= 1; ++e; } while (!(man & 0x400u));
+        b = sign | ((uint32_t)(127 - 15 - e) << 23) | ((man & 0x3FFu) << 13);
+    }
+    float f;
+    memcpy(&f, &b, 4);
+    return f;
+}
+
+/* Per-image quantisation parameters of the packed record: q = {log_tau min, scale,
+ * r min, scale, c_r min, scale, c_g min, scale, c_b min, scale} with min and max over
+ * the active sites and scale = max - min (all 0 without active sites). */
+void ora_pack_qparams(const float *sites, int64_t cap, int64_t n, float *q)
+{
+    static const int par[5] = {P_LOGTAU, P_R, P_CR, P_CG, P_CB};
+    float mn[5], mx[5];
+    int any = 0;
+    for (int k = 0; k < 5; ++k) { mn[k] = INFINITY; mx[k] = -INFINITY; }
+    for (int64_t i = 0; i < n; ++i) {
+        int act = prm(sites, cap, P_X, i) >= 0.0f;
+        for (int p = 0; p < NPARAM; ++p) act &= isfinite(prm(sites, cap, p, i)) ? 1 : 0;
+        if (!act) continue;
+        any = 1;
+        for (int k = 0; k < 5; ++k) {
+            float v = prm(sites, cap, par[k], i);
+            if (v < mn[k]) mn[k] = v;
+            if (v > mx[k]) mx[k] = v;
+        }
+    }
+    for (int k = 0; k < 5; ++k) {
+        q[2 * k] = any ? mn[k] : 0.0f;
+        q[2 * k + 1] = any ? mx[k] - mn[k] : 0.0f;
+    }
+}
+
+/* UNORM code of v with `bits` bits over [mn, mn + sc]: t = (v - mn) / sc clamped to
+ * [0, 1] (0 if sc = 0), code = rint(t (2^bits - 1)); every step one float32 operation. */
+static uint32_t unorm_code(float v, float mn, float sc, int bits)
+{
+    float maxq = (float)((1u << bits) - 1u);
+    float t = sc > 0.0f ? (v - mn) / sc : 0.0f;
+    if (!(t > 0.0f)) t = 0.0f;
+    if (t > 1.0f) t = 1.0f;
+    return (uint32_t)rintf(t * maxq);
+}
+
+/* Decoded value of a UNORM code: mn + sc (code / (2^bits - 1)). */
+static float unorm_value(uint32_t code, float mn, float sc, int bits)
+{
+    float maxq = (float)((1u << bits) - 1u);
+    return mn + sc * ((float)code / maxq);
+}
+
+/* Angle code of the direction u over [-pi, pi] (16-bit UNORM): theta = atan2(u_y, u_x)
+ * in double, code = rint((theta + pi) / (2 pi) (2^16 - 1)). */
+static uint32_t angle_code(float ux, float uy)
+{
+    double th = atan2((double)uy, (double)ux);
+    double t = (th + ORA_PI) / (2.0 * ORA_PI);
+    return (uint32_t)rint(t * 65535.0);
+}
+
+/* App. B.2 packed record of every slot < n: four 32-bit words
+ *   w0 = x code (15-bit UNORM over [0, W-1]) | y code << 15 (over [0, H-1]) | 1 << 31
+ *        (the active flag; bit 30 is 0)
+ *   w1 = c_r code (11 bits) | c_g code << 11 (11 bits) | c_b code << 22 (10 bits)
+ *   w2 = log_tau code (16 bits) | r code << 16 (16 bits)
+ *   w3 = angle code of u (16 bits) | float16 bits of a << 16
+ * with the per-image min / scale of q for log_tau, r and the colours; an inactive slot
+ * packs to four zero words.  packed: uint32[n][4].  Parity: pinned (hand-derived words
+ * of edge values; round-trip error bounds; numpy float16). */
+void ora_pack_sites(int H, int W, const float *sites, int64_t cap, int64_t n, const float *q,
+                    uint32_t *packed)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t *w = packed + 4 * i;
+        w[0] = w[1] = w[2] = w[3] = 0;
+        int act = prm(sites, cap, P_X, i) >= 0.0f;
+        for (int p = 0; p < NPARAM; ++p) act &= isfinite(prm(sites, cap, p, i)) ? 1 : 0;
+        if (!act) continue;
+        float x = prm(sites, cap, P_X, i), y = prm(sites, cap, P_Y, i);
+        uint32_t qx = unorm_code(x, 0.0f, (float)(W - 1), 15);
+        uint32_t qy = unorm_code(y, 0.0f, (float)(H - 1), 15);
+        w[0] = qx | (qy << 15) | 0x80000000u;
+        w[1] = unorm_code(prm(sites, cap, P_CR, i), q[4], q[5], 11) |
+               (unorm_code(prm(sites, cap, P_CG, i), q[6], q[7], 11) << 11) |
+               (unorm_code(prm(sites, cap, P_CB, i), q[8], q[9], 10) << 22);
+        w[2] = unorm_code(prm(sites, cap, P_LOGTAU, i), q[0], q[1], 16) |
+               (unorm_code(prm(sites, cap, P_R, i), q[2], q[3], 16) << 16);
+        w[3] = angle_code(prm(sites, cap, P_UX, i), prm(sites, cap, P_UY, i)) |
+               ((uint32_t)ora_f32_to_f16(prm(sites, cap, P_A, i)) << 16);
+    }
+}
+
+/* Decode of ora_pack_sites into float32 sites [10][cap] (slots < n): each UNORM as
+ * unorm_value (positions over [0, W-1] and [0, H-1]); u = (cos theta, sin theta) with
+ * theta = code / (2^16 - 1) 2 pi - pi in double, each rounded once to float; a from its
+ * float16 bits.  A record without the active flag decodes to an inactive site
+ * (x = y = -1, the rest 0). */
+void ora_unpack_sites(int H, int W, const uint32_t *packed, int64_t n, const float *q,
+                      float *sites, int64_t cap)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        const uint32_t *w = packed + 4 * i;
+        float v[NPARAM] = {-1.0f, -1.0f, 0, 0, 0, 0, 0, 0, 0, 0};
+        if (w[0] & 0x80000000u) {
+            v[P_X] = unorm_value(w[0] & 0x7FFFu, 0.0f, (float)(W - 1), 15);
+            v[P_Y] = unorm_value((w[0] >> 15) & 0x7FFFu, 0.0f, (float)(H - 1), 15);
+            v[P_CR] = unorm_value(w[1] & 0x7FFu, q[4], q[5], 11);
+            v[P_CG] = unorm_value((w[1] >> 11) & 0x7FFu, q[6], q[7], 11);
+            v[P_CB] = unorm_value(w[1] >> 22, q[8], q[9], 10);
+            v[P_LOGTAU] = unorm_value(w[2] & 0xFFFFu, q[0], q[1], 16);
+            v[P_R] = unorm_value(w[2] >> 16, q[2], q[3], 16);
+            double th = (double)(w[3] & 0xFFFFu) / 65535.0 * (2.0 * ORA_PI) - ORA_PI;
+            v[P_UX] = (float)cos(th);
+            v[P_UY] = (float)sin(th);
+            v[P_A] = ora_f16_to_f32((uint16_t)(w[3] >> 16));
+        }
+        for (int p = 0; p < NPARAM; ++p) sites[(int64_t)p * cap + i] = v[p];
+    }
 }
 
 /* Sec. 6.1: L = E_x ||c(x) - I(x)||^2 = (1/P) sum_x sum_ch (c - I)^2 with P = H W;
