@@ -94,6 +94,17 @@ def lib():
         L.ora_pack_qparams.argtypes = [_f32p, i64, i64, _f32p]
         L.ora_pack_sites.argtypes = [i32, i32, _f32p, i64, i64, _f32p, _u32p]
         L.ora_unpack_sites.argtypes = [i32, i32, _u32p, i64, _f32p, _f32p, i64]
+        L.ora_tau_diffusion.argtypes = [i32, i32, i32, f32, _f32p, i64, i64, _u32p, _f64p, f64,
+                                         _f64p]
+        L.ora1d_brute_topk.argtypes = [i32, i32, f32, _f32p, i64, i64, _u32p]
+        L.ora1d_seed.argtypes = [i32, i32, f32, _f32p, i64, i64, _u32p]
+        L.ora1d_prop_pass.argtypes = [i32, i32, f32, _f32p, i64, i64, _u32p, _u32p, i32, i32, u64,
+                                      u64]
+        L.ora1d_render_loss_bwd.argtypes = [i32, i32, f32, _f32p, i64, i64, _u32p, _opt(_f32p),
+                                            i32, _opt(_f64p), _opt(_f64p), _opt(_f64p)]
+        L.ora1d_render_loss_bwd.restype = f64
+        L.ora1d_adam.argtypes = [i32, _f64p, _f64p, _f64p, _f64p, i64, i64, _f64p, f64, f64, f64,
+                                 i64]
         L.ora_set_threads.argtypes = [i32]
         L.ora_set_threads.restype = i32
         _lib = L
@@ -395,3 +406,68 @@ def unpack_sites(H, W, packed, q, cap=None):
 def bpp(n, H, W):
     """Parameter-space bits per pixel of n packed records (Sec. 6.1): n 16 8 / (H W)."""
     return n * 16 * 8 / (H * W)
+
+
+# ---- tau diffusion (App. B.6) ----------------------------------------------------------
+
+def tau_diffusion(H, W, K, s, sites, n, lists, g, lam):
+    """One Jacobi step of the log tau gradient smoothing; g: [n] -> [n] (float64)."""
+    sites = _sites(sites)
+    g = np.ascontiguousarray(g, np.float64)
+    out = np.empty(n, np.float64)
+    lib().ora_tau_diffusion(H, W, K, s, sites, sites.shape[1], n, _lists(lists, H * W, K), g,
+                            float(lam), out)
+    return out
+
+
+# ---- one-dimensional SAD (Sec. 7) ----------------------------------------------------------
+
+def _sites1(sites):
+    s = np.ascontiguousarray(sites, dtype=np.float32)
+    assert s.ndim == 2 and s.shape[0] == 4, s.shape
+    return s
+
+
+def scale1d(M):
+    return float(np.float32(1.0) / np.float32(M))
+
+
+def brute_topk1d(M, K, s, sites, n):
+    sites = _sites1(sites)
+    out = np.empty((M, K), np.uint32)
+    lib().ora1d_brute_topk(M, K, s, sites, sites.shape[1], n, out)
+    return out
+
+
+def seed1d(M, K, s, sites, n):
+    sites = _sites1(sites)
+    out = np.empty((M, K), np.uint32)
+    lib().ora1d_seed(M, K, s, sites, sites.shape[1], n, out)
+    return out
+
+
+def prop_pass1d(M, K, s, sites, n, lists, jump_, J, seed, t):
+    sites = _sites1(sites)
+    out = np.empty((M, K), np.uint32)
+    lib().ora1d_prop_pass(M, K, s, sites, sites.shape[1], n, _lists(lists, M, K), out, jump_, J,
+                          seed, t)
+    return out
+
+
+def render1d(M, K, s, sites, n, lists, target=None, mode=SCORE_F32, grad=False, abs_sum=False):
+    """(colours [M], loss or None, gradient [4, cap] or None, abs sums or None)."""
+    sites = _sites1(sites)
+    cap = sites.shape[1]
+    out = np.empty(M, np.float64)
+    g = np.zeros((4, cap), np.float64) if grad else None
+    ga = np.zeros((4, cap), np.float64) if abs_sum else None
+    tgt = None if target is None else np.ascontiguousarray(target, np.float32)
+    L = lib().ora1d_render_loss_bwd(M, K, s, sites, cap, n, _lists(lists, M, K), tgt, mode, out,
+                                    g, ga)
+    return out, (L if target is not None else None), g, ga
+
+
+def adam1d(M, sites, grad, m, v, n, lr, b1, b2, eps, t):
+    cap = sites.shape[1]
+    lib().ora1d_adam(M, sites, np.ascontiguousarray(grad, np.float64), m, v, cap, n,
+                     np.ascontiguousarray(lr, np.float64), b1, b2, eps, t)

@@ -785,6 +785,238 @@ void ora_unpack_sites(int H, int W, const uint32_t *packed, int64_t n, const flo
     }
 }
 
+/* ------------------------------------------------------------------------------ */
+/* Tau diffusion (App. B.6)                                                          */
+/* ------------------------------------------------------------------------------ */
+
+/* One Jacobi step of log tau gradient smoothing: for every active, valid site i < n,
+ * with N(i) = the valid sites other than i in the candidate list of the pixel nearest
+ * its centre ((rint(p_y), rint(p_x)) clamped),
+ *   g_out[i] = (1 - lambda) g_in[i] + lambda mean_{j in N(i)} g_in[j],
+ * and g_out[i] = g_in[i] when N(i) is empty or the site is inactive.  All reads are of
+ * g_in (Jacobi).  g_in, g_out: double[n].  Parity: pinned (lambda = 0 is the identity,
+ * lambda = 1 the neighbour mean, a constant field is fixed, a hand-worked example). */
+void ora_tau_diffusion(int H, int W, int K, float s, const float *sites, int64_t cap, int64_t n,
+                       const uint32_t *lists, const double *g_in, double lambda, double *g_out)
+{
+    site_t *st = (site_t *)malloc(sizeof(site_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) st[i] = site_load(sites, cap, i, s);
+    for (int64_t i = 0; i < n; ++i) {
+        g_out[i] = g_in[i];
+        if (!st[i].valid) continue;
+        float fi = rintf(st[i].y), fj = rintf(st[i].x);
+        int64_t ii = fi < 0 ? 0 : (fi > (float)(H - 1) ? H - 1 : (int64_t)fi);
+        int64_t jj = fj < 0 ? 0 : (fj > (float)(W - 1) ? W - 1 : (int64_t)fj);
+        const uint32_t *l = lists + (ii * W + jj) * K;
+        double sum = 0;
+        int cnt = 0;
+        for (int k = 0; k < K; ++k) {
+            uint32_t id = l[k];
+            if (id == ORA_INVALID || (int64_t)id >= n || (int64_t)id == i || !st[id].valid) continue;
+            sum += g_in[id];
+            ++cnt;
+        }
+        if (cnt) g_out[i] = (1.0 - lambda) * g_in[i] + lambda * (sum / cnt);
+    }
+    free(st);
+}
+
+/* ------------------------------------------------------------------------------ */
+/* One-dimensional SAD (Sec. 7 "1D Signal Fitting")                                  */
+/* ------------------------------------------------------------------------------ */
+
+/* A 1-D signal of M samples, sample m at x = m.  Each site has four parameters, stored
+ * float[4][cap] in the order (p, c, log_tau, r): position, value, log-temperature and
+ * radius.  The soft partition is the 2-D one on a line: the score is
+ *   l_i(x) = tau_i s (r_i - |x - p_i|)
+ * (the metric is the absolute value), s = 1/M unless given, and a sample blends the
+ * values of its top-K list by the softmax of the scores.  Canonical float32 score:
+ * d = X - p, n = |d|, l = kappa (r - n) + 0 with kappa = f32(exp(double log_tau)) * s.
+ * A site is active iff p >= 0 and all four values are finite (and kappa finite > 0). */
+enum { Q_P, Q_C, Q_LOGTAU, Q_R, NPARAM1 };
+
+typedef struct { int valid; float p, c, log_tau, r, kappa; } site1_t;
+
+static site1_t site1_load(const float *sites, int64_t cap, int64_t i, float s)
+{
+    site1_t t;
+    t.p = sites[Q_P * cap + i]; t.c = sites[Q_C * cap + i];
+    t.log_tau = sites[Q_LOGTAU * cap + i]; t.r = sites[Q_R * cap + i];
+    t.valid = t.p >= 0.0f && isfinite(t.p) && isfinite(t.c) && isfinite(t.log_tau) && isfinite(t.r);
+    t.kappa = 0.0f;
+    if (t.valid) {
+        t.kappa = (float)exp((double)t.log_tau) * s;
+        if (!(t.kappa > 0.0f) || !isfinite(t.kappa)) t.valid = 0;
+    }
+    return t;
+}
+
+static float score1_f32(const site1_t *t, float X)
+{
+    float n = fabsf(X - t->p);
+    float l = t->kappa * (t->r - n);
+    return l + 0.0f;
+}
+
+/* Exact top-K of every sample over the active sites (l descending, ID ascending).
+ * out: [M][K].  Parity: pinned (sorted distance in the equal-tau, equal-r case). */
+void ora1d_brute_topk(int M, int K, float s, const float *sites, int64_t cap, int64_t n,
+                      uint32_t *out)
+{
+    site1_t *st = (site1_t *)malloc(sizeof(site1_t) * (size_t)(n > 0 ? n : 1));
+    cand_t *c = (cand_t *)malloc(sizeof(cand_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) st[i] = site1_load(sites, cap, i, s);
+    for (int64_t m = 0; m < M; ++m) {
+        int nc = 0;
+        for (int64_t i = 0; i < n; ++i)
+            if (st[i].valid) { c[nc].l = score1_f32(&st[i], (float)m); c[nc].id = (uint32_t)i; ++nc; }
+        select_topk(c, nc, K, out + m * K);
+    }
+    free(c); free(st);
+}
+
+/* Seed pass: each active site goes to sample rint(p) clamped to [0, M-1]; a sample keeps
+ * the top K of its sites.  Parity: pinned (brute force per sample). */
+void ora1d_seed(int M, int K, float s, const float *sites, int64_t cap, int64_t n,
+                uint32_t *lists)
+{
+    for (int64_t q = 0; q < (int64_t)M * K; ++q) lists[q] = ORA_INVALID;
+    site1_t *st = (site1_t *)malloc(sizeof(site1_t) * (size_t)(n > 0 ? n : 1));
+    int64_t *where = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    cand_t *c = (cand_t *)malloc(sizeof(cand_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) {
+        st[i] = site1_load(sites, cap, i, s);
+        where[i] = -1;
+        if (!st[i].valid) continue;
+        float f = rintf(st[i].p);
+        where[i] = f > (float)(M - 1) ? M - 1 : (int64_t)f;
+    }
+    for (int64_t m = 0; m < M; ++m) {
+        int nc = 0;
+        for (int64_t i = 0; i < n; ++i)
+            if (where[i] == m) { c[nc].l = score1_f32(&st[i], (float)m); c[nc].id = (uint32_t)i; ++nc; }
+        if (nc) select_topk(c, nc, K, lists + m * K);
+    }
+    free(c); free(where); free(st);
+}
+
+/* One propagation pass on the line (Sec. 4.3 update equation in 1-D), Jacobi:
+ * candidates = own list, the lists at m +- jump inside [0, M), and J injected IDs (draw
+ * j: SplitMix64 output (t M + m) J + j, ID = hi32 n_slots / 2^32).  Parity: pinned
+ * (converges to brute force when K >= active sites; monotone per entry; single-site
+ * dilation by {0, +-s_t}). */
+void ora1d_prop_pass(int M, int K, float s, const float *sites, int64_t cap, int64_t n,
+                     const uint32_t *in, uint32_t *out, int jump, int J, uint64_t seed,
+                     uint64_t t)
+{
+    site1_t *st = (site1_t *)malloc(sizeof(site1_t) * (size_t)(n > 0 ? n : 1));
+    cand_t *c = (cand_t *)malloc(sizeof(cand_t) * (size_t)(3 * K + J + 1));
+    for (int64_t i = 0; i < n; ++i) st[i] = site1_load(sites, cap, i, s);
+    for (int64_t m = 0; m < M; ++m) {
+        int64_t src[3]; int ns = 0;
+        src[ns++] = m;
+        if (m + jump < M) src[ns++] = m + jump;
+        if (m - jump >= 0) src[ns++] = m - jump;
+        int nc = 0;
+        for (int a = 0; a < ns; ++a)
+            for (int k = 0; k < K; ++k) {
+                uint32_t id = in[src[a] * K + k];
+                if (id == ORA_INVALID || (int64_t)id >= n || !st[id].valid) continue;
+                c[nc].l = score1_f32(&st[id], (float)m); c[nc].id = id; ++nc;
+            }
+        for (int j = 0; j < J; ++j) {
+            uint32_t id = n > 0 ? ora_inject_id(seed, t, M, m, J, j, (uint32_t)n) : ORA_INVALID;
+            if (id == ORA_INVALID || (int64_t)id >= n || !st[id].valid) continue;
+            c[nc].l = score1_f32(&st[id], (float)m); c[nc].id = id; ++nc;
+        }
+        select_topk(c, nc, K, out + m * K);
+    }
+    free(c); free(st);
+}
+
+/* Blend of every sample (softmax of the valid entries' scores, max subtracted; an empty
+ * list gives 0), its loss L = (1/M) sum (c - I)^2 against target[M] (returned, if target
+ * != NULL) and, if grad != NULL, the gradients for dL/dc = (2/M)(c - I), accumulated
+ * into grad[4][cap] (+=):
+ *   dc_k += w_k g;  gamma_k = w_k g (c_k - c);  dlog_tau_k += gamma_k l_k;
+ *   dr_k += gamma_k kappa_k;  dp_k += gamma_k kappa_k sign(x - p_k)  (0 at x = p_k).
+ * gabs (nullable, [4][cap]) accumulates |term|.  mode SCORE_F64 scores in double
+ * (finite differences).  out: double[M] (nullable).  Parity: pinned (K = N full softmax,
+ * hard limit, central finite differences, sum identities). */
+double ora1d_render_loss_bwd(int M, int K, float s, const float *sites, int64_t cap, int64_t n,
+                             const uint32_t *lists, const float *target, int mode, double *out,
+                             double *grad, double *gabs)
+{
+    site1_t *st = (site1_t *)malloc(sizeof(site1_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) st[i] = site1_load(sites, cap, i, s);
+    double L = 0;
+    for (int64_t m = 0; m < M; ++m) {
+        double X = (double)m;
+        int idx[64], nv = 0;
+        double l[64], e[64], S = 0, c = 0, mx = -INFINITY;
+        for (int k = 0; k < K; ++k) {
+            uint32_t id = lists[m * K + k];
+            if (id == ORA_INVALID || (int64_t)id >= n || !st[id].valid) continue;
+            const site1_t *t = &st[id];
+            idx[nv] = (int)id;
+            l[nv] = mode == SCORE_F64
+                        ? exp((double)t->log_tau) * (double)s * ((double)t->r - fabs(X - (double)t->p))
+                        : (double)score1_f32(t, (float)m);
+            if (l[nv] > mx) mx = l[nv];
+            ++nv;
+        }
+        for (int v = 0; v < nv; ++v) { e[v] = exp(l[v] - mx); S += e[v]; }
+        for (int v = 0; v < nv; ++v) c += e[v] / S * (double)st[idx[v]].c;
+        if (out) out[m] = c;
+        if (!target) continue;
+        double d = c - (double)target[m];
+        L += d * d;
+        if (!grad) continue;
+        double g = 2.0 * d / (double)M;
+        for (int v = 0; v < nv; ++v) {
+            const site1_t *t = &st[idx[v]];
+            int64_t id = idx[v];
+            double w = e[v] / S;
+            double gam = w * g * ((double)t->c - c);
+            double kap = exp((double)t->log_tau) * (double)s;
+            double dx = X - (double)t->p;
+            double sg = dx > 0 ? 1.0 : (dx < 0 ? -1.0 : 0.0);
+            double term[4] = {gam * kap * sg, w * g, gam * l[v], gam * kap};
+            for (int q = 0; q < 4; ++q) {
+                grad[q * cap + id] += term[q];
+                if (gabs) gabs[q * cap + id] += fabs(term[q]);
+            }
+        }
+    }
+    free(st);
+    return target ? L / (double)M : 0.0;
+}
+
+/* Adam on the four parameters (Kingma & Ba, bias-corrected, as ora_adam) followed by the
+ * clamps p in [0, M-1], log_tau in [2, 20], r in [1, 512]; inactive slots untouched.
+ * sites, m, v: double[4][cap] in place; grad: double[4][cap]; lr: double[4].  Parity:
+ * pinned (torch.optim.Adam). */
+void ora1d_adam(int M, double *sites, const double *grad, double *m, double *v, int64_t cap,
+                int64_t n, const double *lr, double b1, double b2, double eps, int64_t t)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        int act = sites[Q_P * cap + i] >= 0.0;
+        for (int q = 0; q < NPARAM1; ++q) act &= isfinite(sites[q * cap + i]) ? 1 : 0;
+        if (!act) continue;
+        for (int q = 0; q < NPARAM1; ++q) {
+            int64_t o = q * cap + i;
+            m[o] = b1 * m[o] + (1 - b1) * grad[o];
+            v[o] = b2 * v[o] + (1 - b2) * grad[o] * grad[o];
+            double mh = m[o] / (1 - pow(b1, (double)t)), vh = v[o] / (1 - pow(b2, (double)t));
+            sites[o] -= lr[q] * mh / (sqrt(vh) + eps);
+        }
+        double *p = &sites[Q_P * cap + i], *lt = &sites[Q_LOGTAU * cap + i], *r = &sites[Q_R * cap + i];
+        *p = *p < 0 ? 0 : (*p > M - 1 ? M - 1 : *p);
+        *lt = *lt < 2 ? 2 : (*lt > 20 ? 20 : *lt);
+        *r = *r < 1 ? 1 : (*r > 512 ? 512 : *r);
+    }
+}
+
 /* Sec. 6.1: L = E_x ||c(x) - I(x)||^2 = (1/P) sum_x sum_ch (c - I)^2 with P = H W;
  * dL/dc(x) = (2/P)(c(x) - I(x)).  Returns L. */
 double ora_loss_grad(int H, int W, const double *img, const float *target, double *grad)
