@@ -620,24 +620,112 @@ def plain_loop(sets, reqs, times):
 def topk_quality(trials):
     """Propagated field vs exact top-K at 256 random pixels (Sec. 6.5 protocol, its two
     domains 1024^2 and 2048^2): sites at distinct pixel cells, 8 / 12 / 16 passes,
-    J = 4, K = 8."""
+    J = 4, K = 8; the field starts from the seed pass, and again from the JFA prepass
+    of a full refresh (App. B.3)."""
     import synth
     from paper_2604_21984_amd import quality as Q
-    out = {"K": K, "J": J, "pixels": 256, "trials": trials, "by_domain": {}}
-    for side in (1024, 2048):
-        qt = {}
-        for n in (16384, 65536, 131072):
-            acc = {t: [0.0, 0.0] for t in (8, 12, 16)}
-            for trial in range(trials):
-                sites = synth.cell_sites(1000 + trial, side, side, n)
-                r = Q.convergence(sites, side, side, K=K, J=J, passes=(8, 12, 16), n_pix=256,
-                                  seed=trial)
-                for t in acc:
-                    acc[t][0] += r[t][0] / trials
-                    acc[t][1] += r[t][1] / trials
-            qt[str(n)] = {str(t): {"exact_match": round(v[0], 4), "recall": round(v[1], 4)}
-                          for t, v in acc.items()}
-        out["by_domain"][f"{side}x{side}"] = qt
+    out = {"K": K, "J": J, "pixels": 256, "trials": trials, "by_domain": {},
+           "by_domain_jfa": {}}
+    for jfa, key in ((False, "by_domain"), (True, "by_domain_jfa")):
+        for side in (1024, 2048):
+            qt = {}
+            for n in (16384, 65536, 131072):
+                acc = {t: [0.0, 0.0] for t in (8, 12, 16)}
+                for trial in range(trials):
+                    sites = synth.cell_sites(1000 + trial, side, side, n)
+                    r = Q.convergence(sites, side, side, K=K, J=J, passes=(8, 12, 16),
+                                      n_pix=256, seed=trial, jfa=jfa)
+                    for t in acc:
+                        acc[t][0] += r[t][0] / trials
+                        acc[t][1] += r[t][1] / trials
+                qt[str(n)] = {str(t): {"exact_match": round(v[0], 4), "recall": round(v[1], 4)}
+                              for t, v in acc.items()}
+            out[key][f"{side}x{side}"] = qt
+    return out
+
+
+def render_call(reps, seed=4):
+    """The paper's render-call protocol (Sec. 6.6, Tab. render_call / render_breakdown):
+    at 512^2, 1024^2 and 2048^2 with 1 bpp of packed records (n = H W / 128 sites), K = 8,
+    J = 4; sites with random anisotropic metrics (decode cost does not depend on how they
+    were fitted).  Per call, event-timed over `reps` calls after warm-up calls: the full
+    render call (JFA prepass + 16 passes + render, sad_refresh then sad_render_grid), the
+    JFA prepass alone, 16 passes alone, one pass, and the render from cached lists; then
+    a re-render at a new grid of twice the resolution (refresh on that grid + render)
+    and the image rendered from a candidate grid downscaled by 2."""
+    import torch
+
+    import synth
+    from paper_2604_21984_amd import _lib as S
+    out = {"K": K, "J": J, "reps": reps, "bpp": 1.0, "by_side": {}}
+    for side in (512, 1024, 2048):
+        Hs = Ws = side
+        n = Hs * Ws // 128
+        sites = synth.perturb_sites(seed + 1, synth.random_sites(seed, Hs, Ws, n, log_tau=5.5,
+                                                                 r=1.0), n, Hs, Ws)
+        img = S.image(Hs, Ws, K, n, n)
+        sd = torch.from_numpy(sites).cuda()
+        rec = torch.empty(n * S.REC_FLOATS, dtype=torch.float32, device="cuda")
+        S.prepare_sites(img, sd, rec)
+
+        def field(h, w):
+            return torch.empty((K // 4, h, w, 4), dtype=torch.int32, device="cuda")
+
+        a, b = field(Hs, Ws), field(Hs, Ws)
+        scratch = torch.empty(4 * Hs * Ws, dtype=torch.int64, device="cuda")
+        img_out = torch.empty((3, 2 * Hs, 2 * Ws), dtype=torch.float32, device="cuda")
+
+        def full():
+            S.refresh(img, Hs, Ws, rec, a, b, scratch, 16, J, seed, jfa=True)
+            S.render_grid(img, Hs, Ws, rec, a, Hs, Ws, img_out)
+
+        def prepass():
+            S.refresh(img, Hs, Ws, rec, a, b, scratch, 0, J, seed, jfa=True)
+
+        def passes(npass):
+            def run():
+                x, y = a, b
+                for t in range(npass):
+                    S.propagate_topk(img, rec, x, y, 1, J, seed, 100 + t)
+                    x, y = y, x
+            return run
+
+        def render():
+            S.render_fwd(img, rec, a, img_out)
+
+        a2, b2 = field(2 * Hs, 2 * Ws), field(2 * Hs, 2 * Ws)
+
+        def new_grid():
+            S.refresh(img, 2 * Hs, 2 * Ws, rec, a2, b2, scratch, 16, J, seed, jfa=True)
+            S.render_grid(img, 2 * Hs, 2 * Ws, rec, a2, 2 * Hs, 2 * Ws, img_out)
+
+        ah, bh = field(Hs // 2, Ws // 2), field(Hs // 2, Ws // 2)
+
+        def half_grid():
+            S.refresh(img, Hs // 2, Ws // 2, rec, ah, bh, scratch, 16, J, seed, jfa=True)
+            S.render_grid(img, Hs // 2, Ws // 2, rec, ah, Hs, Ws, img_out)
+
+        row = {"n_sites": n}
+        for name, fn, r in (("full_render_call_ms", full, reps),
+                            ("jfa_prepass_ms", prepass, reps),
+                            ("update_16_passes_ms", passes(16), reps),
+                            ("update_1_pass_ms", passes(1), reps),
+                            ("render_only_ms", render, reps),
+                            ("new_grid_2x_render_call_ms", new_grid, max(1, reps // 4)),
+                            ("candidate_grid_half_render_call_ms", half_grid, reps)):
+            for _ in range(3):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(r):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            row[name] = round(e0.elapsed_time(e1) / r, 4)
+        out["by_side"][f"{side}x{side}"] = row
+        del a, b, a2, b2, ah, bh, scratch, img_out, sd, rec
+        torch.cuda.empty_cache()
     return out
 
 
@@ -699,6 +787,8 @@ def main():
                     help="seconds of Poisson arrivals per rate (0: skip serving)")
     ap.add_argument("--quality-trials", type=int, default=4,
                     help="trials of the top-K convergence measurement (0: skip)")
+    ap.add_argument("--render-call-reps", type=int, default=20,
+                    help="timed calls per stage of the render-call measurement (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: the implementation runs on one GPU; --gpus {args.gpus} is not "
@@ -871,6 +961,8 @@ def main():
         extra("serving", serving, (10, 100, 1000), args.serve_seconds)
     if args.quality_trials > 0:
         extra("topk_quality", topk_quality, args.quality_trials)
+    if args.render_call_reps > 0:
+        extra("render_call", render_call, args.render_call_reps)
 
     if args.cpu_budget > 0:
         sites_np, lists_np = cpu_baseline_inputs(target_np)

@@ -436,6 +436,123 @@ sad_status sad_densify_prune(const sad_image *img, const float *target, float *s
                              int64_t *counts, void *workspace, size_t *workspace_bytes,
                              void *stream);
 
+/* ---- full-refresh regime (Sec. 6.6 "full refresh"; App. B.3) ----------------------
+ * A list field may live on a grid of Hg x Wg cells laid over img's H x W image: a
+ * downscaled candidate grid (App. B.3 "Downscaled candidate grid", Hg = ceil(H / s_grid))
+ * or the pixels of a new output resolution (Sec. 6.6: a new pixel grid needs its lists
+ * rebuilt).  Its layout is that of `topk` with Hg*Wg cells in place of the pixels:
+ * uint32[K/4][Hg*Wg][4].  Cell (i, j) is evaluated at the centre of its UV square,
+ *   x = ((2 j + 1) W - Wg) / (2 Wg),  y = ((2 i + 1) H - Hg) / (2 Hg)
+ * (pixel units, each a ratio of exact integers divided in double and rounded once to
+ * float; on the image's own grid Hg = H, Wg = W the cell is the pixel), and image point
+ * (or pixel) j belongs to cell floor((2 j + 1) Wg / (2 W)) -- the integer mapping of
+ * App. B.3 (floor(j / s) when W = s Wg).  Hg, Wg >= 1, Hg*Wg <= 2^30. */
+
+/* Seed pass on a grid (App. B.3 "JFA prepass": the seed pass): every entry cleared to
+ * SAD_INVALID_ID, then each valid site goes to the cell of its nearest pixel
+ * (rint(y), rint(x)) clamped to the image, and a cell keeps its best n_entries sites
+ * (0 <= n_entries <= K) by (score at the cell's point descending, ID ascending).  With
+ * Hg = H, Wg = W, n_entries = K it is sad_seed_topk.  topk: [K/4][Hg*Wg][4] (written);
+ * scratch: uint64[Hg*Wg] (contents undefined after). */
+sad_status sad_seed_grid(const sad_image *img, int32_t Hg, int32_t Wg, int32_t n_entries,
+                         const float *rec, uint32_t *topk, uint64_t *scratch, void *stream);
+
+/* One propagation pass on a grid: sad_propagate_topk with cells in place of pixels --
+ * neighbours at +-jump cells, candidates scored at the cell's point, injection draws of
+ * pass t numbered (t * Hg*Wg + cell) * n_inject + j.  With Hg = H, Wg = W it is
+ * sad_propagate_topk. */
+sad_status sad_propagate_grid(const sad_image *img, int32_t Hg, int32_t Wg, const float *rec,
+                              const uint32_t *topk_in, uint32_t *topk_out, int32_t jump,
+                              int32_t n_inject, uint64_t seed, uint64_t pass_index,
+                              void *stream);
+
+/* One JFA flood pass (App. B.3 "JFA prepass"), Jacobi: each cell gathers the first four
+ * entries (plane 0 of the field, "the first candidate texture") of the cells at
+ * (di step, dj step), di, dj in {-1, 0, 1}, that lie in the grid (itself included),
+ * drops empty, out-of-range and invalid IDs and repeats, scores the rest exactly at its
+ * point and writes the best four by (score descending, ID ascending) into plane 0 of
+ * topk_out.  Planes 1.. of topk_out are not written.  step >= 1. */
+sad_status sad_jfa_flood(const sad_image *img, int32_t Hg, int32_t Wg, const float *rec,
+                         const uint32_t *topk_in, uint32_t *topk_out, int32_t step,
+                         void *stream);
+
+/* Steps of the JFA prepass on an Hg x Wg grid (App. B.3: ceil(log2 max(W, H)) flood
+ * passes): L = ceil(log2 max(Hg, Wg)) steps 2^(L-1), ..., 2, 1 written to steps[]
+ * (host, room for 31); returns L, or -1 for a bad argument.  Host function. */
+int32_t sad_jfa_steps(int32_t Hg, int32_t Wg, int32_t *steps);
+
+/* A full refresh of a list field on a grid (Sec. 6.6; App. B.3): with SAD_REFRESH_JFA the
+ * JFA prepass (seed pass keeping four entries per cell, then the flood passes of
+ * sad_jfa_steps, so entries 4..K-1 start empty), otherwise the seed pass keeping K
+ * entries; then n_pass propagation passes t = 0 .. n_pass - 1 with the Sec. 4.3
+ * schedule of the grid (jump sad_jump_step(t, Hg, Wg), injection stream t).  The result
+ * is in topk; topk_tmp (the same size, not aliasing topk) is ping-pong space, scratch
+ * uint64[Hg*Wg]; the contents of both are undefined after.  The paper's render call is
+ * SAD_REFRESH_JFA with 16 passes followed by a render. */
+#define SAD_REFRESH_JFA 1u
+sad_status sad_refresh(const sad_image *img, int32_t Hg, int32_t Wg, uint32_t flags,
+                       int32_t n_pass, int32_t n_inject, uint64_t seed, const float *rec,
+                       uint32_t *topk, uint32_t *topk_tmp, uint64_t *scratch, void *stream);
+
+/* Render at an output grid of Ho x Wo points over the image from a list field of
+ * Hg x Wg cells (Sec. 4.2 blend; Sec. 6.6 re-render at a different resolution):
+ * output point (io, jo) is the centre of its cell of the output grid, takes the list of
+ * the list-grid cell holding that centre (the integer mapping above) and is blended as
+ * by sad_render_fwd at its own coordinates.  Ho = Hg, Wo = Wg renders a grid's own
+ * lists; Ho = H, Wo = W renders the image from a downscaled candidate grid; all four
+ * equal to the image is sad_render_fwd.  out: float[3][Ho][Wo] (written). */
+sad_status sad_render_grid(const sad_image *img, int32_t Hg, int32_t Wg, const float *rec,
+                           const uint32_t *topk, int32_t Ho, int32_t Wo, float *out,
+                           void *stream);
+
+/* ---- packed 16-byte inference record (App. B.2 "Packed storage for evaluation") ----
+ * Four 32-bit words per site slot (uint32[n_slots][4]):
+ *   w0 = x code | y code << 15 | 1 << 31: positions as 15-bit UNORM over [0, W-1] and
+ *        [0, H-1], bit 31 the active flag (bit 30 zero)
+ *   w1 = c_r | c_g << 11 | c_b << 22: colours as 11 / 11 / 10-bit UNORM over their
+ *        per-image [min, min + scale]
+ *   w2 = log_tau | r << 16: 16-bit UNORM each over their per-image [min, min + scale]
+ *   w3 = angle code | float16 bits of a << 16: the direction u as a 16-bit UNORM of
+ *        atan2(u_y, u_x) over [-pi, pi] (double precision)
+ * An inactive slot packs to four zero words.  A UNORM code with b bits is
+ * rint(t (2^b - 1)) with t = (v - min) / scale clamped to [0, 1] (0 when scale = 0),
+ * each step one float32 operation; it decodes to min + scale (code / (2^b - 1)).  The
+ * direction decodes to (f32(cos th), f32(sin th)) with th = code / 65535 * 2 pi - pi in
+ * double, a to the float16 value; a record without the active flag decodes to an
+ * inactive site (x = y = -1, the rest 0).  At 16 bytes per site the size in bits per
+ * pixel is n 128 / (H W) (Sec. 6.1).
+ * Quantisation parameters q: float[SAD_NQPARAM] = {log_tau min, scale, r min, scale,
+ * c_r min, scale, c_g min, scale, c_b min, scale}, min and max over the active slots
+ * < n_slots and scale = max - min (all zero without an active site). */
+#define SAD_NQPARAM 10
+
+/* q (written) from sites [10][cap] over slots < n_slots.  q is also the reduction's
+ * working memory (no other scratch). */
+sad_status sad_pack_qparams(const sad_image *img, const float *sites, float *q, void *stream);
+
+/* packed [n_slots][4] (written) from sites [10][cap] with quantisation parameters q
+ * (device, e.g. from sad_pack_qparams).  Requires H, W <= 32768. */
+sad_status sad_pack_sites(const sad_image *img, const float *sites, const float *q,
+                          uint32_t *packed, void *stream);
+
+/* Decode packed [n_slots][4] into sites [10][cap] (slots < n_slots written). */
+sad_status sad_unpack_sites(const sad_image *img, const uint32_t *packed, const float *q,
+                            float *sites, void *stream);
+
+/* Decode packed [n_slots][4] straight into derived records rec [n_slots][16] (the records
+ * sad_prepare_sites would write for the decoded sites), for the image-space calls. */
+sad_status sad_prepare_packed(const sad_image *img, const uint32_t *packed, const float *q,
+                              float *rec, void *stream);
+
+/* sad_render_fwd and sad_query_points reading the packed records: each list entry's
+ * record is decoded in place (16 bytes gathered per entry instead of the derived
+ * record's 48), with the same result as the same call on sad_prepare_packed's records. */
+sad_status sad_render_packed(const sad_image *img, const uint32_t *packed, const float *q,
+                             const uint32_t *topk, float *out, void *stream);
+sad_status sad_query_packed(const sad_image *img, const uint32_t *packed, const float *q,
+                            const uint32_t *topk, const float *xy, int64_t M, float *out,
+                            void *stream);
+
 /* ---- diagnostics ------------------------------------------------------------------ */
 const char *sad_status_string(sad_status s);
 const char *sad_last_error(void);

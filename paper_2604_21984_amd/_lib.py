@@ -96,6 +96,17 @@ def _load():
                               C.POINTER(SZ), P],
         "sad_batch_train_step": [C.POINTER(SadBatch), C.POINTER(SadTrainConfig), P, P, P, P, P, P,
                                  P, P, P, P, P, P],
+        "sad_seed_grid": [IMG, I32, I32, I32, P, P, P, P],
+        "sad_propagate_grid": [IMG, I32, I32, P, P, P, I32, I32, U64, U64, P],
+        "sad_jfa_flood": [IMG, I32, I32, P, P, P, I32, P],
+        "sad_refresh": [IMG, I32, I32, C.c_uint32, I32, I32, U64, P, P, P, P, P],
+        "sad_render_grid": [IMG, I32, I32, P, P, I32, I32, P, P],
+        "sad_pack_qparams": [IMG, P, P, P],
+        "sad_pack_sites": [IMG, P, P, P, P],
+        "sad_unpack_sites": [IMG, P, P, P, P],
+        "sad_prepare_packed": [IMG, P, P, P, P],
+        "sad_render_packed": [IMG, P, P, P, P, P],
+        "sad_query_packed": [IMG, P, P, P, P, I64, P, P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -103,6 +114,8 @@ def _load():
         fn.restype = C.c_int
     L.sad_jump_step.argtypes = [I64, I32, I32]
     L.sad_jump_step.restype = I32
+    L.sad_jfa_steps.argtypes = [I32, I32, C.POINTER(I32)]
+    L.sad_jfa_steps.restype = I32
     for name in ("sad_status_string",):
         getattr(L, name).argtypes = [C.c_int]
         getattr(L, name).restype = C.c_char_p
@@ -465,3 +478,137 @@ def query_batch(jobs_dev, n_jobs, total, K):
     _check(lib.sad_query_batch(C.c_void_p(jobs_dev.data_ptr()), int(n_jobs), int(total), int(K),
                                _stream()),
            "sad_query_batch")
+
+
+# ---- full-refresh regime: list fields on a grid of cells (sad_seed_grid ... sad_render_grid)
+
+REFRESH_JFA = 1
+
+
+def _scratch_ptr(scratch, n_bytes, name):
+    if scratch.numel() * scratch.element_size() < n_bytes:
+        raise ValueError(f"{name}: scratch needs {n_bytes} bytes")
+    return _ptr(scratch, scratch.dtype, None, "scratch")
+
+
+def seed_grid(img, Hg, Wg, n_entries, rec, topk, scratch):
+    """Seed pass on an Hg x Wg grid keeping n_entries per cell (sad_seed_grid)."""
+    Pg = int(Hg) * int(Wg)
+    _check(lib.sad_seed_grid(C.byref(img), int(Hg), int(Wg), int(n_entries),
+                             _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                             _ptr(topk, torch.int32, img.K * Pg, "topk"),
+                             _scratch_ptr(scratch, 8 * Pg, "seed_grid"), _stream()),
+           "sad_seed_grid")
+
+
+def propagate_grid(img, Hg, Wg, rec, topk_in, topk_out, jump, n_inject, seed, pass_index):
+    """One propagation pass on an Hg x Wg grid (sad_propagate_grid)."""
+    Pg = int(Hg) * int(Wg)
+    _check(lib.sad_propagate_grid(C.byref(img), int(Hg), int(Wg),
+                                  _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                                  _ptr(topk_in, torch.int32, img.K * Pg, "topk_in"),
+                                  _ptr(topk_out, torch.int32, img.K * Pg, "topk_out"),
+                                  int(jump), int(n_inject), int(seed) & (2 ** 64 - 1),
+                                  int(pass_index), _stream()),
+           "sad_propagate_grid")
+
+
+def jfa_flood(img, Hg, Wg, rec, topk_in, topk_out, step):
+    """One JFA flood pass on plane 0 of an Hg x Wg list field (sad_jfa_flood)."""
+    Pg = int(Hg) * int(Wg)
+    _check(lib.sad_jfa_flood(C.byref(img), int(Hg), int(Wg),
+                             _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                             _ptr(topk_in, torch.int32, 4 * Pg, "topk_in"),
+                             _ptr(topk_out, torch.int32, 4 * Pg, "topk_out"), int(step), _stream()),
+           "sad_jfa_flood")
+
+
+def jfa_steps(Hg, Wg):
+    buf = (C.c_int32 * 32)()
+    n = int(lib.sad_jfa_steps(int(Hg), int(Wg), buf))
+    if n < 0:
+        raise SadError("sad_jfa_steps: bad grid")
+    return [int(buf[k]) for k in range(n)]
+
+
+def refresh(img, Hg, Wg, rec, topk, topk_tmp, scratch, n_pass, n_inject, seed, jfa=True):
+    """Full refresh of an Hg x Wg list field (sad_refresh): JFA prepass (or seed pass),
+    then n_pass propagation passes; the result is in topk."""
+    Pg = int(Hg) * int(Wg)
+    _check(lib.sad_refresh(C.byref(img), int(Hg), int(Wg), REFRESH_JFA if jfa else 0, int(n_pass),
+                           int(n_inject), int(seed) & (2 ** 64 - 1),
+                           _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                           _ptr(topk, torch.int32, img.K * Pg, "topk"),
+                           _ptr(topk_tmp, torch.int32, img.K * Pg, "topk_tmp"),
+                           _scratch_ptr(scratch, 8 * Pg, "refresh"), _stream()),
+           "sad_refresh")
+
+
+def render_grid(img, Hg, Wg, rec, topk, Ho, Wo, out):
+    """Render an Ho x Wo output grid from an Hg x Wg list field (sad_render_grid)."""
+    _check(lib.sad_render_grid(C.byref(img), int(Hg), int(Wg),
+                               _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                               _ptr(topk, torch.int32, img.K * int(Hg) * int(Wg), "topk"),
+                               int(Ho), int(Wo), _ptr(out, torch.float32, 3 * int(Ho) * int(Wo), "out"),
+                               _stream()),
+           "sad_render_grid")
+
+
+# ---- packed 16-byte inference record (sad_pack_qparams ... sad_query_packed)
+
+NQPARAM = 10
+
+
+def pack_qparams(img, sites, q):
+    """Per-image quantisation parameters q [10] (device float32) from sites."""
+    _check(lib.sad_pack_qparams(C.byref(img), _ptr(sites, torch.float32, NPARAM * img.cap, "sites"),
+                                _ptr(q, torch.float32, NQPARAM, "q"), _stream()),
+           "sad_pack_qparams")
+
+
+def pack_sites(img, sites, q, packed):
+    """packed [n_slots, 4] int32 (the uint32 words) from sites with parameters q."""
+    _check(lib.sad_pack_sites(C.byref(img), _ptr(sites, torch.float32, NPARAM * img.cap, "sites"),
+                              _ptr(q, torch.float32, NQPARAM, "q"),
+                              _ptr(packed, torch.int32, 4 * img.n_slots, "packed"), _stream()),
+           "sad_pack_sites")
+
+
+def unpack_sites(img, packed, q, sites):
+    _check(lib.sad_unpack_sites(C.byref(img), _ptr(packed, torch.int32, 4 * img.n_slots, "packed"),
+                                _ptr(q, torch.float32, NQPARAM, "q"),
+                                _ptr(sites, torch.float32, NPARAM * img.cap, "sites"), _stream()),
+           "sad_unpack_sites")
+
+
+def prepare_packed(img, packed, q, rec):
+    _check(lib.sad_prepare_packed(C.byref(img), _ptr(packed, torch.int32, 4 * img.n_slots, "packed"),
+                                  _ptr(q, torch.float32, NQPARAM, "q"),
+                                  _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                                  _stream()),
+           "sad_prepare_packed")
+
+
+def render_packed(img, packed, q, topk, out):
+    P = img.H * img.W
+    _check(lib.sad_render_packed(C.byref(img), _ptr(packed, torch.int32, 4 * img.n_slots, "packed"),
+                                 _ptr(q, torch.float32, NQPARAM, "q"),
+                                 _ptr(topk, torch.int32, img.K * P, "topk"),
+                                 _ptr(out, torch.float32, 3 * P, "out"), _stream()),
+           "sad_render_packed")
+
+
+def query_packed(img, packed, q, topk, xy, out):
+    M = xy.shape[0] if xy.dim() == 2 else xy.numel() // 2
+    P = img.H * img.W
+    _check(lib.sad_query_packed(C.byref(img), _ptr(packed, torch.int32, 4 * img.n_slots, "packed"),
+                                _ptr(q, torch.float32, NQPARAM, "q"),
+                                _ptr(topk, torch.int32, img.K * P, "topk"),
+                                _ptr(xy, torch.float32, 2 * M, "xy"), int(M),
+                                _ptr(out, torch.float32, 3 * M, "out"), _stream()),
+           "sad_query_packed")
+
+
+def bpp(n_sites, H, W):
+    """Bits per pixel of n_sites packed 16-byte records over an H x W image (Sec. 6.1)."""
+    return n_sites * 16 * 8 / (H * W)

@@ -6,8 +6,12 @@
 
 namespace sad {
 
-template <int K>
-__global__ __launch_bounds__(256) void k_prop(PropArgs a, const float4 *__restrict__ rec,
+// a.H x a.W is the grid the list field lives on; with kGrid it is a candidate grid over
+// an Hi x Wi image and each cell is scored at its centre (App. B.3), otherwise the grid
+// is the image and each pixel is scored at itself.
+template <int K, bool kGrid>
+__global__ __launch_bounds__(256) void k_prop(PropArgs a, int Hi, int Wi,
+                                              const float4 *__restrict__ rec,
                                               const uint4 *__restrict__ lin,
                                               uint4 *__restrict__ lout) {
     __shared__ uint32_t queue[QueueDepth<K>::v][256];
@@ -15,7 +19,11 @@ __global__ __launch_bounds__(256) void k_prop(PropArgs a, const float4 *__restri
     const TilePix px = tile_pixel(tile, a.tiles_x);
     if (px.i >= a.H || px.j >= a.W) return;  // no block barriers below
     uint64_t keys[K];
-    prop_pixel<K>(a, rec, lin, px, queue, keys);
+    if (kGrid)
+        prop_pixel<K>(a, rec, lin, px, queue, keys, grid_point(px.j, Wi, a.W),
+                      grid_point(px.i, Hi, a.H));
+    else
+        prop_pixel<K>(a, rec, lin, px, queue, keys);
     const int64_t P = (int64_t)a.H * a.W;
     const int64_t p = (int64_t)px.i * a.W + px.j;
 #pragma unroll
@@ -25,9 +33,14 @@ __global__ __launch_bounds__(256) void k_prop(PropArgs a, const float4 *__restri
 }
 
 template <int K>
-static void launch_prop(const PropArgs &a, const float4 *rec, const uint4 *lin, uint4 *lout,
-                        hipStream_t st) {
-    hipLaunchKernelGGL(k_prop<K>, dim3(a.n_blocks), dim3(256), 0, st, a, rec, lin, lout);
+static void launch_prop(const PropArgs &a, int Hi, int Wi, const float4 *rec, const uint4 *lin,
+                        uint4 *lout, hipStream_t st) {
+    if (Hi == a.H && Wi == a.W)
+        hipLaunchKernelGGL((k_prop<K, false>), dim3(a.n_blocks), dim3(256), 0, st, a, Hi, Wi, rec,
+                           lin, lout);
+    else
+        hipLaunchKernelGGL((k_prop<K, true>), dim3(a.n_blocks), dim3(256), 0, st, a, Hi, Wi, rec,
+                           lin, lout);
 }
 
 __global__ __launch_bounds__(256) void k_fill_list(uint32_t *__restrict__ p, int64_t n) {
@@ -96,36 +109,45 @@ extern "C" int32_t sad_jump_step(int64_t t, int32_t H, int32_t W) { return jump_
 void sad::launch_propagate(const sad_image *img, const float *rec, const uint32_t *in,
                            uint32_t *out, int32_t jump, int32_t n_inject, uint64_t seed,
                            uint64_t pass, const int64_t *pass_dev, hipStream_t st) {
-    const int64_t P = (int64_t)img->H * img->W;
+    launch_propagate_grid(img, img->H, img->W, rec, in, out, jump, n_inject, seed, pass, pass_dev,
+                          st);
+}
+
+void sad::launch_propagate_grid(const sad_image *img, int32_t Hg, int32_t Wg, const float *rec,
+                                const uint32_t *in, uint32_t *out, int32_t jump, int32_t n_inject,
+                                uint64_t seed, uint64_t pass, const int64_t *pass_dev,
+                                hipStream_t st) {
+    const int64_t P = (int64_t)Hg * Wg;
     if (img->n_slots == 0) {
         const int64_t n = P * img->K;
         hipLaunchKernelGGL(k_fill_list, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, out, n);
         return;
     }
     PropArgs a;
-    a.H = img->H;
-    a.W = img->W;
+    a.H = Hg;
+    a.W = Wg;
     a.n_slots = img->n_slots;
     a.jump = jump;
     a.J = n_inject;
     a.every = 1;
-    a.tiles_x = tiles_x(img);
-    a.n_blocks = n_tiles(img);
+    a.tiles_x = (Wg + 15) / 16;
+    a.n_blocks = a.tiles_x * ((Hg + 15) / 16);
     a.seed = seed;
     a.pass = pass;
     a.pass_dev = pass_dev;
     const float4 *r4 = reinterpret_cast<const float4 *>(rec);
     const uint4 *li = reinterpret_cast<const uint4 *>(in);
     uint4 *lo = reinterpret_cast<uint4 *>(out);
+    const int Hi = img->H, Wi = img->W;
     switch (img->K) {
-        case 4: launch_prop<4>(a, r4, li, lo, st); break;
-        case 8: launch_prop<8>(a, r4, li, lo, st); break;
-        case 12: launch_prop<12>(a, r4, li, lo, st); break;
-        case 16: launch_prop<16>(a, r4, li, lo, st); break;
-        case 20: launch_prop<20>(a, r4, li, lo, st); break;
-        case 24: launch_prop<24>(a, r4, li, lo, st); break;
-        case 28: launch_prop<28>(a, r4, li, lo, st); break;
-        case 32: launch_prop<32>(a, r4, li, lo, st); break;
+        case 4: launch_prop<4>(a, Hi, Wi, r4, li, lo, st); break;
+        case 8: launch_prop<8>(a, Hi, Wi, r4, li, lo, st); break;
+        case 12: launch_prop<12>(a, Hi, Wi, r4, li, lo, st); break;
+        case 16: launch_prop<16>(a, Hi, Wi, r4, li, lo, st); break;
+        case 20: launch_prop<20>(a, Hi, Wi, r4, li, lo, st); break;
+        case 24: launch_prop<24>(a, Hi, Wi, r4, li, lo, st); break;
+        case 28: launch_prop<28>(a, Hi, Wi, r4, li, lo, st); break;
+        case 32: launch_prop<32>(a, Hi, Wi, r4, li, lo, st); break;
         default: break;
     }
 }

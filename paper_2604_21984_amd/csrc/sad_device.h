@@ -133,6 +133,23 @@ __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
     return z ^ (z >> 31);
 }
 
+// Evaluation grids (App. B.3 "Downscaled candidate grid").  A list field may live on a
+// grid of n_grid cells along an axis of n_img pixels.  Cell j is evaluated at the centre
+// of its UV interval, (j + 1/2) / n_grid, which in pixel units (pixel j at coordinate j)
+// is ((2 j + 1) n_img - n_grid) / (2 n_grid): a ratio of exact integers divided in
+// double and rounded once to float; on the image's own grid it is j exactly.
+__host__ __device__ __forceinline__ float grid_point(int j, int n_img, int n_grid) {
+    if (n_img == n_grid) return (float)j;
+    const double num = (double)(2 * (int64_t)j + 1) * (double)n_img - (double)n_grid;
+    return (float)(num / (2.0 * (double)n_grid));
+}
+// The integer map from an axis of n_from points to n_to cells: point j lies in the cell
+// whose UV interval holds its UV centre, floor((2 j + 1) n_to / (2 n_from)); for
+// n_from = s n_to that is floor(j / s), and the identity when the two are equal.
+__host__ __device__ __forceinline__ int cell_of(int j, int n_from, int n_to) {
+    return (int)(((2 * (int64_t)j + 1) * (int64_t)n_to) / (2 * (int64_t)n_from));
+}
+
 // Workgroups are handed to the eight XCDs round-robin (block b runs on XCD b % 8).
 // Remap so that each XCD works through one contiguous range of tiles: neighbouring
 // tiles then share that XCD's L2 (site records and neighbour lists).

@@ -14,6 +14,20 @@ namespace sad {
 void launch_propagate(const sad_image *img, const float *rec, const uint32_t *in, uint32_t *out,
                       int32_t jump, int32_t n_inject, uint64_t seed, uint64_t pass,
                       const int64_t *pass_dev, hipStream_t st);
+// Seed pass (App. B.3) on a grid of Hg x Wg cells over img's H x W image: every entry
+// of topk [K/4][Hg*Wg][4] cleared, then each cell keeps its best n_entries sites (the
+// sites whose nearest pixel lies in it), scored at the cell's point.  scratch:
+// uint64[Hg*Wg].
+struct SeedGrid {
+    int H, W, Hg, Wg;
+};
+void launch_seed(const sad_image *img, int32_t Hg, int32_t Wg, int32_t n_entries,
+                 const float *rec, uint32_t *topk, uint64_t *scratch, hipStream_t st);
+// The same pass on a list field of Hg x Wg cells over img's image, each cell scored at
+// its centre (App. B.3); Hg = H, Wg = W is launch_propagate.
+void launch_propagate_grid(const sad_image *img, int32_t Hg, int32_t Wg, const float *rec,
+                           const uint32_t *in, uint32_t *out, int32_t jump, int32_t n_inject,
+                           uint64_t seed, uint64_t pass, const int64_t *pass_dev, hipStream_t st);
 void launch_fwd(const sad_image *img, const float *rec, const uint32_t *topk, float *out,
                 hipStream_t st);
 void launch_loss_grad(const sad_image *img, const float *rendered, const float *target,

@@ -128,12 +128,23 @@ __device__ __forceinline__ void finish_blend(PixelBlend<K> &b, const float (*col
     b.dc[2] = d2 * inv;
 }
 
+// Where the blend gathers a site's record from: the derived records (RecSrc), or a
+// source that builds q0..q2 another way (the packed records' decoder).
+struct RecSrc {
+    const float4 *__restrict__ rec;
+    __device__ __forceinline__ void fetch(uint32_t id, float4 &q0, float4 &q1, float4 &q2) const {
+        q0 = rec[4 * (size_t)id];
+        q1 = rec[4 * (size_t)id + 1];
+        q2 = rec[4 * (size_t)id + 2];
+    }
+};
+
 // Gather and score the list of pixel p at point (X, Y); max-subtracted softmax; colour.
 // The entries are taken in the order rotated by `rot`.
-template <int K, bool kRef>
-__device__ __forceinline__ void blend(const float4 *__restrict__ rec, uint32_t ns,
-                                      const uint4 *__restrict__ topk, int64_t P, int64_t p,
-                                      float X, float Y, PixelBlend<K> &b, int rot = 0) {
+template <int K, bool kRef, class Src>
+__device__ __forceinline__ void blend_src(const Src &src, uint32_t ns,
+                                          const uint4 *__restrict__ topk, int64_t P, int64_t p,
+                                          float X, float Y, PixelBlend<K> &b, int rot = 0) {
     float m = -INFINITY;
     b.nv = 0;
     uint32_t ids[K];
@@ -152,8 +163,8 @@ __device__ __forceinline__ void blend(const float4 *__restrict__ rec, uint32_t n
         const uint32_t id = ids[k];
         const bool in_range = id < ns;
         const uint32_t idc = in_range ? id : 0u;
-        const float4 q0 = rec[4 * (size_t)idc], q1 = rec[4 * (size_t)idc + 1];
-        const float4 q2 = rec[4 * (size_t)idc + 2];
+        float4 q0, q1, q2;
+        src.fetch(idc, q0, q1, q2);
         b.id[k] = idc;
         b.ok[k] = in_range && q1.w != 0.0f;
         b.l[k] = score(q0, q1, X, Y);
@@ -166,6 +177,13 @@ __device__ __forceinline__ void blend(const float4 *__restrict__ rec, uint32_t n
         }
     }
     finish_blend<K, kRef>(b, col, m);
+}
+
+template <int K, bool kRef>
+__device__ __forceinline__ void blend(const float4 *__restrict__ rec, uint32_t ns,
+                                      const uint4 *__restrict__ topk, int64_t P, int64_t p,
+                                      float X, float Y, PixelBlend<K> &b, int rot = 0) {
+    blend_src<K, kRef>(RecSrc{rec}, ns, topk, P, p, X, Y, b, rot);
 }
 
 // The blend of a pixel from its freshly propagated keys (sorted descending, so entry 0
@@ -257,15 +275,17 @@ __device__ __forceinline__ void exact_keys(const float4 *__restrict__ rec, uint3
 // The new list of pixel (px.i, px.j) into keys[] (sorted, 0 = empty).  Lanes of pixels
 // outside the image must not call it (it votes across the wave, so call it from a
 // branch that those lanes skip).  queue: the kernel's LDS queue, Q x 256 words.
+// (X, Y) is the point the candidates are scored at: the pixel itself on the image's own
+// grid, the cell's centre on a candidate grid (a.H x a.W cells then).
 template <int K>
 __device__ __forceinline__ void prop_pixel(const PropArgs &a, const float4 *__restrict__ rec,
                                            const uint4 *__restrict__ lin, TilePix px,
-                                           uint32_t (*queue)[256], uint64_t (&keys)[K]) {
+                                           uint32_t (*queue)[256], uint64_t (&keys)[K],
+                                           float X, float Y) {
     constexpr int Q = QueueDepth<K>::v;
     const int tid = threadIdx.x;
     const int64_t P = (int64_t)a.H * a.W;
     const int64_t p = (int64_t)px.i * a.W + px.j;
-    const float X = (float)px.j, Y = (float)px.i;
     const uint32_t ns = (uint32_t)a.n_slots;
     const uint64_t it = a.pass_dev ? (uint64_t)*a.pass_dev : a.pass;
     // with an update period f, iteration it is pass it / f, and only every f-th
@@ -385,6 +405,13 @@ __device__ __forceinline__ void prop_pixel(const PropArgs &a, const float4 *__re
     }
     // 3. remaining survivors
     drain_if(Q + 1);
+}
+
+template <int K>
+__device__ __forceinline__ void prop_pixel(const PropArgs &a, const float4 *__restrict__ rec,
+                                           const uint4 *__restrict__ lin, TilePix px,
+                                           uint32_t (*queue)[256], uint64_t (&keys)[K]) {
+    prop_pixel<K>(a, rec, lin, px, queue, keys, (float)px.j, (float)px.i);
 }
 
 

@@ -8,16 +8,19 @@
 
 namespace sad {
 
-// Derived record of slot i (Sec. 4.1: G = e^a u u^T + e^-a v v^T, v = (-u_y, u_x);
-// tau = exp(log_tau); kappa = tau * s).  Transcendentals in double, rounded once.
-__device__ __forceinline__ void record_of(const float (&v)[SAD_NPARAM], int64_t i, float s,
-                                          float4 *__restrict__ rec) {
+// Derived record of a site with parameters v[] (Sec. 4.1: G = e^a u u^T + e^-a v v^T,
+// v = (-u_y, u_x); tau = exp(log_tau); kappa = tau * s), as the four float4 q0..q3 of
+// the record layout.  Transcendentals in double, rounded once.
+__device__ __forceinline__ void derive(const float (&v)[SAD_NPARAM], float s, float4 &q0,
+                                       float4 &q1, float4 &q2, float4 &q3) {
     bool finite = true;
 #pragma unroll
     for (int p = 0; p < SAD_NPARAM; ++p) finite = finite && isfinite(v[p]);
     const float x = v[0], y = v[1], lt = v[2], r = v[3], ux = v[7], uy = v[8], a = v[9];
-    float4 q0 = make_float4(x, y, 0.f, 0.f), q1 = make_float4(0.f, 0.f, r, 0.f);
-    float4 q2 = make_float4(v[4], v[5], v[6], ux), q3 = make_float4(uy, 0.f, 0.f, 0.f);
+    q0 = make_float4(x, y, 0.f, 0.f);
+    q1 = make_float4(0.f, 0.f, r, 0.f);
+    q2 = make_float4(v[4], v[5], v[6], ux);
+    q3 = make_float4(uy, 0.f, 0.f, 0.f);
     if (finite && x >= 0.0f) {
         const float tau = (float)exp((double)lt);
         const float ep = (float)exp((double)a);
@@ -39,6 +42,13 @@ __device__ __forceinline__ void record_of(const float (&v)[SAD_NPARAM], int64_t 
         q3.z = em;
         q3.w = tau;
     }
+}
+
+// Derived record of slot i written to rec[i].
+__device__ __forceinline__ void record_of(const float (&v)[SAD_NPARAM], int64_t i, float s,
+                                          float4 *__restrict__ rec) {
+    float4 q0, q1, q2, q3;
+    derive(v, s, q0, q1, q2, q3);
     rec[4 * i + 0] = q0;
     rec[4 * i + 1] = q1;
     rec[4 * i + 2] = q2;

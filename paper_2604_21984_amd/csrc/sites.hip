@@ -24,14 +24,16 @@ __global__ __launch_bounds__(256) void k_fill_u64(uint64_t *__restrict__ p, int6
     if (i < n) p[i] = v;
 }
 
-__device__ __forceinline__ int64_t seed_pixel(float x, float y, int H, int W) {
+// The cell of a site's nearest pixel (rint(y), rint(x)) clamped to the H x W image, on
+// a grid of Hg x Wg cells (the pixel itself when the grid is the image's).
+__device__ __forceinline__ int64_t seed_cell(float x, float y, const SeedGrid &g) {
     const float fi = rintf(y), fj = rintf(x);
-    const int ii = fi < 0.f ? 0 : (fi > (float)(H - 1) ? H - 1 : (int)fi);
-    const int jj = fj < 0.f ? 0 : (fj > (float)(W - 1) ? W - 1 : (int)fj);
-    return (int64_t)ii * W + jj;
+    const int ii = fi < 0.f ? 0 : (fi > (float)(g.H - 1) ? g.H - 1 : (int)fi);
+    const int jj = fj < 0.f ? 0 : (fj > (float)(g.W - 1) ? g.W - 1 : (int)fj);
+    return (int64_t)cell_of(ii, g.H, g.Hg) * g.Wg + cell_of(jj, g.W, g.Wg);
 }
 
-// Has site i already been placed in slots 0..round-1 of pixel p?
+// Has site i already been placed in entries 0..round-1 of cell p?
 __device__ __forceinline__ bool placed(const uint32_t *__restrict__ topk, int64_t P, int64_t p,
                                        int round, uint32_t i) {
     for (int k = 0; k < round; ++k)
@@ -39,37 +41,42 @@ __device__ __forceinline__ bool placed(const uint32_t *__restrict__ topk, int64_
     return false;
 }
 
+// The key of a site at the point of its seed cell.
+__device__ __forceinline__ uint64_t seed_key(const float4 q0, const float4 q1, int64_t p,
+                                             const SeedGrid &g, uint32_t i) {
+    const float X = grid_point((int)(p % g.Wg), g.W, g.Wg);
+    const float Y = grid_point((int)(p / g.Wg), g.H, g.Hg);
+    return make_key(score(q0, q1, X, Y), i);
+}
+
 // Round r of the seed pass: every valid, not yet placed site bids its key for its
-// pixel with a 64-bit atomic max; the winner takes slot r (next kernel).
-__global__ __launch_bounds__(256) void k_seed_bid(const float4 *__restrict__ rec, int n, int H,
-                                                  int W, int round,
+// cell with a 64-bit atomic max; the winner takes entry r (next kernel).
+__global__ __launch_bounds__(256) void k_seed_bid(const float4 *__restrict__ rec, int n,
+                                                  SeedGrid g, int round,
                                                   const uint32_t *__restrict__ topk,
                                                   unsigned long long *__restrict__ best) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float4 q0 = rec[4 * i], q1 = rec[4 * i + 1];
     if (q1.w == 0.0f) return;
-    const int64_t P = (int64_t)H * W;
-    const int64_t p = seed_pixel(q0.x, q0.y, H, W);
+    const int64_t P = (int64_t)g.Hg * g.Wg;
+    const int64_t p = seed_cell(q0.x, q0.y, g);
     if (placed(topk, P, p, round, (uint32_t)i)) return;
-    const float X = (float)(p % W), Y = (float)(p / W);
-    const uint64_t key = make_key(score(q0, q1, X, Y), (uint32_t)i);
-    atomicMax(best + p, (unsigned long long)key);
+    atomicMax(best + p, (unsigned long long)seed_key(q0, q1, p, g, (uint32_t)i));
 }
 
-__global__ __launch_bounds__(256) void k_seed_take(const float4 *__restrict__ rec, int n, int H,
-                                                   int W, int round, uint32_t *__restrict__ topk,
+__global__ __launch_bounds__(256) void k_seed_take(const float4 *__restrict__ rec, int n,
+                                                   SeedGrid g, int round,
+                                                   uint32_t *__restrict__ topk,
                                                    unsigned long long *__restrict__ best) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float4 q0 = rec[4 * i], q1 = rec[4 * i + 1];
     if (q1.w == 0.0f) return;
-    const int64_t P = (int64_t)H * W;
-    const int64_t p = seed_pixel(q0.x, q0.y, H, W);
+    const int64_t P = (int64_t)g.Hg * g.Wg;
+    const int64_t p = seed_cell(q0.x, q0.y, g);
     if (placed(topk, P, p, round, (uint32_t)i)) return;
-    const float X = (float)(p % W), Y = (float)(p / W);
-    const uint64_t key = make_key(score(q0, q1, X, Y), (uint32_t)i);
-    if (best[p] == (unsigned long long)key) {
+    if (best[p] == (unsigned long long)seed_key(q0, q1, p, g, (uint32_t)i)) {
         topk[((int64_t)(round >> 2) * P + p) * 4 + (round & 3)] = (uint32_t)i;
         best[p] = 0ull;  // only the winner resets; losers compare against their own key
     }
@@ -104,33 +111,39 @@ extern "C" sad_status sad_prepare_sites(const sad_image *img, const float *sites
     return check_launch("sad_prepare_sites");
 }
 
+void sad::launch_seed(const sad_image *img, int32_t Hg, int32_t Wg, int32_t n_entries,
+                      const float *rec, uint32_t *topk, uint64_t *scratch, hipStream_t st) {
+    const int64_t P = (int64_t)Hg * Wg;
+    const int64_t nl = P * img->K;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, topk, nl,
+                       SAD_INVALID_ID);
+    const int n = img->n_slots;
+    if (n == 0 || n_entries <= 0) return;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, scratch, P,
+                       0ull);
+    const float4 *r4 = reinterpret_cast<const float4 *>(rec);
+    auto *best = reinterpret_cast<unsigned long long *>(scratch);
+    SeedGrid g;
+    g.H = img->H;
+    g.W = img->W;
+    g.Hg = Hg;
+    g.Wg = Wg;
+    for (int round = 0; round < n_entries && round < img->K; ++round) {
+        hipLaunchKernelGGL(k_seed_bid, dim3((n + 255) / 256), dim3(256), 0, st, r4, n, g, round,
+                           topk, best);
+        hipLaunchKernelGGL(k_seed_take, dim3((n + 255) / 256), dim3(256), 0, st, r4, n, g, round,
+                           topk, best);
+    }
+}
+
 extern "C" sad_status sad_seed_topk(const sad_image *img, const float *rec, uint32_t *topk,
                                     uint64_t *scratch, void *stream) {
     SAD_TRY(check_image(img, nullptr));
     SAD_REQUIRE(topk && scratch && (rec || img->n_slots == 0), SAD_ERR_INVALID_ARGUMENT,
                 "sad_seed_topk: NULL pointer");
     SAD_REQUIRE(!rec || aligned16(rec), SAD_ERR_INVALID_ARGUMENT, "sad_seed_topk: rec not 16-byte aligned");
-    hipStream_t st = as_stream(stream);
-    const int64_t P = (int64_t)img->H * img->W;
-    const int64_t nl = P * img->K;
-    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, st, topk, nl,
-                       SAD_INVALID_ID);
-    SAD_TRY(check_launch("sad_seed_topk"));
-    const int n = img->n_slots;
-    if (n == 0) return SAD_OK;
-    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, scratch, P,
-                       0ull);
-    SAD_TRY(check_launch("sad_seed_topk"));
-    const float4 *r4 = reinterpret_cast<const float4 *>(rec);
-    auto *best = reinterpret_cast<unsigned long long *>(scratch);
-    for (int round = 0; round < img->K; ++round) {
-        hipLaunchKernelGGL(k_seed_bid, dim3((n + 255) / 256), dim3(256), 0, st, r4, n, img->H,
-                           img->W, round, topk, best);
-        hipLaunchKernelGGL(k_seed_take, dim3((n + 255) / 256), dim3(256), 0, st, r4, n, img->H,
-                           img->W, round, topk, best);
-        SAD_TRY(check_launch("sad_seed_topk"));
-    }
-    return SAD_OK;
+    launch_seed(img, img->H, img->W, img->K, rec, topk, scratch, as_stream(stream));
+    return check_launch("sad_seed_topk");
 }
 
 void sad::launch_adam(const sad_image *img, float s, float *sites, float *grad, float *m,

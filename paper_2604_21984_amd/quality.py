@@ -1,9 +1,9 @@
 """Quality of the propagated top-K field against the exact top-K (Sec. 6.5).
 
-A list field is built from the seed pass and n propagation passes (the jump schedule
-of Sec. 4.3, J injections per pass), and compared at sampled pixels with the exact
-top-K from ``sad_exact_topk``: "exact match" is the fraction of pixels whose K-set
-equals the exact one, "recall" the mean fraction of the exact K found.
+A list field is built from the seed pass (or the JFA prepass) and n propagation passes
+(the jump schedule of Sec. 4.3, J injections per pass), and compared at sampled pixels
+with the exact top-K from ``sad_exact_topk``: "exact match" is the fraction of pixels
+whose K-set equals the exact one, "recall" the mean fraction of the exact K found.
 """
 import numpy as np
 import torch
@@ -30,9 +30,12 @@ def _rows(lists, pix, H, W, K):
     return a.cpu().numpy().view(np.uint32)
 
 
-def convergence(sites, H, W, K=8, J=4, passes=(8, 12, 16), n_pix=256, seed=0, device="cuda"):
+def convergence(sites, H, W, K=8, J=4, passes=(8, 12, 16), n_pix=256, seed=0, device="cuda",
+                jfa=False):
     """Exact match and recall after each number of passes in `passes` for one site set
-    (float32 [10, N] host array)."""
+    (float32 [10, N] host array).  The field starts from the seed pass, or with jfa=True
+    from the JFA prepass of a full refresh (App. B.3: seed pass keeping four entries,
+    then the flood passes)."""
     N = sites.shape[1]
     img = S.image(H, W, K, N, N)
     sd = torch.from_numpy(np.ascontiguousarray(sites)).to(device)
@@ -40,7 +43,11 @@ def convergence(sites, H, W, K=8, J=4, passes=(8, 12, 16), n_pix=256, seed=0, de
     S.prepare_sites(img, sd, rec)
     a = torch.empty((K // 4, H, W, 4), dtype=torch.int32, device=device)
     b = torch.empty_like(a)
-    S.seed_topk(img, rec, a, b)
+    if jfa:
+        scratch = torch.empty(H * W, dtype=torch.int64, device=device)
+        S.refresh(img, H, W, rec, a, b, scratch, 0, J, seed ^ 0x5EED, jfa=True)
+    else:
+        S.seed_topk(img, rec, a, b)
     pix = np.sort(np.random.default_rng(seed).choice(H * W, n_pix, replace=False))
     pix_d = torch.from_numpy(pix.astype(np.int64)).to(device)
     exact = torch.empty((n_pix, K), dtype=torch.int32, device=device)

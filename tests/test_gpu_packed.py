@@ -1,0 +1,157 @@
+"""GPU parity of the packed 16-byte inference record (App. B.2) against the CPU oracle:
+quantisation parameters, the packed words, the decode (to sites and to derived
+records) and rendering / point queries that read the packed records.
+
+Words and decoded values are compared bit for bit; colours max-abs <= 1e-5 against the
+oracle's float64 blend over the oracle's decode of the same records."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import synth
+from _helpers import rows_to_planar
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def S():
+    import paper_2604_21984_amd._lib as S
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return S
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _sites(seed, H, W, n, cap=None):
+    s = synth.random_sites(seed, H, W, n, cap=cap, anisotropic=True, log_tau_range=(2.0, 9.0),
+                           r_range=(1.0, 30.0))
+    s[0:2, 3] = -1.0                  # inactive
+    s[9, 5] = np.nan                  # non-finite: inactive, packs to zeros
+    s[0, 6], s[1, 7] = 0.0, H - 1.0   # the ends of the position ranges
+    s[0, 8], s[1, 8] = W - 1.0, 0.0
+    s[7:9, 9] = (-1.0, 0.0)           # u at the angle code's ends (theta = pi)
+    s[7:9, 10] = (1.0, -0.0)
+    s[9, 11] = 1e-6                   # a float16 subnormal
+    s[4:7, 12] = 0.0                  # colour at its minimum
+    return s
+
+
+def _packed_rows(t):
+    return t.cpu().numpy().view(np.uint32).reshape(-1, 4)
+
+
+SHAPES = [(50, 70, 300, 310), (33, 47, 1, 1), (512, 768, 20000, 20000)]
+
+
+@pytest.mark.parametrize("H,W,n,cap", SHAPES)
+def test_pack_bit_exact(S, H, W, n, cap):
+    sites = _sites(3, H, W, n, cap) if n > 20 else synth.random_sites(4, H, W, n, cap=cap)
+    img = S.image(H, W, 8, n, cap)
+    sd = _t(sites)
+    q = torch.empty(S.NQPARAM, dtype=torch.float32, device=DEV)
+    S.pack_qparams(img, sd, q)
+    packed = torch.empty((n, 4), dtype=torch.int32, device=DEV)
+    S.pack_sites(img, sd, q, packed)
+    torch.cuda.synchronize()
+    qref = O.pack_qparams(sites, n)
+    assert np.array_equal(q.cpu().numpy(), qref), (q.cpu().numpy(), qref)
+    pref, _ = O.pack_sites(H, W, sites, n, qref)
+    got = _packed_rows(packed)
+    bad = np.argwhere(np.any(got != pref, axis=1)).ravel()
+    assert bad.size == 0, f"{bad.size} records differ, first {bad[:5]}: {got[bad[:3]]} vs {pref[bad[:3]]}"
+    # decode to sites, bit for bit
+    back = torch.empty((10, cap), dtype=torch.float32, device=DEV)
+    back[0:2] = -1.0
+    S.unpack_sites(img, packed, q, back)
+    torch.cuda.synchronize()
+    uref = O.unpack_sites(H, W, pref, qref, cap)
+    assert np.array_equal(back.cpu().numpy()[:, :n], uref[:, :n], equal_nan=True)
+    # decode straight to derived records: the oracle's derived values of the decode
+    rec = torch.empty(n * 16, dtype=torch.float32, device=DEV)
+    S.prepare_packed(img, packed, q, rec)
+    torch.cuda.synchronize()
+    r = rec.cpu().numpy().reshape(n, 16)
+    dref = O.site_derived(uref, n, O.default_scale(H, W))
+    valid = dref[:, 0] == 1.0
+    np.testing.assert_array_equal(r[:, 7], dref[:, 0])
+    for col_g, col_o, mul in [(15, 1, 1), (13, 2, 1), (14, 3, 1), (5, 4, 1), (2, 5, 1),
+                              (3, 6, 2), (4, 7, 1)]:
+        np.testing.assert_array_equal(r[valid, col_g], dref[valid, col_o] * np.float32(mul))
+    np.testing.assert_array_equal(r[valid, 0:2], uref[0:2, :n].T[valid])
+    np.testing.assert_array_equal(r[valid, 8:11], uref[4:7, :n].T[valid])
+
+
+def test_qparams_without_active_sites(S):
+    H, W, n = 20, 30, 6
+    sites = synth.random_sites(9, H, W, n)
+    sites[0:2, :] = -1.0
+    img = S.image(H, W, 4, n, n)
+    q = torch.full((S.NQPARAM,), 7.0, dtype=torch.float32, device=DEV)
+    S.pack_qparams(img, _t(sites), q)
+    packed = torch.full((n, 4), 5, dtype=torch.int32, device=DEV)
+    S.pack_sites(img, _t(sites), q, packed)
+    torch.cuda.synchronize()
+    assert np.all(q.cpu().numpy() == 0.0)
+    assert np.all(packed.cpu().numpy() == 0)
+
+
+@pytest.mark.parametrize("K", [4, 8, 16])
+def test_render_and_query_from_packed_records(S, K):
+    H, W, n = 96, 140, 900
+    s = O.default_scale(H, W)
+    sites = _sites(21 + K, H, W, n)
+    pref, qref = O.pack_sites(H, W, sites, n)
+    dec = O.unpack_sites(H, W, pref, qref, n)
+    lists = O.refresh(H, W, H, W, K, s, dec, n, True, 8, 4, 5)
+    img = S.image(H, W, K, n, n)
+    packed = _t(pref.view(np.int32))
+    q = _t(qref)
+    topk = _t(rows_to_planar(lists, H, W, K))
+    out = torch.empty((3, H, W), dtype=torch.float32, device=DEV)
+    S.render_packed(img, packed, q, topk, out)
+    rng = np.random.default_rng(K)
+    xy = np.stack([rng.uniform(-2, W + 1, 5000), rng.uniform(-2, H + 1, 5000)], 1).astype(np.float32)
+    col = torch.empty((5000, 3), dtype=torch.float32, device=DEV)
+    S.query_packed(img, packed, q, topk, _t(xy), col)
+    # the same through the decoded derived records and the float32-record kernels
+    rec = torch.empty(n * 16, dtype=torch.float32, device=DEV)
+    S.prepare_packed(img, packed, q, rec)
+    out2 = torch.empty_like(out)
+    S.render_fwd(img, rec, topk, out2)
+    col2 = torch.empty_like(col)
+    S.query_points(img, rec, topk, _t(xy), col2)
+    torch.cuda.synchronize()
+    ref = O.render(H, W, K, s, dec, n, lists)
+    assert float(np.abs(out.cpu().numpy() - ref).max()) <= 1e-5
+    qr = O.query(H, W, K, s, dec, n, lists, xy)
+    assert float(np.abs(col.cpu().numpy() - qr).max()) <= 1e-5
+    assert torch.equal(out, out2) and torch.equal(col, col2)
+
+
+def test_pack_2048_one_bpp_round_trip(S):
+    """2048 x 2048 at 1 bpp (32 768 records = 512 KiB): words bit-exact, decode bounded by
+    half a code step per UNORM field."""
+    H = W = 2048
+    n = H * W // 128
+    sites = synth.perturb_sites(2, synth.random_sites(1, H, W, n, log_tau=5.5, r=1.0), n, H, W)
+    img = S.image(H, W, 8, n, n)
+    sd = _t(sites)
+    q = torch.empty(S.NQPARAM, dtype=torch.float32, device=DEV)
+    packed = torch.empty((n, 4), dtype=torch.int32, device=DEV)
+    S.pack_qparams(img, sd, q)
+    S.pack_sites(img, sd, q, packed)
+    back = torch.empty_like(sd)
+    S.unpack_sites(img, packed, q, back)
+    torch.cuda.synchronize()
+    pref, qref = O.pack_sites(H, W, sites, n)
+    assert np.array_equal(_packed_rows(packed), pref)
+    b = back.cpu().numpy()
+    # half a code step, plus a few float32 roundings of values up to 2047 (resp. ~6)
+    assert np.all(np.abs(b[0] - sites[0]) <= 0.5 * (W - 1) / 32767 + 1e-3)
+    assert np.all(np.abs(b[2] - sites[2]) <= 0.5 * qref[1] / 65535 + 4e-6)
+    assert S.bpp(n, H, W) == 1.0 == O.bpp(n, H, W)

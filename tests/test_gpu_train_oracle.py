@@ -268,6 +268,8 @@ def test_batch_step_matches_oracle_per_image(S, grid, chunked, det):
         assert np.array_equal(lists, rlists), f"image {b}: lists differ"
         assert abs(losses[b] - rL) <= 1e-5 * rL, (b, losses[b], rL)
         m = be.view_sites(b, be.m).cpu().numpy().astype(np.float64)
+        if det:  # the deterministic mode's per-term rounding at this image's own P
+            ab = ab + _det_quantum(H, W, rlists, ab.shape[1])[None, :] / 1e-5
         w, plain, rep = grad_check(m / b1, rgrad, ab,
                                    f"batch grid={grid} chunked={chunked} det={det} image {b}")
         assert w <= 1.0, f"image {b}: gradient mismatch ratio {w}\n{rep}"
