@@ -98,6 +98,20 @@ sad_status sad_prepare_sites(const sad_image *img, const float *sites, float *re
 sad_status sad_seed_topk(const sad_image *img, const float *rec, uint32_t *topk,
                          uint64_t *scratch, void *stream);
 
+/* sad_seed_topk for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same result, with the
+ * per-pixel scratch taken from a static array in the library's own device memory
+ * instead of an argument.  The array holds SAD_SEED_STATIC_PIXELS uint64 words (32 MiB)
+ * on every device the library runs on, until the process ends; its address on a device
+ * is looked up on the first call made with that device current.  Images of more than
+ * SAD_SEED_STATIC_PIXELS pixels are rejected with SAD_ERR_WORKSPACE.  The call allocates
+ * nothing.  Every call on one device shares that device's array (each call clears what
+ * it uses with a kernel), so calls that overlap on one device -- on different streams or
+ * from different threads -- race and must be ordered by the caller. */
+#define SAD_SEED_STATIC_PIXELS (1 << 22)
+sad_status sad_seed_topk_noalloc(const sad_image *img, const float *rec, uint32_t *topk,
+                                 void *stream);
+
 /* ---- a3: one propagation pass (Sec. 4.3 update equation) --------------------------
  * Jacobi: reads topk_in everywhere, writes topk_out (must not alias).  Candidate set of
  * pixel p: its own list, the lists at (+-jump, 0) and (0, +-jump) that lie inside the

@@ -76,6 +76,7 @@ def _load():
     sig = {
         "sad_prepare_sites": [IMG, P, P, P],
         "sad_seed_topk": [IMG, P, P, P, P],
+        "sad_seed_topk_noalloc": [IMG, P, P, P],
         "sad_propagate_topk": [IMG, P, P, P, I32, I32, U64, U64, P],
         "sad_render_fwd": [IMG, P, P, P, P],
         "sad_loss_grad": [IMG, P, P, P, P, P],
@@ -175,6 +176,19 @@ def seed_topk(img, rec, topk, scratch):
                              _ptr(topk, torch.int32, img.K * P, "topk"),
                              _ptr(scratch, scratch.dtype, None, "scratch"), _stream()),
            "sad_seed_topk")
+
+
+SEED_STATIC_PIXELS = 1 << 22
+
+
+def seed_topk_noalloc(img, rec, topk):
+    """sad_seed_topk with the library's static per-device scratch (no allocation); images
+    of up to SEED_STATIC_PIXELS pixels."""
+    P = img.H * img.W
+    _check(lib.sad_seed_topk_noalloc(C.byref(img),
+                                     _ptr(rec, torch.float32, REC_FLOATS * img.n_slots, "rec"),
+                                     _ptr(topk, torch.int32, img.K * P, "topk"), _stream()),
+           "sad_seed_topk_noalloc")
 
 
 def propagate_topk(img, rec, topk_in, topk_out, jump, n_inject, seed, pass_index):
@@ -612,3 +626,4 @@ def query_packed(img, packed, q, topk, xy, out):
 def bpp(n_sites, H, W):
     """Bits per pixel of n_sites packed 16-byte records over an H x W image (Sec. 6.1)."""
     return n_sites * 16 * 8 / (H * W)
+

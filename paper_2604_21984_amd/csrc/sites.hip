@@ -1,5 +1,6 @@
 // sites.hip -- per-site kernels: derived records (the pack step), seed pass, Adam.
 #include <cmath>
+#include <mutex>
 
 #include "sad_device.h"
 #include "sad_host.h"
@@ -144,6 +145,56 @@ extern "C" sad_status sad_seed_topk(const sad_image *img, const float *rec, uint
     SAD_REQUIRE(!rec || aligned16(rec), SAD_ERR_INVALID_ARGUMENT, "sad_seed_topk: rec not 16-byte aligned");
     launch_seed(img, img->H, img->W, img->K, rec, topk, scratch, as_stream(stream));
     return check_launch("sad_seed_topk");
+}
+
+// ---- seed pass without allocation ---------------------------------------------------
+// The seed pass's per-pixel bid words for callers that cannot allocate: one array per
+// device, in the code object's own device memory, for images of up to
+// SAD_SEED_STATIC_PIXELS pixels (32 MiB, held on every device the library runs on until
+// the process ends).  Host code never passes the array's name to a kernel (on the host it
+// is only a stand-in for the symbol): each device's address is looked up once, with that
+// device current, and kept.
+static __device__ __align__(256) uint64_t scratch[SAD_SEED_STATIC_PIXELS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint64_t *g_scratch_dev[kMaxDevices] = {};
+
+sad_status static_scratch(uint64_t **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    SAD_REQUIRE(e == hipSuccess, SAD_ERR_DEVICE, "sad_seed_topk_noalloc: hipGetDevice: %s",
+                hipGetErrorString(e));
+    SAD_REQUIRE(dev >= 0 && dev < kMaxDevices, SAD_ERR_UNSUPPORTED,
+                "sad_seed_topk_noalloc: device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        SAD_REQUIRE(e == hipSuccess && p, SAD_ERR_DEVICE,
+                    "sad_seed_topk_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+        g_scratch_dev[dev] = static_cast<uint64_t *>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return SAD_OK;
+}
+}  // namespace
+
+extern "C" sad_status sad_seed_topk_noalloc(const sad_image *img, const float *rec,
+                                            uint32_t *topk, void *stream) {
+    SAD_TRY(check_image(img, nullptr));
+    SAD_REQUIRE(topk && (rec || img->n_slots == 0), SAD_ERR_INVALID_ARGUMENT,
+                "sad_seed_topk_noalloc: NULL pointer");
+    SAD_REQUIRE(!rec || aligned16(rec), SAD_ERR_INVALID_ARGUMENT,
+                "sad_seed_topk_noalloc: rec not 16-byte aligned");
+    SAD_REQUIRE((int64_t)img->H * img->W <= (int64_t)SAD_SEED_STATIC_PIXELS, SAD_ERR_WORKSPACE,
+                "sad_seed_topk_noalloc: %d x %d pixels exceed the static scratch of %d pixels",
+                img->H, img->W, SAD_SEED_STATIC_PIXELS);
+    uint64_t *ws = nullptr;
+    SAD_TRY(static_scratch(&ws));
+    launch_seed(img, img->H, img->W, img->K, rec, topk, ws, as_stream(stream));
+    return check_launch("sad_seed_topk_noalloc");
 }
 
 void sad::launch_adam(const sad_image *img, float s, float *sites, float *grad, float *m,
