@@ -567,6 +567,64 @@ sad_status sad_query_packed(const sad_image *img, const uint32_t *packed, const 
                             const uint32_t *topk, const float *xy, int64_t M, float *out,
                             void *stream);
 
+/* ---- tau diffusion (App. B.6) ---------------------------------------------------------
+ * One Jacobi step of the optional smoothing of the log tau gradient: for every slot
+ * i < n_slots whose record is valid, with N(i) the valid entries other than i of the list
+ * at the pixel nearest its centre ((rint(y), rint(x)) clamped),
+ *   g_out[i] = (1 - lambda) g_in[i] + lambda mean_{j in N(i)} g_in[j],
+ * and g_out[i] = g_in[i] when N(i) is empty or the record is invalid.  Element i of a
+ * gradient array is at g[i * stride]: stride 1 for the log tau row of a [10][cap]
+ * gradient (g = grad + 2 cap), stride 10 for the training step's site-major [cap][10]
+ * accumulator (g = grad + 2).  g_in and g_out must not alias; 0 <= lambda <= 1. */
+sad_status sad_tau_diffusion(const sad_image *img, const float *rec, const uint32_t *topk,
+                             const float *g_in, int64_t in_stride, float lambda, float *g_out,
+                             int64_t out_stride, void *stream);
+
+/* ---- one-dimensional SAD (Sec. 7 "1D Signal Fitting") -----------------------------------
+ * A signal of M samples, sample m at x = m.  Sites have four parameters, float[4][cap] in
+ * the order (p, c, log_tau, r); the score is the 2-D one on a line,
+ *   l_i(x) = tau_i s (r_i - |x - p_i|),   s = score_scale (0 selects 1/M),
+ * evaluated in float32 as d = x - p, n = |d|, l = kappa (r - n) + 0 with
+ * kappa = f32(exp(double log_tau)) * s.  A site is active iff p >= 0, all four values are
+ * finite and kappa is finite and > 0.  Lists: uint32[K/4][M][4] as the 2-D field, sorted
+ * by (score descending, ID ascending).  Derived records rec1: float4[n_slots] =
+ * {p, r, kappa, c}, kappa = 0 for an inactive site. */
+typedef struct {
+    int32_t M;
+    int32_t K;
+    int32_t n_slots;
+    int32_t pad;
+    int64_t cap;
+    float score_scale;
+} sad_signal;
+
+/* rec1 [n_slots] (written) from sites [4][cap]. */
+sad_status sad1d_prepare(const sad_signal *sg, const float *sites, float *rec1, void *stream);
+/* Seed pass: every entry cleared, then each active site goes to sample rint(p) (clamped)
+ * and a sample keeps the top K of its sites.  scratch: uint64[M]. */
+sad_status sad1d_seed(const sad_signal *sg, const float *rec1, uint32_t *topk,
+                      uint64_t *scratch, void *stream);
+/* One Jacobi propagation pass on the line: own list, the lists at m +- jump inside
+ * [0, M), n_inject IDs (draw j: SplitMix64 output (pass_index M + m) n_inject + j of the
+ * stream `seed`, ID = floor(hi32 n_slots / 2^32)); the top K distinct valid IDs. */
+sad_status sad1d_propagate(const sad_signal *sg, const float *rec1, const uint32_t *topk_in,
+                           uint32_t *topk_out, int32_t jump, int32_t n_inject, uint64_t seed,
+                           uint64_t pass_index, void *stream);
+/* Blend of every sample (max-subtracted softmax of its valid entries; an empty list gives
+ * 0) into out[M] (nullable).  With target[M]: L = (1/M) sum (c - I)^2 is added to
+ * loss->value (nullable), and if grad != NULL the gradients for dL/dc = (2/M)(c - I) are
+ * accumulated (+=, float atomics) into grad[4][cap]: dc += w g, gamma = w g (c_k - c),
+ * dlog_tau += gamma l, dr += gamma kappa, dp += gamma kappa sign(x - p) (0 at x = p). */
+sad_status sad1d_render(const sad_signal *sg, const float *rec1, const uint32_t *topk,
+                        const float *target, float *out, float *grad, sad_loss_acc *loss,
+                        void *stream);
+/* Adam (bias-corrected, step >= 1) on the four parameters with learning rates lr (host
+ * [4]), then p clamped to [0, M-1], log_tau to [2, 20], r to [1, 512]; inactive slots
+ * untouched.  sites, m, v: [4][cap] (updated); grad: [4][cap]. */
+sad_status sad1d_adam(const sad_signal *sg, float *sites, const float *grad, float *m, float *v,
+                      const float *lr, float beta1, float beta2, float eps, int64_t step,
+                      void *stream);
+
 /* ---- diagnostics ------------------------------------------------------------------ */
 const char *sad_status_string(sad_status s);
 const char *sad_last_error(void);

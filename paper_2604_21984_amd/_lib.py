@@ -67,6 +67,11 @@ class SadQueryJob(C.Structure):
                 ("n_slots", C.c_int32), ("pad", C.c_int32)]
 
 
+class SadSignal(C.Structure):
+    _fields_ = [("M", C.c_int32), ("K", C.c_int32), ("n_slots", C.c_int32), ("pad", C.c_int32),
+                ("cap", C.c_int64), ("score_scale", C.c_float)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
@@ -108,6 +113,12 @@ def _load():
         "sad_prepare_packed": [IMG, P, P, P, P],
         "sad_render_packed": [IMG, P, P, P, P, P],
         "sad_query_packed": [IMG, P, P, P, P, I64, P, P],
+        "sad_tau_diffusion": [IMG, P, P, P, I64, F32, P, I64, P],
+        "sad1d_prepare": [C.POINTER(SadSignal), P, P, P],
+        "sad1d_seed": [C.POINTER(SadSignal), P, P, P, P],
+        "sad1d_propagate": [C.POINTER(SadSignal), P, P, P, I32, I32, U64, U64, P],
+        "sad1d_render": [C.POINTER(SadSignal), P, P, P, P, P, P, P],
+        "sad1d_adam": [C.POINTER(SadSignal), P, P, P, P, C.POINTER(F32), F32, F32, F32, I64, P],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -627,3 +638,69 @@ def bpp(n_sites, H, W):
     """Bits per pixel of n_sites packed 16-byte records over an H x W image (Sec. 6.1)."""
     return n_sites * 16 * 8 / (H * W)
 
+
+# ---- tau diffusion and the one-dimensional SAD (sad_tau_diffusion, sad1d_*)
+
+
+def tau_diffusion(img, rec, topk, g_in, in_stride, lam, g_out, out_stride):
+    """One Jacobi step of the log tau gradient smoothing (sad_tau_diffusion); g_in, g_out
+    are float32 views whose element i sits at i * stride."""
+    n = img.n_slots
+    need_in = (n - 1) * int(in_stride) + 1 if n else 0
+    need_out = (n - 1) * int(out_stride) + 1 if n else 0
+    _check(lib.sad_tau_diffusion(C.byref(img), _ptr(rec, torch.float32, REC_FLOATS * n, "rec"),
+                                 _ptr(topk, torch.int32, img.K * img.H * img.W, "topk"),
+                                 _ptr(g_in, torch.float32, need_in, "g_in"), int(in_stride),
+                                 float(lam), _ptr(g_out, torch.float32, need_out, "g_out"),
+                                 int(out_stride), _stream()),
+           "sad_tau_diffusion")
+
+
+def signal(M, K, n_slots, cap=None, score_scale=0.0):
+    """Descriptor of a one-dimensional signal (sad_signal)."""
+    return SadSignal(int(M), int(K), int(n_slots), 0, int(cap if cap is not None else n_slots),
+                     float(score_scale))
+
+
+def prepare1d(sg, sites, rec1):
+    _check(lib.sad1d_prepare(C.byref(sg), _ptr(sites, torch.float32, 4 * sg.cap, "sites"),
+                             _ptr(rec1, torch.float32, 4 * sg.n_slots, "rec1"), _stream()),
+           "sad1d_prepare")
+
+
+def seed1d(sg, rec1, topk, scratch):
+    if scratch.numel() * scratch.element_size() < 8 * sg.M:
+        raise ValueError("seed1d: scratch needs 8 bytes per sample")
+    _check(lib.sad1d_seed(C.byref(sg), _ptr(rec1, torch.float32, 4 * sg.n_slots, "rec1"),
+                          _ptr(topk, torch.int32, sg.K * sg.M, "topk"),
+                          _ptr(scratch, scratch.dtype, None, "scratch"), _stream()),
+           "sad1d_seed")
+
+
+def propagate1d(sg, rec1, topk_in, topk_out, jump, n_inject, seed, pass_index):
+    _check(lib.sad1d_propagate(C.byref(sg), _ptr(rec1, torch.float32, 4 * sg.n_slots, "rec1"),
+                               _ptr(topk_in, torch.int32, sg.K * sg.M, "topk_in"),
+                               _ptr(topk_out, torch.int32, sg.K * sg.M, "topk_out"), int(jump),
+                               int(n_inject), int(seed) & (2 ** 64 - 1), int(pass_index),
+                               _stream()),
+           "sad1d_propagate")
+
+
+def render1d(sg, rec1, topk, target=None, out=None, grad=None, loss=None):
+    _check(lib.sad1d_render(C.byref(sg), _ptr(rec1, torch.float32, 4 * sg.n_slots, "rec1"),
+                            _ptr(topk, torch.int32, sg.K * sg.M, "topk"),
+                            _ptr(target, torch.float32, sg.M, "target"),
+                            _ptr(out, torch.float32, sg.M, "out"),
+                            _ptr(grad, torch.float32, 4 * sg.cap, "grad"),
+                            _ptr(loss, torch.float32, LOSS_ACC_FLOATS, "loss"), _stream()),
+           "sad1d_render")
+
+
+def adam1d(sg, sites, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
+    n = 4 * sg.cap
+    lr4 = (C.c_float * 4)(*[float(x) for x in lr])
+    _check(lib.sad1d_adam(C.byref(sg), _ptr(sites, torch.float32, n, "sites"),
+                          _ptr(grad, torch.float32, n, "grad"), _ptr(m, torch.float32, n, "m"),
+                          _ptr(v, torch.float32, n, "v"), lr4, float(beta1), float(beta2),
+                          float(eps), int(step), _stream()),
+           "sad1d_adam")

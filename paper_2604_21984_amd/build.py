@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsad.so")
 SOURCES = ["api.hip", "sites.hip", "prop.hip", "render.hip", "init.hip", "step.hip", "batch.hip",
-           "budget.hip", "refresh.hip", "packed.hip"]
+           "budget.hip", "refresh.hip", "packed.hip", "variants.hip"]
 ARCH = os.environ.get("SAD_OFFLOAD_ARCH", "gfx950")
 
 HIPFLAGS = [

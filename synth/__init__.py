@@ -274,3 +274,30 @@ def perturb_sites(seed, sites, n, H, W, jitter=0.5, on_centre=0.1, a_range=(-1.5
     s[8, :n] = np.sin(th)
     s[9, :n] = rng.uniform(*a_range, n)
     return s
+
+
+def sites1d(seed, M, n, cap=None, log_tau_range=(2.0, 5.0), r_range=(1.0, 4.0)):
+    """Sites of a one-dimensional signal, float32 [4, cap] in the order (p, c, log_tau, r):
+    positions uniform in [0, M-1], values uniform in [-1, 1], log_tau and r uniform in
+    their ranges; slots n..cap-1 inactive (p = -1)."""
+    rng = _rng(seed)
+    cap = n if cap is None else cap
+    s = np.zeros((4, cap), np.float32)
+    s[0, :] = -1.0
+    s[0, :n] = rng.uniform(0, M - 1, n)
+    s[1, :n] = rng.uniform(-1, 1, n)
+    s[2, :n] = rng.uniform(*log_tau_range, n)
+    s[3, :n] = rng.uniform(*r_range, n)
+    return s
+
+
+def signal1d(seed, M, n_steps=12):
+    """A one-dimensional target of M samples: n_steps random jumps (piecewise constant,
+    values in [-1, 1]) plus a slow sine and a linear ramp, float32 [M]."""
+    rng = _rng(seed)
+    x = np.arange(M, dtype=np.float64)
+    edges = np.sort(rng.uniform(0, M, n_steps))
+    levels = rng.uniform(-1, 1, n_steps + 1)
+    y = levels[np.searchsorted(edges, x)]
+    y = 0.6 * y + 0.25 * np.sin(2 * np.pi * x / rng.uniform(M / 8, M / 2)) + 0.15 * (x / M - 0.5)
+    return y.astype(np.float32)
