@@ -26,10 +26,13 @@ __device__ __forceinline__ int upper_index(int n, int64_t x, F key) {
 __device__ __forceinline__ FixScale fix_scale_dev(int64_t P) {
     const int e = fix_exponent(P);
     FixScale fx;
-    fx.to_fix = ldexp(1.0, 40 + e);
-    fx.from_fix = ldexp(1.0, -(40 + e));
+    fx.to_fix = ldexp(1.0, 32 + e);
+    fx.from_fix = ldexp(1.0, -(32 + e));
     fx.limit = (float)ldexp(1.0, 15 - e);
     fx.to_det = ldexp(1.0, 40 + e - kGlobShift);
+    fx.pre = ldexpf(1.0f, 8 + e);
+    fx.pre_det = ldexpf(1.0f, 16 + e - kGlobShift);
+    fx.post = ldexpf(1.0f, -(8 + e));
     return fx;
 }
 

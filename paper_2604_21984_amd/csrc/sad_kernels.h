@@ -439,11 +439,33 @@ __device__ __forceinline__ float *grad_at(float *grad, int q, uint32_t id, int64
 }
 
 struct FixScale {
-    double to_fix;     // 2^(40 + e)
-    double from_fix;   // 2^-(40 + e)
+    double to_fix;     // 2^(32 + e): the tile table's unit is 2^-(32 + e)
+    double from_fix;   // 2^-(32 + e)
     float limit;       // |v| must be below 2^(15 - e)
-    double to_det;     // 2^(40 + e - kGlobShift): the deterministic mode's unit
+    double to_det;     // 2^(20 + e): the deterministic mode's unit is 2^-(20 + e)
+    // The backward forms its terms from a pre-scaled dL/dc (every gradient term is
+    // linear in dL/dc, so scaling it by a power of two scales each term exactly): a
+    // term v arrives as v' = v 2^-24 / unit, |v'| < 2^23 when the term is in range,
+    // and its fixed-point integer is rint(v' 2^24) (to_fixed24).
+    float pre;         // 2^(8 + e)
+    float pre_det;     // 2^(e - 4)
+    float post;        // 2^-(8 + e): back from v' to v (float fallback)
 };
+
+// |v'| bound of a pre-scaled term that the tile table takes.
+constexpr float kHiLimit = 0x1p23f;
+
+// rint(v' 2^24) (ties to even) as a 64-bit two's complement integer, for |v'| < 2^23,
+// from float operations alone: hi = floor(v') and the fraction f = v' - hi (exact, or
+// for -1/2 < v' < 0 rounded to 2^-24 with the same tie rule as the whole, which can
+// round up to 1 for a tiny negative v'); lo = rint(f 2^24) <= 2^24; the integer is
+// hi 2^24 + lo, formed with a 64-bit add so that lo = 2^24 carries (below 2^47 in
+// magnitude).
+__device__ __forceinline__ unsigned long long to_fixed24(float vs) {
+    const float hi = floorf(vs);
+    const float lo = rintf((vs - hi) * 0x1p24f);
+    return ((unsigned long long)(long long)(int32_t)hi << 24) + (uint32_t)lo;
+}
 
 // Deterministic gradient sums (training steps with SAD_TRAIN_DETERMINISTIC): every
 // term is rounded once into units of det_grad_unit(P) (2^kGlobShift times the default
@@ -459,9 +481,10 @@ __device__ __forceinline__ long long *grad64_at(float *grad, int q, uint32_t id,
     return site_major ? g + (int64_t)id * SAD_NPARAM + q : g + q * cap + id;
 }
 
-// A term straight into the deterministic accumulator (clamped to the int64 range).
-__device__ __forceinline__ void det_add(long long *dst, float v, const FixScale &fx) {
-    double x = rint((double)v * fx.to_det);
+// A pre-scaled term v' (v' 2^24 in the deterministic unit) straight into the
+// deterministic accumulator (clamped to the int64 range).
+__device__ __forceinline__ void det_add_hi(long long *dst, float vs) {
+    double x = rint((double)vs * 0x1p24);
     x = fmin(fmax(x, -0x1p62), 0x1p62);
     atomicAdd(reinterpret_cast<unsigned long long *>(dst), (unsigned long long)(long long)x);
 }
@@ -549,6 +572,10 @@ __device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const 
             dr2 = -b.c[2];
         }
     }
+    // Every gradient term is linear in dL/dc: form them from dL/dc pre-scaled so that
+    // each term arrives in units of 2^24 table units (to_fixed24).
+    const float pre = kDet ? fx.pre_det : fx.pre;
+    const float gs0 = g0 * pre, gs1 = g1 * pre, gs2 = g2 * pre;
     // Entries are visited one at a time from the front of shifting copies of the
     // per-entry arrays (a rolled loop without dynamic register indexing), which keeps
     // one entry's records in flight and the register footprint small.
@@ -577,26 +604,29 @@ __device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const 
         const float d1 = (q2.y - cr1) - dc1;
         const float d2 = (q2.z - cr2) - dc2;
         float acc[kAcc];
-        acc[4] = w * g0;
-        acc[5] = w * g1;
-        acc[6] = w * g2;
-        const float gam = w * (g0 * d0 + g1 * d1 + g2 * d2);
+        acc[4] = w * gs0;
+        acc[5] = w * gs1;
+        acc[6] = w * gs2;
+        const float gam = w * fmaf(gs0, d0, fmaf(gs1, d1, gs2 * d2));
         acc[2] = gam * lk;
         acc[3] = gam * q1.y;
-        const float n = sqrtf(quad(q0, q1, X, Y));
         {
-            // (a select, not a branch, for n = 0: a branch here lets the compiler defer
-            // the gather of q2.w and q3 behind it, a second dependent round trip)
+            // n by the hardware square root (a gradient term needs no correctly rounded
+            // n); a select, not a branch, for n = 0, so that the gathers of q2.w and q3
+            // are not deferred behind it
+            const float dx = X - q0.x, dy = Y - q0.y;
+            const float t = fmaf(q0.w, dy, q0.z * dx);
+            const float n = __builtin_amdgcn_sqrtf(fmaxf(fmaf(t, dx, q1.x * dy * dy), 0.0f));
             const float rho = n > 0.f ? -0.5f * gam * q1.y * __builtin_amdgcn_rcpf(n) : 0.f;
             const float ux = q2.w, uy = q3.x, ep = q3.y, em = q3.z;
-            const float dx = X - q0.x, dy = Y - q0.y;
-            const float al = ux * dx + uy * dy, be = ux * dy - uy * dx;
+            const float al = fmaf(ux, dx, uy * dy), be = fmaf(ux, dy, -(uy * dx));
             const float A = ep * al, B = em * be;
-            acc[0] = -2.0f * rho * (A * ux - B * uy);
-            acc[1] = -2.0f * rho * (A * uy + B * ux);
-            acc[9] = rho * (A * al - B * be);
-            acc[7] = 2.0f * rho * (A * dx + B * dy);
-            acc[8] = 2.0f * rho * (A * dy - B * dx);
+            const float r2 = 2.0f * rho;
+            acc[0] = -r2 * fmaf(A, ux, -(B * uy));
+            acc[1] = -r2 * fmaf(A, uy, B * ux);
+            acc[9] = rho * fmaf(A, al, -(B * be));
+            acc[7] = r2 * fmaf(A, dx, B * dy);
+            acc[8] = r2 * fmaf(A, dy, -(B * dx));
         }
         acc[10] = 0.f;
         if (kRD) {
@@ -612,31 +642,31 @@ __device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const 
                 p2 = f * d2;
             }
             acc[10] = (p0 * (p0 + 2.0f * e0) + p1 * (p1 + 2.0f * e1) +
-                       p2 * (p2 + 2.0f * e2)) * inv_P;
+                       p2 * (p2 + 2.0f * e2)) * (inv_P * pre);
         }
         const int slot = hash_slot(hkey, id);
         constexpr int nq = kRD ? kAcc : 10;
-        // Every term is added to the table (zero when it goes to global memory instead),
-        // so the ten adds are straight-line code; the rare out-of-range or table-full
-        // terms follow in one branch.
-        const int sl = slot >= 0 ? slot : 0;
-        bool spill = false;
+        // One range test per entry: the table takes all of the entry's terms when their
+        // absolute sum is in range (a NaN fails the test and reaches global memory), else
+        // every non-zero term goes to global memory.  Every term is added to the table
+        // (zero when it goes global), so the adds are straight-line code.
+        float asum = fabsf(acc[0]);
 #pragma unroll
-        for (int q = 0; q < nq; ++q) {
-            const bool in = slot >= 0 && fabsf(acc[q]) < fx.limit;
-            spill |= !in && acc[q] != 0.0f;
-            atomicAdd(&hacc[q][sl], in ? to_fixed(acc[q], kDet ? fx.to_det : fx.to_fix) : 0ull);
-        }
-        if (spill) {
+        for (int q = 1; q < nq; ++q) asum += fabsf(acc[q]);
+        const bool in = slot >= 0 && asum < kHiLimit;
+        const int sl = slot >= 0 ? slot : 0;
+#pragma unroll
+        for (int q = 0; q < nq; ++q)
+            atomicAdd(&hacc[q][sl], in ? to_fixed24(acc[q]) : 0ull);
+        if (!in) {
 #pragma unroll
             for (int q = 0; q < nq; ++q) {
-                const bool in = slot >= 0 && fabsf(acc[q]) < fx.limit;
-                if (in || acc[q] == 0.0f) continue;
+                if (acc[q] == 0.0f) continue;
                 if (kDet && q < 10)
-                    det_add(grad64_at(grad, q, id, cap, kSiteMajor), acc[q], fx);
+                    det_add_hi(grad64_at(grad, q, id, cap, kSiteMajor), acc[q]);
                 else
                     atomic_add_f32(q < 10 ? grad_at<kSiteMajor>(grad, q, id, cap) : rdel + id,
-                                   acc[q]);
+                                   acc[q] * fx.post);
             }
         }
     }
@@ -694,10 +724,13 @@ __device__ __forceinline__ void bwd_flush(const uint32_t *__restrict__ hkey,
 inline FixScale fix_scale(int64_t P) {
     const int e = fix_exponent(P);
     FixScale fx;
-    fx.to_fix = std::ldexp(1.0, 40 + e);
-    fx.from_fix = std::ldexp(1.0, -(40 + e));
+    fx.to_fix = std::ldexp(1.0, 32 + e);
+    fx.from_fix = std::ldexp(1.0, -(32 + e));
     fx.limit = (float)std::ldexp(1.0, 15 - e);
     fx.to_det = std::ldexp(1.0, 40 + e - kGlobShift);
+    fx.pre = std::ldexp(1.0f, 8 + e);
+    fx.pre_det = std::ldexp(1.0f, 16 + e - kGlobShift);
+    fx.post = std::ldexp(1.0f, -(8 + e));
     return fx;
 }
 
