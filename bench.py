@@ -112,16 +112,18 @@ def cpu_baseline(target_np, sites_np, lists_np, budget_s, threads):
     return H * W * steps / el / 1e6, steps, el
 
 
-def autograd_path(enc, steps):
-    """Iterations through the torch.autograd.Function wrappers (propagation pass, lists
-    not differentiable; SADRender forward; SADMSELoss; backward; Adam on sites.grad),
-    counters in a device step state: eagerly, and recorded as one HIP graph of up to 50
-    iterations and replayed."""
+def autograd_path(enc, steps, fused=False):
+    """Iterations through the torch.autograd.Function wrappers, counters in a device step
+    state: eagerly, and recorded as one HIP graph of up to 50 iterations and replayed.
+    Plain: propagation pass (lists not differentiable), SADRender forward, SADMSELoss,
+    backward (the backward kernel recomputes the blend weights), Adam on sites.grad.
+    Fused: SADTrainPass (pass, blend, loss and backward in one kernel behind the
+    Function; backward hands out the gradient), Adam on sites.grad."""
     import torch
 
     from paper_2604_21984_amd import autograd as A
-    tr = A.AutogradTrainer(enc.img, enc.sites, enc.topk, enc.target, enc.adam, n_inject=J,
-                           seed=77)
+    cls = A.FusedAutogradTrainer if fused else A.AutogradTrainer
+    tr = cls(enc.img, enc.sites, enc.topk, enc.target, enc.adam, n_inject=J, seed=77)
     for _ in range(4):
         tr.step()
     torch.cuda.synchronize()
@@ -148,8 +150,9 @@ def autograd_path(enc, steps):
             "graph_mpix_s": round(enc.H * enc.W / (gms * 1e3), 1),
             "graph_steps": 2 * gp * reps, "iterations_per_graph": 2 * gp,
             "loss": round(float(tr.loss.item()), 6),
-            "path": "propagate_topk_state + SADRender.apply + SADMSELoss.apply + backward "
-                    "+ adam_step_state (eager, and recorded as one HIP graph)"}
+            "path": ("SADTrainPass.apply (fused pass) + backward + adam_step_state" if fused else
+                     "propagate_topk_state + SADRender.apply + SADMSELoss.apply + backward "
+                     "+ adam_step_state") + " (eager, and recorded as one HIP graph)"}
 
 
 def whole_encode(iterations, seed=0):
@@ -947,6 +950,7 @@ def main():
 
     if args.autograd_steps > 0:
         extra("autograd", autograd_path, enc, args.autograd_steps)
+        extra("autograd_fused", autograd_path, enc, args.autograd_steps, True)
     if args.encode_iterations > 0:
         extra("whole_encode", whole_encode, args.encode_iterations)
     if args.det_steps > 0:

@@ -303,6 +303,15 @@ sad_status sad_train_image_pass(const sad_image *img, const sad_train_config *cf
                                 uint32_t *topk_out, float *grad_sites, float *rendered,
                                 float *grad_img, sad_step_state *state, void *stream);
 
+/* The training pass's site-major gradient acc [cap][10] in the layout of the sites,
+ * grad [10][cap] (written, every slot < cap): grad[q][i] = scale * acc[i][q] with scale =
+ * *scale (a DEVICE float, e.g. the incoming gradient of an autograd backward) or 1 when
+ * scale is NULL.  With SAD_GRAD_CLEAR_SOURCE, acc is zeroed after it is read (ready for
+ * the next pass).  Float accumulators only (not the deterministic int64 form). */
+#define SAD_GRAD_CLEAR_SOURCE 1u
+sad_status sad_grad_to_params(const sad_image *img, float *grad_site_major, const float *scale,
+                              float *grad, uint32_t flags, void *stream);
+
 /* Device-counter forms of sad_propagate_topk and sad_adam_step (Sec. 4.3 schedule,
  * Sec. 5 Adam), for an iteration assembled from the separate calls (e.g. around the
  * autograd wrapper) and recorded once into a HIP graph: the counters live in a

@@ -114,6 +114,7 @@ def _load():
         "sad_render_packed": [IMG, P, P, P, P, P],
         "sad_query_packed": [IMG, P, P, P, P, I64, P, P],
         "sad_tau_diffusion": [IMG, P, P, P, I64, F32, P, I64, P],
+        "sad_grad_to_params": [IMG, P, P, P, C.c_uint32, P],
         "sad1d_prepare": [C.POINTER(SadSignal), P, P, P],
         "sad1d_seed": [C.POINTER(SadSignal), P, P, P, P],
         "sad1d_propagate": [C.POINTER(SadSignal), P, P, P, I32, I32, U64, U64, P],
@@ -476,6 +477,20 @@ def train_image_pass(img, cfg, target, rec, topk_in, topk_out, grad, rendered, g
                                     _ptr(grad_img, torch.float32, 3 * P, "grad_img"),
                                     _ptr(state, torch.int64, STEP_STATE_INT64, "state"), _stream()),
            "sad_train_image_pass")
+
+
+GRAD_CLEAR_SOURCE = 1
+
+
+def grad_to_params(img, grad_site_major, grad, scale=None, clear=False):
+    """grad [10][cap] = scale * transpose(grad_site_major [cap][10]) (sad_grad_to_params);
+    scale: a device float tensor or None; clear zeroes the source."""
+    n = NPARAM * img.cap
+    _check(lib.sad_grad_to_params(C.byref(img), _ptr(grad_site_major, torch.float32, n, "grad_site_major"),
+                                  _ptr(scale, torch.float32, 1, "scale"),
+                                  _ptr(grad, torch.float32, n, "grad"),
+                                  GRAD_CLEAR_SOURCE if clear else 0, _stream()),
+           "sad_grad_to_params")
 
 
 def batch_train_step(batch, cfg, target, sites, rec, topk_in, topk_out, grad, m, v, rendered,

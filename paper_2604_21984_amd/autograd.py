@@ -7,6 +7,9 @@ differentiable) -> image [3, H, W].  The forward stores nothing but the derived
 records and the lists; the backward recomputes the blend weights.
 ``SADMSELoss``: L = (1/P) sum_x ||c(x) - I(x)||^2 (Sec. 6.1) with its gradient formed
 by the loss kernel in the forward call.
+``SADTrainPass``: sites -> L for one whole pass (propagation, blend, loss, backward in
+the fused kernel); the gradient is formed in the forward launch and handed out by the
+backward.
 """
 import torch
 
@@ -45,6 +48,32 @@ class SADMSELoss(torch.autograd.Function):
     def backward(ctx, g):
         (grad,) = ctx.saved_tensors
         return grad * g, None, None
+
+
+class SADTrainPass(torch.autograd.Function):
+    """One propagation pass, blend, MSE loss and backward in a single kernel (the fused
+    training pass, ``sad_train_image_pass``): the forward returns L and forms dL/dsites
+    in the same launch (site-major accumulator, nothing else stored); the backward
+    returns grad_output * dL/dsites in the layout of the sites (``sad_grad_to_params``,
+    which also clears the accumulator for the next call).  The lists are not
+    differentiable; the pass index comes from the device step state."""
+
+    @staticmethod
+    def forward(ctx, sites, target, img, cfg, rec, topk_in, topk_out, gacc, state, prepare):
+        if prepare:
+            S.prepare_sites(img, sites.detach(), rec)
+        S.state_loss(state).zero_()
+        S.train_image_pass(img, cfg, target, rec, topk_in, topk_out, gacc, None, None, state)
+        ctx.img, ctx.cap = img, sites.shape[1]
+        ctx.gacc = gacc
+        return S.state_loss(state).clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        grad = torch.empty((10, ctx.cap), dtype=torch.float32, device=g.device)
+        S.grad_to_params(ctx.img, ctx.gacc, grad, scale=g.detach().reshape(1).contiguous(),
+                         clear=True)
+        return grad, None, None, None, None, None, None, None, None, None
 
 
 def render(sites, topk, img, rec=None):
@@ -119,3 +148,25 @@ class AutogradTrainer:
     def counters(self):
         """(pass, adam_step) on the host (synchronises)."""
         return tuple(int(x) for x in S.state_counters(self.state).cpu())
+
+
+class FusedAutogradTrainer(AutogradTrainer):
+    """Training iterations through ``SADTrainPass``: the pass, blend, loss and backward of
+    an iteration are one kernel behind the autograd Function; ``backward()`` lays the
+    gradient out as ``sites.grad`` and Adam (which also refreshes the derived records and
+    advances the device counters) follows.  Recordable as a HIP graph like the parent."""
+
+    def __init__(self, img, sites, topk, target, adam, n_inject=4, seed=0):
+        super().__init__(img, sites, topk, target, adam, n_inject, seed)
+        self.cfg = S.train_config(self.J, self.seed, adam)
+        self.gacc = torch.zeros((img.cap, 10), dtype=torch.float32, device=sites.device)
+
+    def step(self):
+        a, b = self.lists[self.cur], self.lists[1 - self.cur]
+        loss = SADTrainPass.apply(self.sites, self.target, self.img, self.cfg, self.rec, a, b,
+                                  self.gacc, self.state, False)
+        loss.backward()
+        self.loss = loss.detach()
+        S.adam_step_state(self.img, self.sites.data, self.sites.grad, self.m, self.v,
+                          self.adam, self.rec, self.state, zero_grad=True)
+        self.cur = 1 - self.cur

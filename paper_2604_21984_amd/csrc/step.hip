@@ -70,6 +70,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K == 16 ? 4
     bwd_flush<false, true, kDet>(hkey, hacc, fx, a.cap, grad, nullptr, occ);
 }
 
+// grad[q][i] = scale * acc[i][q] for every slot i < cap (scale = *scale_dev, or 1), and
+// with clear the source row is zeroed after it has been read.
+__global__ __launch_bounds__(256) void k_grad_to_params(float *__restrict__ acc,
+                                                        const float *__restrict__ scale_dev,
+                                                        float *__restrict__ grad, int64_t cap,
+                                                        int clear) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cap) return;
+    const float sc = scale_dev ? *scale_dev : 1.0f;
+    float v[SAD_NPARAM];
+#pragma unroll
+    for (int q = 0; q < SAD_NPARAM; ++q) v[q] = acc[i * SAD_NPARAM + q];
+#pragma unroll
+    for (int q = 0; q < SAD_NPARAM; ++q) grad[q * cap + i] = sc * v[q];
+    if (clear) {
+#pragma unroll
+        for (int q = 0; q < SAD_NPARAM; ++q) acc[i * SAD_NPARAM + q] = 0.0f;
+    }
+}
+
 __global__ void k_state_advance(sad_step_state *__restrict__ s) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         s->pass += 1;
@@ -196,4 +216,21 @@ extern "C" sad_status sad_train_step(const sad_image *img, const sad_train_confi
     launch_adam(img, s, sites, grad_sites, adam_m, adam_v, &cfg->adam, 1, &state->adam_step, rec,
                 true, true, state, st, (cfg->flags & SAD_TRAIN_DETERMINISTIC) != 0);
     return check_launch("sad_train_step");
+}
+
+extern "C" sad_status sad_grad_to_params(const sad_image *img, float *grad_site_major,
+                                         const float *scale, float *grad, uint32_t flags,
+                                         void *stream) {
+    SAD_TRY(check_image(img, nullptr));
+    SAD_REQUIRE(grad_site_major && grad, SAD_ERR_INVALID_ARGUMENT,
+                "sad_grad_to_params: NULL pointer");
+    SAD_REQUIRE(grad_site_major != grad, SAD_ERR_INVALID_ARGUMENT,
+                "sad_grad_to_params: source and destination must not alias");
+    SAD_REQUIRE((flags & ~SAD_GRAD_CLEAR_SOURCE) == 0, SAD_ERR_INVALID_ARGUMENT,
+                "sad_grad_to_params: unknown flags 0x%x", flags);
+    if (img->cap == 0) return SAD_OK;
+    hipLaunchKernelGGL(k_grad_to_params, dim3((unsigned)((img->cap + 255) / 256)), dim3(256), 0,
+                       as_stream(stream), grad_site_major, scale, grad, img->cap,
+                       (flags & SAD_GRAD_CLEAR_SOURCE) ? 1 : 0);
+    return check_launch("sad_grad_to_params");
 }

@@ -136,6 +136,75 @@ def test_autograd_render_matches_oracle(mods):
     assert grad_close(sites.grad.cpu().numpy(), ref, ab) <= 1.0
 
 
+def test_fused_autograd_pass_matches_oracle(mods):
+    """SADTrainPass: one fused pass behind the autograd Function; the loss, the new lists
+    and the gradient (handed out by backward, scaled by the incoming gradient) against
+    the oracle's pass, blend, loss and backward; the accumulator is cleared for the next
+    call."""
+    S, A, E = mods
+    H, W, N, K, J, seed = 40, 52, 150, 8, 3, 17
+    sites_np = synth.random_sites(4, H, W, N, cap=160, anisotropic=True,
+                                  log_tau_range=(3, 6), r_range=(1, 3))
+    s = O.default_scale(H, W)
+    lists = O.seed_lists(H, W, K, s, sites_np, N)
+    for t in range(5):
+        lists = O.prop_pass(H, W, K, s, sites_np, N, lists, O.jump(t, H, W), J, seed, t)
+    target_np = synth.image_encode(2, H, W, n_polygons=8, patch=16)
+    img = S.image(H, W, K, N, 160)
+    sites = torch.from_numpy(sites_np).to(DEV).requires_grad_(True)
+    topk_in = torch.from_numpy(rows_to_planar(lists, H, W, K)).to(DEV)
+    topk_out = torch.empty_like(topk_in)
+    target = torch.from_numpy(target_np).to(DEV)
+    rec = torch.empty(N * S.REC_FLOATS, dtype=torch.float32, device=DEV)
+    gacc = torch.zeros((160, 10), dtype=torch.float32, device=DEV)
+    state = S.step_state(DEV)
+    state[0] = 5
+    cfg = S.train_config(J, seed, S.adam_params([0.0] * 10))
+    loss = A.SADTrainPass.apply(sites, target, img, cfg, rec, topk_in, topk_out, gacc, state, True)
+    (3.0 * loss).backward()
+    new = O.prop_pass(H, W, K, s, sites_np, N, lists, O.jump(5, H, W), J, seed, 5)
+    ref_img = O.render(H, W, K, s, sites_np, N, new)
+    L, g = O.loss_grad(ref_img, target_np)
+    ref, ab = O.render_bwd(H, W, K, s, sites_np, N, new, g, abs_sum=True)
+    assert np.array_equal(planar_to_rows(topk_out.cpu().numpy(), H, W, K), new)
+    assert abs(loss.item() - L) <= 1e-5 * L
+    assert grad_close(sites.grad.cpu().numpy() / 3.0, ref, ab) <= 1.0
+    assert float(gacc.abs().max()) == 0.0
+
+
+def test_fused_autograd_trainer_graph_matches_eager(mods):
+    """FusedAutogradTrainer recorded as a HIP graph against the same iterations eagerly;
+    its trajectory also follows the separate-kernel autograd trainer."""
+    S, A, E = mods
+    enc = _enc(E, seed=6)
+    for _ in range(4):
+        enc.step()
+    torch.cuda.synchronize()
+    mk = lambda cls: cls(enc.img, enc.sites, enc.topk, enc.target, enc.adam, n_inject=4,
+                         seed=11)
+    eager, graphed = mk(A.FusedAutogradTrainer), mk(A.FusedAutogradTrainer)
+    plain = mk(A.AutogradTrainer)
+    graphed.capture(pairs=1, warmup=2)
+    for _ in range(4):
+        eager.step()
+        plain.step()
+    torch.cuda.synchronize()
+    assert graphed.counters() == eager.counters() == plain.counters() == (4, 4)
+    for r in range(4):
+        graphed.replay(1)
+        for _ in range(2):
+            eager.step()
+            plain.step()
+        torch.cuda.synchronize()
+        assert graphed.counters() == eager.counters() == (6 + 2 * r, 6 + 2 * r)
+        np.testing.assert_allclose(graphed.loss.item(), eager.loss.item(), rtol=1e-4)
+        np.testing.assert_allclose(plain.loss.item(), eager.loss.item(), rtol=1e-3)
+        torch.testing.assert_close(graphed.sites.detach(), eager.sites.detach(),
+                                   rtol=1e-4, atol=1e-4)
+        torch.testing.assert_close(plain.sites.detach(), eager.sites.detach(),
+                                   rtol=1e-3, atol=1e-3)
+
+
 def test_encode_improves_psnr(mods):
     S, A, E = mods
     enc = _enc(E, H=128, W=192, N=1500, seed=5)
