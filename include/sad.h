@@ -345,8 +345,8 @@ sad_status sad_adam_step_state(const sad_image *img, float *sites, float *grad, 
 typedef struct {
     int32_t H, W;
     int32_t n_slots;
-    int32_t tile0;      /* first work item (16x16 tile) of this image; items are
-                           numbered image by image in raster order of tiles */
+    int32_t tile0;      /* first work item (tile of the batch's shape) of this image;
+                           items are numbered image by image in raster order of tiles */
     int64_t cap;
     int64_t px0;        /* pixels of the images before this one */
     int64_t site0;      /* site slots (sum of cap) of the images before this one */
@@ -357,12 +357,14 @@ typedef struct {
 typedef struct {
     int32_t n_images;
     int32_t K;
-    int32_t n_items;           /* total 16x16 tiles of all images */
+    int32_t n_items;           /* total tiles of all images (tile shape: tile_w) */
     int32_t grid;              /* persistent workgroups; 0 => one per tile */
     int32_t chunked;           /* 0: item i goes to workgroup i mod grid; 1: each
                                   workgroup takes a contiguous run of items (its XCD's
                                   L2 then holds neighbouring tiles) */
-    int32_t pad;
+    int32_t tile_w;            /* work-item tile: 0 or 16 = 16 x 16 pixels, 32 = 32 x 8
+                                  (four 8 x 8 wave64 blocks either way); n_items and each
+                                  image's tile0 count tiles of this shape */
     int64_t n_site_slots;      /* sum of cap over the images */
     const sad_batch_image *images;  /* DEVICE array [n_images], tile0 increasing */
 } sad_batch;

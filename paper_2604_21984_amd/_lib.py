@@ -51,7 +51,7 @@ class SadBatchImage(C.Structure):
 
 class SadBatch(C.Structure):
     _fields_ = [("n_images", C.c_int32), ("K", C.c_int32), ("n_items", C.c_int32),
-                ("grid", C.c_int32), ("chunked", C.c_int32), ("pad", C.c_int32),
+                ("grid", C.c_int32), ("chunked", C.c_int32), ("tile_w", C.c_int32),
                 ("n_site_slots", C.c_int64), ("images", C.c_void_p)]
 
 

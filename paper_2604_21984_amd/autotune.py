@@ -1,11 +1,15 @@
 """Autotuner for the batched persistent launch.
 
-Picks the persistent grid size (workgroups per compute unit) and the work assignment
-(contiguous runs of tiles per workgroup, which keeps neighbouring tiles in one XCD's L2,
-or round robin) by timing graph-replayed iterations of the actual batch, then the
+Picks the tile shape of the work items (16 x 16 or 32 x 8 pixels), the persistent grid
+size (workgroups per compute unit) and the work assignment (contiguous runs of tiles per
+workgroup, which keeps neighbouring tiles in one XCD's L2, or round robin) by timing
+graph-replayed iterations of the actual batch, then the
 propagation schedule: the candidate update period f (propagate every f-th iteration,
-App. B.3), the fastest f whose batch loss after a trial window stays within `tol` of
-the loss with f = 1 from the same state.  The trials start from the state reached after
+App. B.3), judged at equal wall time: from the same state, f = 1 runs `window`
+iterations and every other period runs as many iterations as fit in the same time (from
+its own measured iteration time); the period with the lowest batch loss at that time
+wins, so a period is only picked when its cheaper iterations buy more progress than they
+lose.  The trials start from the state reached after
 `warm` iterations past the current one (the first iterations of an encode take the
 long jumps of the schedule with unsettled lists and cost many times the steady state,
 so timing them would tune for the wrong regime).  The batch's state is restored after
@@ -39,15 +43,18 @@ class Autotuner:
             with open(cache_path) as f:
                 self.cache = json.load(f)
 
-    def tune(self, enc, pairs=3, reps=2, schedules=(1,), window=16, tol=0.01, warm=12):
-        """Return (grid, chunked, timings) for a BatchEncoder and apply the best launch;
+    def tune(self, enc, pairs=3, reps=2, schedules=(1,), window=64, warm=12,
+             tile_widths=(16, 32)):
+        """Return (grid, chunked, timings) for a BatchEncoder and apply the best launch
+        (its tile width is then enc.tile_w);
         with more than one candidate update period in `schedules` also pick and apply
         the period (reported under timings["prop_every"]).  `warm` (even) iterations
         are run first; every trial starts from the state they reach."""
-        sig = _signature(enc) + f"|f{','.join(map(str, schedules))}"
+        sig = (_signature(enc) + f"|f{','.join(map(str, schedules))}"
+               f"|t{','.join(map(str, tile_widths))}")
         if sig in self.cache:
-            grid, chunked = self.cache[sig]["best"]
-            enc.set_launch(grid, chunked)
+            grid, chunked, tw = self.cache[sig]["best"]
+            enc.set_launch(grid, chunked, tw)
             if "prop_every" in self.cache[sig]:
                 enc.set_prop_every(self.cache[sig]["prop_every"])
             return grid, chunked, self.cache[sig]["timings"]
@@ -57,48 +64,62 @@ class Autotuner:
             enc.step()
         snap = enc.snapshot()
         timings = {}
-        for grid, chunked in candidates(enc.T_tot, n_cu):
-            enc.restore(snap)
-            enc.set_launch(grid, chunked)
-            enc.capture()
-            enc.replay(1)
-            torch.cuda.synchronize()
-            best = float("inf")
-            for _ in range(reps):
+        for tw in tile_widths:
+            enc.set_launch(0, 0, tw)
+            for grid, chunked in candidates(enc.T_tot, n_cu):
+                enc.restore(snap)
+                enc.set_launch(grid, chunked, tw)
+                enc.capture()
+                enc.replay(1)
+                torch.cuda.synchronize()
+                best = float("inf")
+                for _ in range(reps):
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    enc.replay(pairs)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    best = min(best, e0.elapsed_time(e1) / (2 * pairs))
+                timings[f"{grid}/{chunked}/{tw}"] = best
+        enc.restore(orig)
+        key = min(timings, key=timings.get)
+        grid, chunked, tw = (int(x) for x in key.split("/"))
+        enc.set_launch(grid, chunked, tw)
+        self.cache[sig] = {"best": [grid, chunked, tw], "timings": timings}
+        if len(schedules) > 1:
+            sched = {}
+
+            def run(n_pairs):
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record()
-                enc.replay(pairs)
+                enc.replay(n_pairs)
                 e1.record()
                 torch.cuda.synchronize()
-                best = min(best, e0.elapsed_time(e1) / (2 * pairs))
-            timings[f"{grid}/{chunked}"] = best
-        enc.restore(orig)
-        key = min(timings, key=timings.get)
-        grid, chunked = (int(x) for x in key.split("/"))
-        enc.set_launch(grid, chunked)
-        self.cache[sig] = {"best": [grid, chunked], "timings": timings}
-        if len(schedules) > 1:
-            sched = {}
-            for f in schedules:
+                return e0.elapsed_time(e1)
+
+            per_it = {}
+            for f in schedules:       # iteration time of each period (short window)
                 enc.restore(snap)
                 enc.set_prop_every(f)
                 enc.capture()
+                enc.replay(1)
                 torch.cuda.synchronize()
-                e0 = torch.cuda.Event(enable_timing=True)
-                e1 = torch.cuda.Event(enable_timing=True)
-                e0.record()
-                enc.replay(max(1, window // 2))
-                e1.record()
-                torch.cuda.synchronize()
-                ms = e0.elapsed_time(e1) / (2 * max(1, window // 2))
-                sched[f] = (ms, sum(enc.losses()))
-            base = sched[schedules[0]][1]
-            ok = [f for f in schedules if sched[f][1] <= base * (1.0 + tol)]
-            best_f = min(ok, key=lambda f: sched[f][0])
+                per_it[f] = run(4) / 8
+            budget = per_it[schedules[0]] * window   # wall time of `window` iterations at f_0
+            for f in schedules:
+                n_pairs = max(1, int(budget / per_it[f]) // 2)
+                enc.restore(snap)
+                enc.set_prop_every(f)
+                enc.capture()
+                run(n_pairs)
+                sched[f] = (per_it[f], 2 * n_pairs, sum(enc.losses()))
+            best_f = min(schedules, key=lambda f: (sched[f][2], f))
             enc.restore(orig)
             enc.set_prop_every(best_f)
-            timings["prop_every"] = {str(f): {"ms": v[0], "loss": v[1]} for f, v in sched.items()}
+            timings["prop_every"] = {str(f): {"ms": v[0], "iterations": v[1], "loss": v[2]}
+                                     for f, v in sched.items()}
             timings["prop_every_best"] = best_f
             self.cache[sig]["prop_every"] = best_f
         if self.cache_path:

@@ -15,12 +15,14 @@ from . import _lib as S
 from .encode import EncodeConfig, default_log_tau
 
 
-def tiles_of(H, W):
-    return ((H + 15) // 16) * ((W + 15) // 16)
+def tiles_of(H, W, tile_w=16):
+    """Work items of an H x W image with tiles tile_w pixels wide, 256 / tile_w tall."""
+    th = 256 // tile_w
+    return ((H + th - 1) // th) * ((W + tile_w - 1) // tile_w)
 
 
 class BatchEncoder:
-    def __init__(self, targets, n_sites, cfg=None, device=None, grid=0, chunked=1):
+    def __init__(self, targets, n_sites, cfg=None, device=None, grid=0, chunked=1, tile_w=16):
         cfg = cfg or EncodeConfig()
         self.cfg = cfg
         self.device = device or targets[0].device
@@ -31,17 +33,15 @@ class BatchEncoder:
         self.n_sites = [int(n) for n in n_sites]
         B = len(targets)
         self.B = B
-        px0, site0, tile0 = [], [], []
-        P_tot = S_tot = T_tot = 0
+        px0, site0 = [], []
+        P_tot = S_tot = 0
         for (H, W), n in zip(self.shapes, self.n_sites):
             px0.append(P_tot)
             site0.append(S_tot)
-            tile0.append(T_tot)
             P_tot += H * W
             S_tot += n
-            T_tot += tiles_of(H, W)
-        self.px0, self.site0, self.tile0 = px0, site0, tile0
-        self.P_tot, self.S_tot, self.T_tot = P_tot, S_tot, T_tot
+        self.px0, self.site0 = px0, site0
+        self.P_tot, self.S_tot = P_tot, S_tot
         f32 = dict(dtype=torch.float32, device=dev)
         self.target = torch.empty(3 * P_tot, **f32)
         for b, t in enumerate(targets):
@@ -56,15 +56,8 @@ class BatchEncoder:
         self.lists = [torch.empty(K * P_tot, dtype=torch.int32, device=dev) for _ in range(2)]
         self.cur = 0
         self.states = torch.zeros(B * S.STEP_STATE_INT64, dtype=torch.int64, device=dev)
-        arr = (S.SadBatchImage * B)()
-        for b, ((H, W), n) in enumerate(zip(self.shapes, self.n_sites)):
-            s = float(cfg.score_scale) or float(torch.tensor(1.0, dtype=torch.float32) /
-                                                 torch.tensor(float(max(H, W)), dtype=torch.float32))
-            arr[b] = S.SadBatchImage(H, W, n, tile0[b], n, px0[b], site0[b], s, 0)
-        raw = bytes(arr)
-        self.images_dev = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
-        self.batch = S.SadBatch(B, K, T_tot, int(grid), int(chunked), 0, S_tot,
-                                self.images_dev.data_ptr())
+        self.tile_w = None
+        self._set_tiles(int(tile_w), int(grid), int(chunked))
         # per-image initialisation through the single-image entry points on views
         for b in range(B):
             img = self.img(b)
@@ -111,8 +104,32 @@ class BatchEncoder:
         k = S.STEP_STATE_INT64
         return self.states[k * b:k * (b + 1)]
 
+    def _set_tiles(self, tile_w, grid, chunked):
+        """Number the work items for tiles tile_w pixels wide (16: 16 x 16, 32: 32 x 8)
+        and upload the image descriptors."""
+        assert tile_w in (16, 32), tile_w
+        tile0, T_tot = [], 0
+        for H, W in self.shapes:
+            tile0.append(T_tot)
+            T_tot += tiles_of(H, W, tile_w)
+        self.tile0, self.T_tot, self.tile_w = tile0, T_tot, tile_w
+        arr = (S.SadBatchImage * self.B)()
+        for b, ((H, W), n) in enumerate(zip(self.shapes, self.n_sites)):
+            s = float(self.cfg.score_scale) or float(
+                torch.tensor(1.0, dtype=torch.float32) /
+                torch.tensor(float(max(H, W)), dtype=torch.float32))
+            arr[b] = S.SadBatchImage(H, W, n, tile0[b], n, self.px0[b], self.site0[b], s, 0)
+        self.images_dev = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).to(self.device)
+        self.batch = S.SadBatch(self.B, self.K, T_tot, grid, chunked, tile_w, self.S_tot,
+                                self.images_dev.data_ptr())
+        self.graph = None
+
     # ---- iteration ------------------------------------------------------------------
-    def set_launch(self, grid, chunked):
+    def set_launch(self, grid, chunked, tile_w=None):
+        """Persistent grid (0: one workgroup per tile), work assignment and, if given, the
+        tile shape of the work items."""
+        if tile_w is not None and int(tile_w) != self.tile_w:
+            self._set_tiles(int(tile_w), int(grid), int(chunked))
         self.batch.grid = int(grid)
         self.batch.chunked = int(chunked)
         self.graph = None

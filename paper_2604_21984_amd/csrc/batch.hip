@@ -45,7 +45,7 @@ struct BatchArgs {
 // One (image, tile) work item: propagate, render, loss gradient and backward of its 256
 // pixels, flushed into the image's site-major gradient.  The queue and the accumulators
 // share one LDS buffer (used in turn, as in the single-image training kernel).
-template <int K, bool kDet>
+template <int K, bool kDet, int TW>
 __device__ __forceinline__ void batch_item(const BatchArgs &ba, int item,
                                            const float4 *__restrict__ rec,
                                            const uint4 *__restrict__ lin,
@@ -72,8 +72,8 @@ __device__ __forceinline__ void batch_item(const BatchArgs &ba, int item,
              (uint32_t)__builtin_amdgcn_readfirstlane((int)im.px0);
     im.site0 = ((int64_t)__builtin_amdgcn_readfirstlane((int)(im.site0 >> 32)) << 32) |
                (uint32_t)__builtin_amdgcn_readfirstlane((int)im.site0);
-    const int tiles_x = (im.W + 15) / 16;
-    const TilePix px = tile_pixel(item - im.tile0, tiles_x);
+    const int tiles_x = (im.W + TW - 1) / TW;
+    const TilePix px = tile_pixel_w<TW>(item - im.tile0, tiles_x);
     const int64_t P = (int64_t)im.H * im.W;
     PropArgs pa;
     pa.H = im.H;
@@ -156,7 +156,7 @@ constexpr int batch_lds_words() {
 // range) or round robin.  The loop costs registers: for K <= 8 the kernel is held to 128
 // VGPRs (four waves per SIMD, no spill); larger K would spill under that cap and is left
 // uncapped.
-template <int K, bool kDet>
+template <int K, bool kDet, int TW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8 ? 4 : 1, 8))) void k_batch_train(
     BatchArgs ba, const float4 *__restrict__ rec, const uint4 *__restrict__ lin,
     uint4 *__restrict__ lout, const float *__restrict__ tgt, float *__restrict__ rendered,
@@ -178,15 +178,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8 ? 4 
         step = G;
     }
     for (int item = first; item < last; item += step) {
-        batch_item<K, kDet>(ba, item, rec, lin, lout, tgt, rendered, gimg, states, grad, lds, hkey,
-                            occ);
+        batch_item<K, kDet, TW>(ba, item, rec, lin, lout, tgt, rendered, gimg, states, grad, lds,
+                                hkey, occ);
         __syncthreads();  // the next item re-initialises the table
     }
 }
 
 // One block per item (no loop), items remapped so that each XCD takes a contiguous run
 // of them (neighbouring tiles of an image share that XCD's L2).
-template <int K, bool kDet>
+template <int K, bool kDet, int TW>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K == 16 ? 4 : 1, 8))) void k_batch_train_1(
     BatchArgs ba, const float4 *__restrict__ rec, const uint4 *__restrict__ lin,
     uint4 *__restrict__ lout, const float *__restrict__ tgt, float *__restrict__ rendered,
@@ -194,8 +194,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K == 16 ? 4
     __shared__ __align__(16) uint32_t lds[batch_lds_words<K>()];
     __shared__ uint32_t hkey[kHashSlots];
     __shared__ uint32_t occ[kHashSlots + 1];
-    batch_item<K, kDet>(ba, xcd_tile(blockIdx.x, gridDim.x), rec, lin, lout, tgt, rendered, gimg, states, grad, lds,
-                        hkey, occ);
+    batch_item<K, kDet, TW>(ba, xcd_tile(blockIdx.x, gridDim.x), rec, lin, lout, tgt, rendered,
+                            gimg, states, grad, lds, hkey, occ);
 }
 
 __global__ __launch_bounds__(64) void k_batch_loss_fold(sad_step_state *__restrict__ states) {
@@ -279,7 +279,11 @@ extern "C" sad_status sad_batch_train_step(const sad_batch *batch, const sad_tra
                 "training pass: prop_every must be in [0, 1024]");
     SAD_REQUIRE((cfg->flags & ~SAD_TRAIN_DETERMINISTIC) == 0, SAD_ERR_INVALID_ARGUMENT,
                 "sad_batch_train_step: unknown flags 0x%x", cfg->flags);
+    SAD_REQUIRE(batch->tile_w == 0 || batch->tile_w == 16 || batch->tile_w == 32,
+                SAD_ERR_UNSUPPORTED, "sad_batch_train_step: tile width %d (16 or 32)",
+                batch->tile_w);
     const bool det = (cfg->flags & SAD_TRAIN_DETERMINISTIC) != 0;
+    const bool wide = batch->tile_w == 32;
     hipStream_t st = as_stream(stream);
     BatchArgs ba;
     ba.n_images = batch->n_images;
@@ -295,19 +299,27 @@ extern "C" sad_status sad_batch_train_step(const sad_batch *batch, const sad_tra
     const float4 *r4 = reinterpret_cast<const float4 *>(rec);
     const uint4 *li = reinterpret_cast<const uint4 *>(topk_in);
     uint4 *lo = reinterpret_cast<uint4 *>(topk_out);
-#define SAD_BATCH_LAUNCH(KK, DET)                                                              \
+#define SAD_BATCH_LAUNCH(KK, DET, TW)                                                          \
     if (batch->grid > 0 && grid < batch->n_items)                                              \
-        hipLaunchKernelGGL((k_batch_train<KK, DET>), dim3(grid), dim3(256), 0, st, ba, r4, li,   \
-                           lo, target, rendered, grad_img, states, grad_sites);               \
+        hipLaunchKernelGGL((k_batch_train<KK, DET, TW>), dim3(grid), dim3(256), 0, st, ba, r4,   \
+                           li, lo, target, rendered, grad_img, states, grad_sites);           \
     else                                                                                       \
-        hipLaunchKernelGGL((k_batch_train_1<KK, DET>), dim3(ba.n_items), dim3(256), 0, st, ba,   \
-                           r4, li, lo, target, rendered, grad_img, states, grad_sites);
+        hipLaunchKernelGGL((k_batch_train_1<KK, DET, TW>), dim3(ba.n_items), dim3(256), 0, st,   \
+                           ba, r4, li, lo, target, rendered, grad_img, states, grad_sites);
 #define SAD_BATCH_CASE(KK)                                                                     \
     case KK:                                                                                   \
         if (det) {                                                                             \
-            SAD_BATCH_LAUNCH(KK, true)                                                         \
+            if (wide) {                                                                        \
+                SAD_BATCH_LAUNCH(KK, true, 32)                                                 \
+            } else {                                                                           \
+                SAD_BATCH_LAUNCH(KK, true, 16)                                                 \
+            }                                                                                  \
         } else {                                                                               \
-            SAD_BATCH_LAUNCH(KK, false)                                                        \
+            if (wide) {                                                                        \
+                SAD_BATCH_LAUNCH(KK, false, 32)                                                \
+            } else {                                                                           \
+                SAD_BATCH_LAUNCH(KK, false, 16)                                                \
+            }                                                                                  \
         }                                                                                      \
         break;
     switch (batch->K) {

@@ -32,6 +32,11 @@ inline GridArgs grid_args(const sad_image *img, int Hg, int Wg) {
 // di, dj in {-1, 0, 1}, that lie in the grid (itself included), scores them exactly at
 // its centre and writes the best four distinct IDs by (score descending, ID ascending)
 // into plane 0 of out.  Planes 1.. of out are not touched.
+// The cell's own four entries are scored exactly first; every other candidate is
+// screened as in the propagation pass (an ID already kept is a repeat; otherwise the
+// score is estimated with the hardware square root and dropped when it lies below the
+// fourth key by more than the estimate's error bound), and only survivors are scored
+// exactly and inserted, so the result is the exact best four of the candidate set.
 __global__ __launch_bounds__(256) void k_jfa_flood(GridArgs g, int step,
                                                    const float4 *__restrict__ rec,
                                                    const uint4 *__restrict__ lin,
@@ -42,20 +47,47 @@ __global__ __launch_bounds__(256) void k_jfa_flood(GridArgs g, int step,
     const float X = grid_point(px.j, g.W, g.Wg), Y = grid_point(px.i, g.H, g.Hg);
     const uint32_t ns = (uint32_t)g.n_slots;
     uint64_t keys[4] = {0ull, 0ull, 0ull, 0ull};
+    {
+        const uint4 v = lin[(int64_t)px.i * g.Wg + px.j];
+        const uint32_t id[4] = {v.x, v.y, v.z, v.w};
+        uint64_t nk[4];
+        exact_keys<4>(rec, ns, X, Y, id, nk);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) insert_key<4>(keys, nk[c]);
+    }
 #pragma unroll 1
-    for (int di = -1; di <= 1; ++di) {
-        const int ii = px.i + di * step;
-        if (ii < 0 || ii >= g.Hg) continue;
+    for (int nb = 0; nb < 9; ++nb) {
+        if (nb == 4) continue;  // the cell itself, taken above
+        const int ii = px.i + (nb / 3 - 1) * step, jj = px.j + (nb % 3 - 1) * step;
+        if (ii < 0 || ii >= g.Hg || jj < 0 || jj >= g.Wg) continue;
+        const uint4 v = lin[(int64_t)ii * g.Wg + jj];
+        const uint32_t id[4] = {v.x, v.y, v.z, v.w};
+        bool ok[4];
+        uint32_t idc[4];
 #pragma unroll
-        for (int dj = -1; dj <= 1; ++dj) {
-            const int jj = px.j + dj * step;
-            if (jj < 0 || jj >= g.Wg) continue;
-            const uint4 v = lin[(int64_t)ii * g.Wg + jj];
-            const uint32_t id[4] = {v.x, v.y, v.z, v.w};
-            uint64_t nk[4];
-            exact_keys<4>(rec, ns, X, Y, id, nk);
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t nid = ~id[c];
+            bool kept = false;
 #pragma unroll
-            for (int c = 0; c < 4; ++c) insert_key<4>(keys, nk[c]);
+            for (int k = 0; k < 4; ++k) kept |= ((uint32_t)keys[k] == nid);
+            ok[c] = (id[c] < ns) & !kept;
+            idc[c] = ok[c] ? id[c] : 0u;
+        }
+        float4 q0[4], q1[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            q0[c] = rec[4 * (size_t)idc[c]];
+            q1[c] = rec[4 * (size_t)idc[c] + 1];
+        }
+        const float kth = keys[3] ? key_score(keys[3]) : -INFINITY;
+        const bool open = keys[3] == 0ull;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const float na = __builtin_amdgcn_sqrtf(quad(q0[c], q1[c], X, Y));
+            const float la = q1[c].y * (q1[c].z - na);
+            const float bound = fmaf(q1[c].y, fabsf(q1[c].z) + na, fabsf(la)) * 0x1p-19f;
+            if (ok[c] & (q1[c].w != 0.0f) & (open | (la + bound >= kth)))
+                insert_key<4>(keys, make_key(score(q0[c], q1[c], X, Y), id[c]));
         }
     }
     lout[(int64_t)px.i * g.Wg + px.j] =

@@ -175,6 +175,21 @@ __device__ __forceinline__ TilePix tile_pixel(int tile, int tiles_x) {
     return p;
 }
 
+// The same for a tile TW pixels wide and 256 / TW tall, still four 8x8 wave64 blocks
+// (TW = 16: 2 x 2 blocks, tile_pixel's mapping; TW = 32: 4 x 1 blocks).
+template <int TW>
+__device__ __forceinline__ TilePix tile_pixel_w(int tile, int tiles_x) {
+    static_assert(TW == 16 || TW == 32, "tiles are 16 x 16 or 32 x 8");
+    constexpr int TH = 256 / TW, WX = TW / 8;
+    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    const int t = threadIdx.x;
+    const int w = t >> 6, l = t & 63;
+    TilePix p;
+    p.i = ty * TH + (w / WX) * 8 + (l >> 3);
+    p.j = tx * TW + (w % WX) * 8 + (l & 7);
+    return p;
+}
+
 __device__ __forceinline__ void atomic_add_f32(float *p, float v) { unsafeAtomicAdd(p, v); }
 
 }  // namespace sad

@@ -54,13 +54,17 @@ def test_batch_equals_per_image_encoders(mods):
     assert [int(x) for x in be.state(2)[:2].tolist()] == [6, 6]
 
 
-@pytest.mark.parametrize("grid,chunked", [(0, 0), (7, 1), (5, 0), (3, 1)])
-def test_batch_launch_shapes_agree(mods, grid, chunked):
+@pytest.mark.parametrize("grid,chunked,tile_w", [(0, 0, 16), (7, 1, 16), (5, 0, 16), (3, 1, 16),
+                                                 (0, 0, 32), (7, 1, 32), (5, 0, 32)])
+def test_batch_launch_shapes_agree(mods, grid, chunked, tile_w):
+    """Every launch form and tile shape gives the same lists (bit for bit) and the same
+    parameters up to the order of the float sums."""
     S, B, E, T = mods
     cfg = E.EncodeConfig(K=8, n_inject=4, seed=5)
     tg = _targets()
     ref = B.BatchEncoder(tg, [n for _, _, n in SHAPES], cfg, grid=0, chunked=0)
-    alt = B.BatchEncoder(tg, [n for _, _, n in SHAPES], cfg, grid=grid, chunked=chunked)
+    alt = B.BatchEncoder(tg, [n for _, _, n in SHAPES], cfg, grid=grid, chunked=chunked,
+                         tile_w=tile_w)
     ref.step()
     alt.step()
     torch.cuda.synchronize()
@@ -76,7 +80,8 @@ def test_batch_graph_replay_and_autotune(mods):
     graphed = B.BatchEncoder(tg, [n for _, _, n in SHAPES], cfg)
     before = graphed.sites.clone()
     grid, chunked, timings = T.Autotuner().tune(graphed, pairs=1, reps=1)
-    assert len(timings) >= 1
+    assert len(timings) >= 2 and graphed.tile_w in (16, 32)
+    assert any(k.endswith("/32") for k in timings) and any(k.endswith("/16") for k in timings)
     assert torch.equal(graphed.sites, before)          # tuning leaves the encode untouched
     graphed.capture()
     for _ in range(3):
@@ -98,7 +103,8 @@ def test_deterministic_batch_equals_per_image_bitwise(mods):
     ns = [n for _, _, n in SHAPES]
     singles = [E.Encoder(t, n, cfg) for t, n in zip(tg, ns)]
     runs = [B.BatchEncoder(tg, ns, cfg, grid=0, chunked=0),
-            B.BatchEncoder(tg, ns, cfg, grid=5, chunked=1)]
+            B.BatchEncoder(tg, ns, cfg, grid=5, chunked=1),
+            B.BatchEncoder(tg, ns, cfg, grid=0, chunked=0, tile_w=32)]
     for _ in range(6):
         for enc in singles:
             enc.step()
@@ -110,4 +116,5 @@ def test_deterministic_batch_equals_per_image_bitwise(mods):
             assert torch.equal(be.view_sites(b), enc.sites), b
             assert torch.equal(be.view_list(be.cur, b), enc.topk), b
     assert torch.equal(runs[0].sites, runs[1].sites)
+    assert torch.equal(runs[0].sites, runs[2].sites)
     assert (runs[0].grad == 0).all()

@@ -226,9 +226,10 @@ BATCH_SHAPES = [(64, 80, 300), (96, 50, 250), (130, 77, 520), (33, 47, 60), (16,
                 (70, 200, 700)]
 
 
-@pytest.mark.parametrize("grid,chunked,det", [(0, 0, False), (5, 1, False), (0, 0, True),
-                                              (7, 0, True)])
-def test_batch_step_matches_oracle_per_image(S, grid, chunked, det):
+@pytest.mark.parametrize("grid,chunked,det,tile_w", [(0, 0, False, 16), (5, 1, False, 16),
+                                                     (0, 0, True, 16), (7, 0, True, 16),
+                                                     (0, 0, False, 32), (5, 1, True, 32)])
+def test_batch_step_matches_oracle_per_image(S, grid, chunked, det, tile_w):
     """sad_batch_train_step, image by image, against the oracle: every image starts from
     its own oracle field at its own pass index; lists, loss and gradient per image."""
     from paper_2604_21984_amd import batch as B
@@ -238,7 +239,7 @@ def test_batch_step_matches_oracle_per_image(S, grid, chunked, det):
                for i, (H, W, _) in enumerate(BATCH_SHAPES)]
     cfg = E.EncodeConfig(K=8, n_inject=J, seed=6, deterministic=det)
     be = B.BatchEncoder([_t(x) for x in targets], [n for _, _, n in BATCH_SHAPES], cfg,
-                        grid=grid, chunked=chunked)
+                        grid=grid, chunked=chunked, tile_w=tile_w)
     be.adam = S.adam_params([0.0] * 10, cfg.beta1, cfg.beta2, cfg.eps)
     be.train_cfg = S.train_config(J, be.train_cfg.seed, be.adam, deterministic=det)
     seed = be.train_cfg.seed
@@ -271,5 +272,5 @@ def test_batch_step_matches_oracle_per_image(S, grid, chunked, det):
         if det:  # the deterministic mode's per-term rounding at this image's own P
             ab = ab + _det_quantum(H, W, rlists, ab.shape[1])[None, :] / 1e-5
         w, plain, rep = grad_check(m / b1, rgrad, ab,
-                                   f"batch grid={grid} chunked={chunked} det={det} image {b}")
+                                   f"batch grid={grid} chunked={chunked} det={det} tile={tile_w} image {b}")
         assert w <= 1.0, f"image {b}: gradient mismatch ratio {w}\n{rep}"
