@@ -28,9 +28,9 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources they were taken with: HBM bytes per launch from FETCH_SIZE + WRITE_SIZE
 # scaled by a copy kernel's readings, and the utilisation counters.
 PROFILED = {
-    "f29c90e070c620f1": {"traffic_bytes": 44995762, "valu_insts": 26340834,
-                         "counters": {"VALUBusy_pct": 62.5, "LDSBankConflict_pct": 16.8,
-                                      "OccupancyPercent": 48.8, "MemUnitStalled_pct": 0.07}},
+    "90f33b140f310afe": {"traffic_bytes": 45002203, "valu_insts": 25141279,
+                         "counters": {"VALUBusy_pct": 60.3, "LDSBankConflict_pct": 16.9,
+                                      "OccupancyPercent": 47.7, "MemUnitStalled_pct": 0.08}},
 }
 # Vector-ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s (one
 # non-packed float32 operation per lane; packed FMA makes the 157.3 TFLOP/s headline).
@@ -401,6 +401,7 @@ def batched_vs_loop(steps, seed=0):
 
     be = BatchEncoder(tg, ns, cfg)
     grid, chunked, timings = Autotuner().tune(be, pairs=2, reps=2, schedules=(1, 2, 4))
+    tile_w = be.tile_w
     f_best = timings.get("prop_every_best", 1)
     start = be.snapshot()
     be.set_prop_every(1)
@@ -428,6 +429,29 @@ def batched_vs_loop(steps, seed=0):
     ms_l = timed(loop)
     ps_l = [e.psnr() for e in encs]
     dps = max(abs(x - y) for x, y in zip(ps_b, ps_l))
+    del encs
+    # the same comparison in the deterministic mode (integer gradient sums): the batched
+    # step and the per-image encoders then agree bit for bit, image by image
+    dcfg = EncodeConfig(K=K, n_inject=J, seed=seed, deterministic=True)
+    bd = BatchEncoder(tg, ns, dcfg)
+    bd.set_launch(grid, chunked, tile_w)
+    bd.set_prop_every(1)
+    bd.capture()
+    ms_bd = timed(lambda: bd.replay(pairs))
+    ps_bd = [bd.psnr(i) for i in range(len(shapes))]
+    del bd
+    encs = [Encoder(t, n, dcfg) for t, n in zip(tg, ns)]
+    for e in encs:
+        e.capture()
+    ms_ld = timed(loop)
+    ps_ld = [e.psnr() for e in encs]
+    del encs
+    det = {"batched_mpix_s": round(P * 2 * pairs / (ms_bd * 1e3), 1),
+           "loop_mpix_s": round(P * 2 * pairs / (ms_ld * 1e3), 1),
+           "speedup": round(ms_ld / ms_bd, 3),
+           "mean_psnr_db": round(sum(ps_bd) / len(ps_bd), 3),
+           "max_abs_dpsnr_db": round(max(abs(x - y) for x, y in zip(ps_bd, ps_ld)), 6),
+           "images_within_0.05_db": sum(abs(x - y) <= 0.05 for x, y in zip(ps_bd, ps_ld))}
     return {"images": len(shapes), "pixels": P, "sites": sum(ns), "iterations": 2 * pairs,
             "batched_mpix_s": round(P * 2 * pairs / (ms_b * 1e3), 1),
             "loop_mpix_s": round(P * 2 * pairs / (ms_l * 1e3), 1),
@@ -437,8 +461,10 @@ def batched_vs_loop(steps, seed=0):
             "mean_dpsnr_db": round(sum(x - y for x, y in zip(ps_b, ps_l)) / len(ps_b), 4),
             "max_abs_dpsnr_db": round(dps, 4),
             "psnr_note": "the float atomics of the gradient sums add in a different order on "
-                         "every run, so long encodes of one image drift apart; compare means",
-            "launch": {"grid": grid, "chunked": chunked, "prop_every": 1},
+                         "every run, so long encodes of one image drift apart; compare means, "
+                         "or the deterministic mode image by image",
+            "deterministic": det,
+            "launch": {"grid": grid, "chunked": chunked, "tile_w": tile_w, "prop_every": 1},
             "tuned_schedule": tuned, "autotune": timings}
 
 
@@ -451,27 +477,33 @@ def serving(rates, seconds, seed=0):
     import synth
     from paper_2604_21984_amd import _lib as S
     from paper_2604_21984_amd import serve as V
+    from paper_2604_21984_amd.encode import EncodeConfig, Encoder
     shapes = synth.serve_shapes(seed)
-    sets = []
+    # every set is a 200-iteration encode of its own target (the warm-up encode of the
+    # protocol); targets tile one of four 512 x 512 images from the 768x512 generator to
+    # the set's size (generating 158 Mpx of noise and polygons would take minutes of CPU)
+    tiles = [synth.image_encode(800 + i, 512, 512) for i in range(4)]
+    sets, enc_ms = [], 0.0
     for sid, (H, W, n) in enumerate(shapes):
-        sites = synth.random_sites(500 + sid, H, W, n, anisotropic=True, log_tau=4.0,
-                                   r_range=(1.0, 8.0))
-        img = S.image(H, W, K, n, n)
-        sd = torch.from_numpy(sites).cuda()
-        rec = torch.empty(n * S.REC_FLOATS, dtype=torch.float32, device="cuda")
-        S.prepare_sites(img, sd, rec)
-        a = torch.empty((K // 4, H, W, 4), dtype=torch.int32, device="cuda")
-        b = torch.empty_like(a)
-        S.seed_topk(img, rec, a, b)
-        for t in range(16):
-            S.propagate_topk(img, rec, a, b, S.jump_step(t, H, W), J, sid, t)
-            a, b = b, a
-        del b, sd
-        sets.append(V.ResidentSet(sid, H, W, K, n, rec, a))
+        t = tiles[sid % 4]
+        target = np.ascontiguousarray(np.tile(t, (1, -(-H // 512), -(-W // 512)))[:, :H, :W])
+        enc = Encoder(torch.from_numpy(target).cuda(), n, EncodeConfig(K=K, n_inject=J, seed=sid))
+        enc.capture(5)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        enc.replay(20)
+        e1.record()
+        torch.cuda.synchronize()
+        enc_ms += e0.elapsed_time(e1)
+        sets.append(V.ResidentSet.from_encoder(sid, enc))
+        del enc, target
+    torch.cuda.empty_cache()
     torch.cuda.synchronize()
     resident = sum(rs.nbytes() for rs in sets)
     out = {"sets": len(sets), "resident_pixels": sum(H * W for H, W, _ in shapes),
-           "resident_bytes": resident, "seconds_per_rate": seconds, "by_rate": {}}
+           "resident_bytes": resident, "seconds_per_rate": seconds,
+           "warmup_encodes": {"iterations": 200, "total_ms": round(enc_ms, 1)},
+           "by_rate": {}}
     # untimed warm-up: one render and one query per set (first launches of each kernel
     # and the allocator's first blocks are not part of any rate's latencies)
     warm = []
@@ -532,14 +564,20 @@ def serving(rates, seconds, seed=0):
     # with every request arriving at once (capacity)
     if not specs:
         return out
-    burst = [0.0] * len(times)
+    # the first 10 s of the highest rate's stream (all of it for shorter runs)
+    keep = sum(1 for t in times if t < 10.0)
+    specs, times = specs[:keep], times[:keep]
+    loop_srv = served(specs, times)
     loop = plain_loop(sets, make(specs), times)
     print("bench: plain loop done", file=sys.stderr, flush=True)
+    burst = [0.0] * len(times)
     cap_srv = served(specs, burst)
     cap_loop = plain_loop(sets, make(specs), burst)
     out["plain_loop"] = {
         "rate": rates[-1], "requests": len(specs), "open_loop": rounded(loop),
+        "open_loop_server": rounded(loop_srv),
         "burst": {"server_rps": round(cap_srv["throughput_rps"], 1),
+                  "server_requests_per_launch": round(cap_srv.get("mean_requests_per_launch", 0.0), 2),
                   "loop_rps": round(cap_loop["throughput_rps"], 1),
                   "speedup": round(cap_srv["throughput_rps"] / cap_loop["throughput_rps"], 3),
                   "server_p99_ms": round(cap_srv["p99_ms"], 3),
@@ -571,6 +609,26 @@ def paper_context(result):
         "render_only_2048x2048_ms": {
             "paper": 0.132, "paper_hw": "RTX 5090",
             "here": ms(get("large_image", "k8_n32768", "render_us"))},
+        "render_call_ms": {
+            "paper": {"512x512": 1.100, "1024x1024": 4.614, "2048x2048": 26.539},
+            "paper_hw": "RTX 5090 (JFA seeding + 16 propagation passes + render, 1 bpp)",
+            "here": {k: get("render_call", "by_side", k, "full_render_call_ms")
+                     for k in ("512x512", "1024x1024", "2048x2048")}},
+        "update_16_passes_ms": {
+            "paper": {"512x512": 0.728, "1024x1024": 2.568, "2048x2048": 16.009},
+            "paper_hw": "RTX 5090",
+            "here": {k: get("render_call", "by_side", k, "update_16_passes_ms")
+                     for k in ("512x512", "1024x1024", "2048x2048")}},
+        "update_1_pass_ms": {
+            "paper": {"512x512": 0.053, "1024x1024": 0.168, "2048x2048": 1.006},
+            "paper_hw": "RTX 5090",
+            "here": {k: get("render_call", "by_side", k, "update_1_pass_ms")
+                     for k in ("512x512", "1024x1024", "2048x2048")}},
+        "render_only_ms": {
+            "paper": {"512x512": 0.015, "1024x1024": 0.034, "2048x2048": 0.132},
+            "paper_hw": "RTX 5090 (cached top-K lists)",
+            "here": {k: get("render_call", "by_side", k, "render_only_ms")
+                     for k in ("512x512", "1024x1024", "2048x2048")}},
         "encode_768x512_50k_sites_4000_iterations_s": {
             "paper": 2.2, "paper_hw": "not stated (Kodak, densify and prune included)",
             "here": (None if get("whole_encode", "n50000_budget", "total_ms") is None else
@@ -644,6 +702,76 @@ def topk_quality(trials):
                 qt[str(n)] = {str(t): {"exact_match": round(v[0], 4), "recall": round(v[1], 4)}
                               for t, v in acc.items()}
             out[key][f"{side}x{side}"] = qt
+    return out
+
+
+def packed_decode(reps, seed=6):
+    """Decoding from packed 16-byte records (App. B.2) against the float32 derived records,
+    at 2048^2 with 1 bpp (32 768 sites) and at 4096^2 with 0.05 sites/px (the largest
+    resident set of the serving workload): record bytes, bits per pixel, a full render
+    (in-kernel decode, sad_render_packed; and decode to records + render), 2^20 random
+    point queries (sad_query_packed), and the colour difference the quantisation makes."""
+    import torch
+
+    import synth
+    from paper_2604_21984_amd import _lib as S
+    out = {}
+    for name, side, n in (("2048x2048_1bpp", 2048, 2048 * 2048 // 128),
+                          ("4096x4096_0.05", 4096, int(round(0.05 * 4096 * 4096)))):
+        sites = synth.perturb_sites(seed + 1, synth.random_sites(seed, side, side, n, log_tau=5.5,
+                                                                 r=1.0), n, side, side)
+        img = S.image(side, side, K, n, n)
+        sd = torch.from_numpy(sites).cuda()
+        rec = torch.empty(n * S.REC_FLOATS, dtype=torch.float32, device="cuda")
+        S.prepare_sites(img, sd, rec)
+        q = torch.empty(S.NQPARAM, dtype=torch.float32, device="cuda")
+        pk = torch.empty((n, 4), dtype=torch.int32, device="cuda")
+        S.pack_qparams(img, sd, q)
+        S.pack_sites(img, sd, q, pk)
+        rec_p = torch.empty_like(rec)
+        S.prepare_packed(img, pk, q, rec_p)
+        a = torch.empty((K // 4, side, side, 4), dtype=torch.int32, device="cuda")
+        b = torch.empty_like(a)
+        scratch = torch.empty(side * side, dtype=torch.int64, device="cuda")
+        S.refresh(img, side, side, rec_p, a, b, scratch, 16, J, seed, jfa=True)
+        del b, scratch
+        o1 = torch.empty((3, side, side), dtype=torch.float32, device="cuda")
+        o2 = torch.empty_like(o1)
+        M = 1 << 20
+        g = torch.Generator(device="cuda").manual_seed(seed)
+        xy = torch.rand(M, 2, device="cuda", generator=g) * (side - 1)
+        c1 = torch.empty(M, 3, device="cuda")
+        c2 = torch.empty_like(c1)
+
+        def tm(fn):
+            for _ in range(3):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return round(e0.elapsed_time(e1) * 1e3 / reps, 1)
+
+        row = {"n_sites": n, "bpp_packed": round(S.bpp(n, side, side), 4),
+               "record_bytes_float": n * 64, "record_bytes_packed": n * 16 + 40,
+               "list_bytes": K * 4 * side * side,
+               "render_float_us": tm(lambda: S.render_fwd(img, rec_p, a, o1)),
+               "render_packed_us": tm(lambda: S.render_packed(img, pk, q, a, o2)),
+               "decode_then_render_us": tm(lambda: (S.prepare_packed(img, pk, q, rec_p),
+                                                    S.render_fwd(img, rec_p, a, o1))),
+               "query_1m_float_us": tm(lambda: S.query_points(img, rec_p, a, xy, c1)),
+               "query_1m_packed_us": tm(lambda: S.query_packed(img, pk, q, a, xy, c2))}
+        S.render_fwd(img, rec, a, o2)     # the unquantised sites through the same lists
+        torch.cuda.synchronize()
+        row["max_abs_colour_change_from_packing"] = round(float((o1 - o2).abs().max()), 5)
+        row["psnr_packed_vs_float_db"] = round(float(
+            10 * torch.log10(1.0 / torch.mean((o1.clamp(0, 1) - o2.clamp(0, 1)) ** 2))), 2)
+        out[name] = row
+        del sd, rec, rec_p, pk, a, o1, o2, xy, c1, c2
+        torch.cuda.empty_cache()
     return out
 
 
@@ -786,7 +914,7 @@ def main():
                     help="iterations per 2048x2048 workload of the large-image timing (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=1000,
                     help="iterations of the 64-image batched vs per-image comparison (0: skip)")
-    ap.add_argument("--serve-seconds", type=float, default=3.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="seconds of Poisson arrivals per rate (0: skip serving)")
     ap.add_argument("--quality-trials", type=int, default=4,
                     help="trials of the top-K convergence measurement (0: skip)")
@@ -941,6 +1069,31 @@ def main():
         "wall_s": round(wall, 4),
     }
 
+    def headline_recall(enc, trials=4):
+        """The headline encode's own list field (after the timed iterations) against the
+        exact top-K at random pixels (Sec. 6.5 protocol on this workload): 256 and 4096
+        pixels, `trials` samples each."""
+        import numpy as np
+
+        from paper_2604_21984_amd import quality as Q
+        out = {}
+        lists = enc.topk
+        for npix in (256, 4096):
+            em, rc = [], []
+            for tr in range(trials):
+                pix = np.sort(np.random.default_rng(900 + tr).choice(H * W, npix, replace=False))
+                pd = torch.from_numpy(pix.astype(np.int64)).to(dev)
+                ex = torch.empty((npix, K), dtype=torch.int32, device=dev)
+                S.exact_topk(enc.img, enc.rec, pd, ex)
+                got = lists.view(K // 4, H * W, 4)[:, pd].permute(1, 0, 2).reshape(npix, K)
+                a, b = Q.set_agreement(got.cpu().numpy().view(np.uint32),
+                                       ex.cpu().numpy().view(np.uint32))
+                em.append(a)
+                rc.append(b)
+            out[str(npix)] = {"exact_match": round(sum(em) / trials, 4),
+                              "recall": round(sum(rc) / trials, 4)}
+        return out
+
     def extra(name, fn, *a):
         try:
             result[name] = fn(*a)
@@ -948,6 +1101,7 @@ def main():
             result[name] = {"error": f"{type(e).__name__}: {e}"}
         print(f"bench: {name} done", file=sys.stderr, flush=True)
 
+    extra("headline_topk_recall", headline_recall, enc)
     if args.autograd_steps > 0:
         extra("autograd", autograd_path, enc, args.autograd_steps)
         extra("autograd_fused", autograd_path, enc, args.autograd_steps, True)
@@ -967,6 +1121,7 @@ def main():
         extra("topk_quality", topk_quality, args.quality_trials)
     if args.render_call_reps > 0:
         extra("render_call", render_call, args.render_call_reps)
+        extra("packed_decode", packed_decode, args.render_call_reps)
 
     if args.cpu_budget > 0:
         sites_np, lists_np = cpu_baseline_inputs(target_np)

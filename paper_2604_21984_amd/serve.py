@@ -2,7 +2,10 @@
 cached top-K lists is the fast path).
 
 * Resident sets: encoded site sets (derived records + list field) kept on the device.
-* Requests: point queries (M points of one set) and full renders (one set).
+* Requests: point queries (M points of one set), full renders (one set) and renders at a
+  new resolution (Ho x Wo points over one set's image: the set's lists belong to its own
+  pixel grid, so the request rebuilds lists on the new grid with a full refresh -- JFA
+  prepass and 16 passes, Sec. 6.6 -- and renders from them).
 * Admission by memory: a request is admitted when the device bytes it needs (its
   inputs and outputs) fit in what the budget has left; bytes return when it completes.
   A request that could never fit is rejected.
@@ -25,7 +28,8 @@ import threading
 import time
 from dataclasses import dataclass
 
-QUERY, RENDER = "query", "render"
+QUERY, RENDER, RESCALE = "query", "render", "rescale"
+RESCALE_PASSES = 16
 
 
 @dataclass
@@ -43,6 +47,8 @@ class Request:
     error: str = None
     nbytes: int = 0
     ready: object = None         # backend marker: the request's inputs are written
+    Ho: int = 0                  # output grid of a RESCALE request
+    Wo: int = 0
 
     @property
     def latency(self):
@@ -72,9 +78,12 @@ class ResidentSet:
 
 
 def request_bytes(req, rset):
-    """Device bytes a request holds while admitted: inputs and outputs."""
+    """Device bytes a request holds while admitted: inputs, outputs and, for a render at a
+    new resolution, the two list fields and the seed scratch of its refresh."""
     if req.kind == QUERY:
         return req.M * (8 + 12)
+    if req.kind == RESCALE:
+        return req.Ho * req.Wo * (12 + 2 * 4 * rset.K + 8)
     return 12 * rset.H * rset.W
 
 
@@ -172,6 +181,25 @@ class GpuBackend:
             ev.record(st)
         return {"event": ev, "reqs": [req], "outs": [out], "keep": ()}
 
+    def launch_rescale(self, req, rset, seed=0):
+        """A render of rset at req.Ho x req.Wo: refresh on that grid (JFA prepass and
+        RESCALE_PASSES passes, J = 4), then render from the refreshed lists."""
+        torch, S = self.torch, self.S
+        st = self._stream()
+        self._wait_inputs(st, [req])
+        Ho, Wo, K = req.Ho, req.Wo, rset.K
+        with torch.cuda.stream(st):
+            img = self._image(rset)
+            a = torch.empty((K // 4, Ho, Wo, 4), dtype=torch.int32, device=self.device)
+            b = torch.empty_like(a)
+            scratch = torch.empty(Ho * Wo, dtype=torch.int64, device=self.device)
+            S.refresh(img, Ho, Wo, rset.rec, a, b, scratch, RESCALE_PASSES, 4, seed, jfa=True)
+            out = torch.empty((3, Ho, Wo), dtype=torch.float32, device=self.device)
+            S.render_grid(img, Ho, Wo, rset.rec, a, Ho, Wo, out)
+            ev = torch.cuda.Event()
+            ev.record(st)
+        return {"event": ev, "reqs": [req], "outs": [out], "keep": (a, b, scratch)}
+
     def done(self, h):
         return h["event"].query()
 
@@ -256,6 +284,11 @@ class Server:
                 self._start([head], lambda rs=self.sets[head.set_id], r=head:
                              self.backend.launch_render(r, rs))
                 continue
+            if head.kind == RESCALE:
+                self.admitted.popleft()
+                self._start([head], lambda rs=self.sets[head.set_id], r=head:
+                             self.backend.launch_rescale(r, rs))
+                continue
             # gather admitted point queries with the head's K, up to the point budget
             K = self.sets[head.set_id].K
             batch, keep, total = [], collections.deque(), 0
@@ -332,6 +365,7 @@ class Server:
         t1 = max(r.t_done for r in ok)
         pts = sum(r.M for r in ok if r.kind == QUERY)
         px = sum(self.sets[r.set_id].H * self.sets[r.set_id].W for r in ok if r.kind == RENDER)
+        px += sum(r.Ho * r.Wo for r in ok if r.kind == RESCALE)
 
         def pct(q):
             return lat[min(len(lat) - 1, max(0, math.ceil(q * len(lat)) - 1))]

@@ -138,3 +138,48 @@ def test_inputs_written_on_the_submitting_stream(sets):
         assert r.error is None, r.error
         ref = _alone(S, rsets[r.set_id], r.xy)
         assert torch.equal(r.result, ref), r.rid
+
+
+def test_renders_at_a_new_resolution(sets):
+    """RESCALE requests (a render at another resolution: full refresh on the new grid,
+    then the render) mixed with queries: each output equals sad_refresh + sad_render_grid
+    called directly, bit for bit, and the refreshed lists of a small grid equal the
+    oracle's refresh."""
+    from paper_2604_21984_amd import _lib as S
+    from paper_2604_21984_amd import serve as V
+    rsets, encs = sets
+    srv = V.Server(V.GpuBackend(), rsets, mem_budget=64 << 20, max_inflight=4)
+    sizes = [(96, 128, 0), (24, 32, 0), (80, 60, 1), (17, 41, 2)]
+    reqs = [V.Request(i, sid, V.RESCALE, Ho=Ho, Wo=Wo) for i, (Ho, Wo, sid) in enumerate(sizes)]
+    rng = np.random.default_rng(8)
+    for i in range(3):
+        rs = rsets[i]
+        xy = torch.from_numpy(np.stack([rng.uniform(0, rs.W - 1, 300),
+                                        rng.uniform(0, rs.H - 1, 300)], 1).astype(np.float32)).to(DEV)
+        reqs.append(V.Request(10 + i, i, V.QUERY, xy=xy, M=300))
+    for r in reqs:
+        srv.submit(r)
+    srv.drain(timeout=60.0)
+    torch.cuda.synchronize()
+    assert all(r.error is None for r in reqs), [r.error for r in reqs]
+    for r in reqs:
+        rs = rsets[r.set_id]
+        img = S.image(rs.H, rs.W, rs.K, rs.n_slots, rs.n_slots, rs.score_scale)
+        if r.kind == V.QUERY:
+            assert torch.equal(r.result, _alone(S, rs, r.xy))
+            continue
+        a = torch.empty((rs.K // 4, r.Ho, r.Wo, 4), dtype=torch.int32, device=DEV)
+        b = torch.empty_like(a)
+        sc = torch.empty(r.Ho * r.Wo, dtype=torch.int64, device=DEV)
+        S.refresh(img, r.Ho, r.Wo, rs.rec, a, b, sc, V.RESCALE_PASSES, 4, 0, jfa=True)
+        out = torch.empty((3, r.Ho, r.Wo), dtype=torch.float32, device=DEV)
+        S.render_grid(img, r.Ho, r.Wo, rs.rec, a, r.Ho, r.Wo, out)
+        torch.cuda.synchronize()
+        assert torch.equal(r.result, out), r.rid
+        if r.rid == 1:   # the oracle's refresh of the same sites on the same grid
+            sites = encs[r.set_id].sites.cpu().numpy()
+            ref = oracle.refresh(rs.H, rs.W, r.Ho, r.Wo, rs.K, oracle.default_scale(rs.H, rs.W),
+                                 sites, rs.n_slots, True, V.RESCALE_PASSES, 4, 0)
+            assert np.array_equal(planar_to_rows(a.cpu().numpy(), r.Ho, r.Wo, rs.K), ref)
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["failed"] == 0
