@@ -468,6 +468,9 @@ def batched_vs_loop(steps, seed=0):
             "tuned_schedule": tuned, "autotune": timings}
 
 
+OVERLOAD_RPS = 15000
+
+
 def serving(rates, seconds, seed=0):
     """32 resident sets (sides 512-4096, 0.05 sites/px, K = 8), Poisson arrivals, 80 %
     point queries of 1e3-1e6 points, 20 % full renders; admission by device memory."""
@@ -547,8 +550,7 @@ def serving(rates, seconds, seed=0):
         torch.cuda.synchronize()
         return srv.stats()
 
-    for rate in rates:
-        times = V.poisson_arrivals(rate, seconds, rng)
+    def draw(times):
         specs = []
         for _ in times:
             sid = int(rng.integers(0, len(sets)))
@@ -557,6 +559,11 @@ def serving(rates, seconds, seed=0):
                 continue
             M = int(np.exp(rng.uniform(np.log(1e3), np.log(1e6))))
             specs.append((sid, M, int(rng.integers(0, (1 << 20) - M + 1))))
+        return specs
+
+    for rate in rates:
+        times = V.poisson_arrivals(rate, seconds, rng)
+        specs = draw(times)
         out["by_rate"][str(rate)] = rounded(served(specs, times))
         print(f"bench: serving at {rate} req/s done", file=sys.stderr, flush=True)
     # the same request stream (the highest rate's) served by a plain loop: each request
@@ -582,6 +589,18 @@ def serving(rates, seconds, seed=0):
                   "speedup": round(cap_srv["throughput_rps"] / cap_loop["throughput_rps"], 3),
                   "server_p99_ms": round(cap_srv["p99_ms"], 3),
                   "loop_p99_ms": round(cap_loop["p99_ms"], 3)}}
+    print("bench: serving burst done", file=sys.stderr, flush=True)
+    # an open-loop Poisson load above the plain loop's capacity (same request mix): the
+    # loop falls behind and its queue grows; the server batches the point queries that
+    # arrive while its launches run
+    o_s = min(4.0, seconds)
+    o_times = V.poisson_arrivals(OVERLOAD_RPS, o_s, rng)
+    o_specs = draw(o_times)
+    if o_specs:
+        o_srv = served(o_specs, o_times)
+        o_loop = plain_loop(sets, make(o_specs), o_times)
+        out["overload"] = {"rate": OVERLOAD_RPS, "seconds": o_s, "requests": len(o_specs),
+                           "server": rounded(o_srv), "plain_loop": rounded(o_loop)}
     return out
 
 

@@ -148,7 +148,13 @@ def _check(status, name):
         raise SadError(f"{name}: {lib.sad_status_string(status).decode()} ({status}): {msg}")
 
 
+_raw_stream = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+
+
 def _stream():
+    """The current HIP stream of the current device (the one torch launches on)."""
+    if _raw_stream is not None:   # no Stream object: this runs once per call
+        return C.c_void_p(_raw_stream(torch._C._cuda_getDevice()))
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 

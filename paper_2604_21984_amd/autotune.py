@@ -5,16 +5,19 @@ size (workgroups per compute unit) and the work assignment (contiguous runs of t
 workgroup, which keeps neighbouring tiles in one XCD's L2, or round robin) by timing
 graph-replayed iterations of the actual batch, then the
 propagation schedule: the candidate update period f (propagate every f-th iteration,
-App. B.3), judged at equal wall time: from the same state, f = 1 runs `window`
-iterations and every other period runs as many iterations as fit in the same time (from
-its own measured iteration time); the period with the lowest batch loss at that time
-wins, so a period is only picked when its cheaper iterations buy more progress than they
-lose.  The trials start from the state reached after
-`warm` iterations past the current one (the first iterations of an encode take the
-long jumps of the schedule with unsettled lists and cost many times the steady state,
-so timing them would tune for the wrong regime).  The batch's state is restored after
-the trials, so tuning does not change the encode.  Results are cached per workload
-signature (image shapes, site counts, K) in memory and optionally in a JSON file.
+App. B.3), judged at equal wall time from the batch's current state (the start of the
+encode when the tuner runs first): the first candidate period runs `window` iterations,
+every other period runs for as long as that took, and the period with the lowest batch
+loss at that time wins.  The schedule trials start where the encode starts because the
+period changes the pass index, and with it the jump schedule and the cost of the
+early, long-jump passes: trials from a warmed-up state re-run long jumps that the real
+encode has behind it, and favoured f = 4, which loses at equal wall time over a whole
+1000-iteration encode.  The launch-shape trials start from the state reached after
+`warm` iterations past the current one (the first iterations of an encode cost many
+times the steady state, so timing them would tune for the wrong regime).  The batch's
+state is restored after the trials, so tuning does not change the encode.  Results are
+cached per workload signature (image shapes, site counts, K) in memory and optionally
+in a JSON file.
 """
 import json
 import os
@@ -43,13 +46,14 @@ class Autotuner:
             with open(cache_path) as f:
                 self.cache = json.load(f)
 
-    def tune(self, enc, pairs=3, reps=2, schedules=(1,), window=64, warm=12,
+    def tune(self, enc, pairs=3, reps=2, schedules=(1,), window=128, warm=12,
              tile_widths=(16, 32)):
         """Return (grid, chunked, timings) for a BatchEncoder and apply the best launch
         (its tile width is then enc.tile_w);
         with more than one candidate update period in `schedules` also pick and apply
         the period (reported under timings["prop_every"]).  `warm` (even) iterations
-        are run first; every trial starts from the state they reach."""
+        are run first and every launch trial starts from the state they reach; the
+        schedule trials start from the state the batch had on entry."""
         sig = (_signature(enc) + f"|f{','.join(map(str, schedules))}"
                f"|t{','.join(map(str, tile_widths))}")
         if sig in self.cache:
@@ -99,22 +103,27 @@ class Autotuner:
                 torch.cuda.synchronize()
                 return e0.elapsed_time(e1)
 
-            per_it = {}
-            for f in schedules:       # iteration time of each period (short window)
-                enc.restore(snap)
-                enc.set_prop_every(f)
-                enc.capture()
-                enc.replay(1)
-                torch.cuda.synchronize()
-                per_it[f] = run(4) / 8
-            budget = per_it[schedules[0]] * window   # wall time of `window` iterations at f_0
+            chunk = 1           # pairs of iterations between two clock readings
+            budget = None
             for f in schedules:
-                n_pairs = max(1, int(budget / per_it[f]) // 2)
-                enc.restore(snap)
+                enc.restore(orig)
                 enc.set_prop_every(f)
                 enc.capture()
-                run(n_pairs)
-                sched[f] = (per_it[f], 2 * n_pairs, sum(enc.losses()))
+                enc.replay(1)           # the graph's first replay, untimed
+                torch.cuda.synchronize()
+                enc.restore(orig)
+                t, its, last = 0.0, 0, 0.0
+                if budget is None:      # the first period sets the wall-time budget
+                    while its < window:
+                        t += run(chunk)
+                        its += 2 * chunk
+                    budget = t
+                else:                   # others stop before they would exceed it
+                    while its == 0 or t + last <= budget:
+                        last = run(chunk)
+                        t += last
+                        its += 2 * chunk
+                sched[f] = (t, its, sum(enc.losses()))
             best_f = min(schedules, key=lambda f: (sched[f][2], f))
             enc.restore(orig)
             enc.set_prop_every(best_f)

@@ -87,12 +87,34 @@ def request_bytes(req, rset):
     return 12 * rset.H * rset.W
 
 
+class _OnStream:
+    """Make `stream` the current stream of its device for a block (what
+    torch.cuda.stream() does, without its per-call device lookups)."""
+    __slots__ = ("C", "st", "prev")
+
+    def __init__(self, C, st):
+        self.C, self.st = C, st
+
+    def __enter__(self):
+        st = self.st
+        self.prev = self.C._cuda_getCurrentStream(st.device_index)
+        self.C._cuda_setStream(stream_id=st.stream_id, device_index=st.device_index,
+                               device_type=st.device_type)
+
+    def __exit__(self, *exc):
+        sid, di, dt = self.prev
+        self.C._cuda_setStream(stream_id=sid, device_index=di, device_type=dt)
+
+
 class GpuBackend:
     """Launches on a pool of default-priority HIP streams; completion via events.
 
     A request's inputs (the query points) may still be being written on the stream that
     was current when it was submitted: submit() records an event there, and every launch
-    makes its stream wait for the events of its requests before reading their inputs."""
+    makes its stream wait for the events of its requests before reading their inputs.
+    Events are pooled: a stream's wait holds the event's state at the time of the wait,
+    so a readiness event is reused as soon as its waits are queued, and a completion
+    event once its launch has been seen to finish."""
 
     def __init__(self, device=None, n_streams=4):
         import torch
@@ -100,22 +122,39 @@ class GpuBackend:
         from . import _lib as S
         self.torch, self.S = torch, S
         self.device = torch.device(device or "cuda")
+        self.dev = (self.device.index if self.device.index is not None
+                    else torch.cuda.current_device())
         self.streams = [torch.cuda.Stream(self.device) for _ in range(n_streams)]
         self._next = 0
         self._images = {}  # (set id, shape, K, slots, scale) -> sad_image descriptor
+        self._events = []  # free events
+        self._callers = {}  # stream id -> Stream object of a submitting stream
 
     def now(self):
         return time.perf_counter()
 
+    def _event(self):
+        return self._events.pop() if self._events else self.torch.cuda.Event()
+
+    def _on(self, st):
+        return _OnStream(self.torch._C, st)
+
     def on_submit(self, req):
-        ev = self.torch.cuda.Event()
-        ev.record(self.torch.cuda.current_stream(self.device))
+        sid, di, dt = self.torch._C._cuda_getCurrentStream(self.dev)
+        caller = self._callers.get(sid)
+        if caller is None:
+            caller = self.torch.cuda.Stream(stream_id=sid, device_index=di, device_type=dt)
+            self._callers[sid] = caller
+        ev = self._event()
+        ev.record(caller)
         req.ready = ev
 
     def _wait_inputs(self, st, reqs):
         for r in reqs:
             if r.ready is not None:
                 st.wait_event(r.ready)
+                self._events.append(r.ready)
+                r.ready = None
             if r.xy is not None:
                 r.xy.record_stream(st)   # the allocator keeps xy until st is done with it
 
@@ -144,10 +183,10 @@ class GpuBackend:
             r, rs = reqs[0], sets[reqs[0].set_id]
             st = self._stream()
             self._wait_inputs(st, reqs)
-            with torch.cuda.stream(st):
+            with self._on(st):
                 out = torch.empty((r.M, 3), dtype=torch.float32, device=self.device)
                 S.query_points(self._image(rs), rs.rec, rs.topk, r.xy, out)
-                ev = torch.cuda.Event()
+                ev = self._event()
                 ev.record(st)
             return {"event": ev, "reqs": reqs, "outs": [out], "keep": ()}
         arr = (S.SadQueryJob * n)()
@@ -162,11 +201,11 @@ class GpuBackend:
             q0 += r.M
         st = self._stream()
         self._wait_inputs(st, reqs)
-        with torch.cuda.stream(st):
+        with self._on(st):
             host = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8).pin_memory()
             jobs = host.to(self.device, non_blocking=True)
             S.query_batch(jobs, n, q0, K)
-            ev = torch.cuda.Event()
+            ev = self._event()
             ev.record(st)
         return {"event": ev, "reqs": reqs, "outs": outs, "keep": (host, jobs)}
 
@@ -174,10 +213,10 @@ class GpuBackend:
         torch, S = self.torch, self.S
         st = self._stream()
         self._wait_inputs(st, [req])
-        with torch.cuda.stream(st):
+        with self._on(st):
             out = torch.empty((3, rset.H, rset.W), dtype=torch.float32, device=self.device)
             S.render_fwd(self._image(rset), rset.rec, rset.topk, out)
-            ev = torch.cuda.Event()
+            ev = self._event()
             ev.record(st)
         return {"event": ev, "reqs": [req], "outs": [out], "keep": ()}
 
@@ -188,7 +227,7 @@ class GpuBackend:
         st = self._stream()
         self._wait_inputs(st, [req])
         Ho, Wo, K = req.Ho, req.Wo, rset.K
-        with torch.cuda.stream(st):
+        with self._on(st):
             img = self._image(rset)
             a = torch.empty((K // 4, Ho, Wo, 4), dtype=torch.int32, device=self.device)
             b = torch.empty_like(a)
@@ -196,7 +235,7 @@ class GpuBackend:
             S.refresh(img, Ho, Wo, rset.rec, a, b, scratch, RESCALE_PASSES, 4, seed, jfa=True)
             out = torch.empty((3, Ho, Wo), dtype=torch.float32, device=self.device)
             S.render_grid(img, Ho, Wo, rset.rec, a, Ho, Wo, out)
-            ev = torch.cuda.Event()
+            ev = self._event()
             ev.record(st)
         return {"event": ev, "reqs": [req], "outs": [out], "keep": (a, b, scratch)}
 
@@ -204,6 +243,9 @@ class GpuBackend:
         return h["event"].query()
 
     def results(self, h):
+        """The (request, output) pairs of a finished launch; its event goes back to the
+        pool (call once, after done(h))."""
+        self._events.append(h.pop("event"))
         return list(zip(h["reqs"], h["outs"]))
 
 

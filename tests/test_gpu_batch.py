@@ -93,6 +93,31 @@ def test_batch_graph_replay_and_autotune(mods):
     torch.testing.assert_close(graphed.sites, eager.sites, rtol=1e-4, atol=1e-4)
 
 
+def test_autotune_update_period_at_equal_wall_time(mods):
+    """The schedule trials: the first period runs the window, every other period stops
+    before it would run longer than that; the chosen period is applied, the encode's
+    state is left as it was, and a second call returns the cached choice."""
+    S, B, E, T = mods
+    cfg = E.EncodeConfig(K=8, n_inject=4, seed=11)
+    tg = _targets()
+    be = B.BatchEncoder(tg, [n for _, _, n in SHAPES], cfg)
+    before = (be.sites.clone(), be.lists[be.cur].clone())
+    tuner = T.Autotuner()
+    _, _, timings = tuner.tune(be, pairs=1, reps=1, schedules=(1, 2), window=16,
+                               tile_widths=(16,))
+    pe = timings["prop_every"]
+    assert set(pe) == {"1", "2"} and pe["1"]["iterations"] == 16
+    assert pe["2"]["iterations"] >= 2 and pe["2"]["iterations"] % 2 == 0
+    assert pe["2"]["iterations"] == 2 or pe["2"]["ms"] <= pe["1"]["ms"] * 1.0001
+    best = timings["prop_every_best"]
+    assert best == min((1, 2), key=lambda f: (pe[str(f)]["loss"], f))
+    assert be.train_cfg.prop_every == best
+    assert torch.equal(be.sites, before[0]) and torch.equal(be.lists[be.cur], before[1])
+    be.set_prop_every(1)
+    tuner.tune(be, pairs=1, reps=1, schedules=(1, 2), window=16, tile_widths=(16,))
+    assert be.train_cfg.prop_every == best
+
+
 def test_deterministic_batch_equals_per_image_bitwise(mods):
     """With deterministic gradient sums every image of the batch follows its per-image
     encoder bit for bit (same tiles, exact tile sums, one rounding each, integer sums),
