@@ -113,16 +113,20 @@ class AutogradTrainer:
         self.state = S.step_state(dev)
         self.loss = None
         self.graph = None
+        self._one = torch.ones((), dtype=torch.float32, device=dev)  # dL/dL, allocated once
 
     def step(self):
         a, b = self.lists[self.cur], self.lists[1 - self.cur]
         S.propagate_topk_state(self.img, self.rec, a, b, self.J, self.seed, self.state)
+        # with no .grad the backward's gradient tensor becomes sites.grad as it is (no
+        # accumulate kernel, no clearing after Adam); dL/dL is a preallocated one
+        self.sites.grad = None
         out = render(self.sites, b, self.img, self.rec)
         loss = mse_loss(out, self.target, self.img)
-        loss.backward()
+        loss.backward(self._one)
         self.loss = loss.detach()  # keep no autograd graph alive across iterations
         S.adam_step_state(self.img, self.sites.data, self.sites.grad, self.m, self.v,
-                          self.adam, self.rec, self.state, zero_grad=True)
+                          self.adam, self.rec, self.state)
         self.cur = 1 - self.cur
 
     def capture(self, pairs=1, warmup=2):
@@ -163,10 +167,11 @@ class FusedAutogradTrainer(AutogradTrainer):
 
     def step(self):
         a, b = self.lists[self.cur], self.lists[1 - self.cur]
+        self.sites.grad = None
         loss = SADTrainPass.apply(self.sites, self.target, self.img, self.cfg, self.rec, a, b,
                                   self.gacc, self.state, False)
-        loss.backward()
+        loss.backward(self._one)
         self.loss = loss.detach()
         S.adam_step_state(self.img, self.sites.data, self.sites.grad, self.m, self.v,
-                          self.adam, self.rec, self.state, zero_grad=True)
+                          self.adam, self.rec, self.state)
         self.cur = 1 - self.cur
