@@ -28,9 +28,9 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources they were taken with: HBM bytes per launch from FETCH_SIZE + WRITE_SIZE
 # scaled by a copy kernel's readings, and the utilisation counters.
 PROFILED = {
-    "90f33b140f310afe": {"traffic_bytes": 45002203, "valu_insts": 25141279,
-                         "counters": {"VALUBusy_pct": 60.3, "LDSBankConflict_pct": 16.9,
-                                      "OccupancyPercent": 47.7, "MemUnitStalled_pct": 0.08}},
+    "05a633ff5933d3a9": {"traffic_bytes": 44996892, "valu_insts": 21798139,
+                         "counters": {"VALUBusy_pct": 53.5, "LDSBankConflict_pct": 17.3,
+                                      "OccupancyPercent": 48.2, "MemUnitStalled_pct": 0.11}},
 }
 # Vector-ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s (one
 # non-packed float32 operation per lane; packed FMA makes the 157.3 TFLOP/s headline).

@@ -272,6 +272,10 @@ typedef struct {
     uint32_t flags;
 } sad_train_config;
 #define SAD_TRAIN_DETERMINISTIC 1u
+/* SAD_TRAIN_LOSS_SET (sad_train_image_pass): store L in state->loss.value instead of
+ * adding it (no separate clear of the value before the pass).  sad_train_step always
+ * stores L; the batched step does not take this flag. */
+#define SAD_TRAIN_LOSS_SET 2u
 
 /* One iteration (Sec. 5: no host work inside the loop), enqueued as:
  *   1. propagation pass topk_in -> topk_out with pass index state->pass;
@@ -296,8 +300,9 @@ sad_status sad_train_step(const sad_image *img, const sad_train_config *cfg, con
 
 /* Steps 1-3 of sad_train_step alone (rows a3-a6 as one kernel): the propagation pass
  * with pass index state->pass (not advanced), the blend, the loss gradient (L added to
- * state->loss.value) and the backward into grad_sites (site-major [cap][10],
- * accumulated, +=).  Same argument meaning as sad_train_step. */
+ * state->loss.value, or stored there with SAD_TRAIN_LOSS_SET) and the backward into
+ * grad_sites (site-major [cap][10], accumulated, +=).  Same argument meaning as
+ * sad_train_step. */
 sad_status sad_train_image_pass(const sad_image *img, const sad_train_config *cfg,
                                 const float *target, const float *rec, const uint32_t *topk_in,
                                 uint32_t *topk_out, float *grad_sites, float *rendered,

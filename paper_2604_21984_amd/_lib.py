@@ -296,6 +296,7 @@ ADAM_ZERO_GRAD = 1
 ADAM_GRAD_SITE_MAJOR = 2
 ADAM_GRAD_FIXED = 4
 TRAIN_DETERMINISTIC = 1
+TRAIN_LOSS_SET = 2
 
 
 def _grad_dtype(cfg):
@@ -428,13 +429,15 @@ def version():
     return lib.sad_version().decode()
 
 
-def train_config(n_inject, seed, adam, fixed_jump=0, prop_every=1, deterministic=False):
+def train_config(n_inject, seed, adam, fixed_jump=0, prop_every=1, deterministic=False,
+                 loss_set=False):
     """sad_train_config; deterministic=True makes the gradient accumulator int64 fixed
-    point (allocate it as torch.int64, same shape) and the sums bit-reproducible."""
+    point (allocate it as torch.int64, same shape) and the sums bit-reproducible;
+    loss_set=True makes sad_train_image_pass store L instead of adding it."""
     c = SadTrainConfig()
     c.n_inject, c.fixed_jump, c.seed, c.adam = int(n_inject), int(fixed_jump), int(seed) & (2 ** 64 - 1), adam
     c.prop_every = int(prop_every)
-    c.flags = TRAIN_DETERMINISTIC if deterministic else 0
+    c.flags = (TRAIN_DETERMINISTIC if deterministic else 0) | (TRAIN_LOSS_SET if loss_set else 0)
     return c
 
 

@@ -62,7 +62,8 @@ class SADTrainPass(torch.autograd.Function):
     def forward(ctx, sites, target, img, cfg, rec, topk_in, topk_out, gacc, state, prepare):
         if prepare:
             S.prepare_sites(img, sites.detach(), rec)
-        S.state_loss(state).zero_()
+        if not (cfg.flags & S.TRAIN_LOSS_SET) or img.n_slots == 0:
+            S.state_loss(state).zero_()   # the pass adds L (with no sites it forms none)
         S.train_image_pass(img, cfg, target, rec, topk_in, topk_out, gacc, None, None, state)
         ctx.img, ctx.cap = img, sites.shape[1]
         ctx.gacc = gacc
@@ -162,7 +163,7 @@ class FusedAutogradTrainer(AutogradTrainer):
 
     def __init__(self, img, sites, topk, target, adam, n_inject=4, seed=0):
         super().__init__(img, sites, topk, target, adam, n_inject, seed)
-        self.cfg = S.train_config(self.J, self.seed, adam)
+        self.cfg = S.train_config(self.J, self.seed, adam, loss_set=True)
         self.gacc = torch.zeros((img.cap, 10), dtype=torch.float32, device=sites.device)
 
     def step(self):

@@ -30,9 +30,9 @@ __device__ __forceinline__ FixScale fix_scale_dev(int64_t P) {
     fx.from_fix = ldexp(1.0, -(32 + e));
     fx.limit = (float)ldexp(1.0, 15 - e);
     fx.to_det = ldexp(1.0, 40 + e - kGlobShift);
-    fx.pre = ldexpf(1.0f, 8 + e);
-    fx.pre_det = ldexpf(1.0f, 16 + e - kGlobShift);
-    fx.post = ldexpf(1.0f, -(8 + e));
+    fx.pre = ldexpf(1.0f, 32 + e);
+    fx.pre_det = ldexpf(1.0f, 40 + e - kGlobShift);
+    fx.post = ldexpf(1.0f, -(32 + e));
     return fx;
 }
 

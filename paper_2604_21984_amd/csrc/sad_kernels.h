@@ -445,26 +445,24 @@ struct FixScale {
     double to_det;     // 2^(20 + e): the deterministic mode's unit is 2^-(20 + e)
     // The backward forms its terms from a pre-scaled dL/dc (every gradient term is
     // linear in dL/dc, so scaling it by a power of two scales each term exactly): a
-    // term v arrives as v' = v 2^-24 / unit, |v'| < 2^23 when the term is in range,
-    // and its fixed-point integer is rint(v' 2^24) (to_fixed24).
-    float pre;         // 2^(8 + e)
-    float pre_det;     // 2^(e - 4)
-    float post;        // 2^-(8 + e): back from v' to v (float fallback)
+    // term v arrives as x = v / unit, |x| < 2^47 when the term is in range, and its
+    // fixed-point integer is rint(x) (rint_i64).
+    float pre;         // 2^(32 + e)
+    float pre_det;     // 2^(40 + e - kGlobShift)
+    float post;        // 2^-(32 + e): back from x to v (float fallback)
 };
 
-// |v'| bound of a pre-scaled term that the tile table takes.
-constexpr float kHiLimit = 0x1p23f;
+// |x| bound of a pre-scaled term that the tile table takes (a tile slot then sums at
+// most 256 terms below 2^47: far from 2^63).
+constexpr float kHiLimit = 0x1p47f;
 
-// rint(v' 2^24) (ties to even) as a 64-bit two's complement integer, for |v'| < 2^23,
-// from float operations alone: hi = floor(v') and the fraction f = v' - hi (exact, or
-// for -1/2 < v' < 0 rounded to 2^-24 with the same tie rule as the whole, which can
-// round up to 1 for a tiny negative v'); lo = rint(f 2^24) <= 2^24; the integer is
-// hi 2^24 + lo, formed with a 64-bit add so that lo = 2^24 carries (below 2^47 in
-// magnitude).
-__device__ __forceinline__ unsigned long long to_fixed24(float vs) {
-    const float hi = floorf(vs);
-    const float lo = rintf((vs - hi) * 0x1p24f);
-    return ((unsigned long long)(long long)(int32_t)hi << 24) + (uint32_t)lo;
+// rint(x) (ties to even) of a float with |x| < 2^51 as a 64-bit two's complement
+// integer: in double, x + 1.5 2^52 lies in [2^52, 2^53), where neighbouring doubles are
+// 1 apart, so the add rounds x to an integer and the sum's encoding is the encoding of
+// 1.5 2^52 plus that integer.  A conversion, a double add and a 64-bit subtract.
+__device__ __forceinline__ unsigned long long rint_i64(float x) {
+    const double d = (double)x + 0x1.8p52;
+    return (unsigned long long)__double_as_longlong(d) - 0x4338000000000000ull;
 }
 
 // Deterministic gradient sums (training steps with SAD_TRAIN_DETERMINISTIC): every
@@ -481,10 +479,10 @@ __device__ __forceinline__ long long *grad64_at(float *grad, int q, uint32_t id,
     return site_major ? g + (int64_t)id * SAD_NPARAM + q : g + q * cap + id;
 }
 
-// A pre-scaled term v' (v' 2^24 in the deterministic unit) straight into the
-// deterministic accumulator (clamped to the int64 range).
-__device__ __forceinline__ void det_add_hi(long long *dst, float vs) {
-    double x = rint((double)vs * 0x1p24);
+// A pre-scaled term x (in the deterministic unit) straight into the deterministic
+// accumulator: rint(x), clamped to the int64 range.
+__device__ __forceinline__ void det_add_x(long long *dst, float xs) {
+    double x = rint((double)xs);
     x = fmin(fmax(x, -0x1p62), 0x1p62);
     atomicAdd(reinterpret_cast<unsigned long long *>(dst), (unsigned long long)(long long)x);
 }
@@ -573,7 +571,7 @@ __device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const 
         }
     }
     // Every gradient term is linear in dL/dc: form them from dL/dc pre-scaled so that
-    // each term arrives in units of 2^24 table units (to_fixed24).
+    // each term arrives in table units (rint_i64).
     const float pre = kDet ? fx.pre_det : fx.pre;
     const float gs0 = g0 * pre, gs1 = g1 * pre, gs2 = g2 * pre;
     // Entries are visited one at a time from the front of shifting copies of the
@@ -656,14 +654,19 @@ __device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const 
         const bool in = slot >= 0 && asum < kHiLimit;
         const int sl = slot >= 0 ? slot : 0;
 #pragma unroll
-        for (int q = 0; q < nq; ++q)
-            atomicAdd(&hacc[q][sl], in ? to_fixed24(acc[q]) : 0ull);
+        for (int q = 0; q < nq; ++q) {
+            // select the float, then convert: the empty asm keeps the compiler from
+            // moving the select after the conversion (two 32-bit selects instead of one)
+            float x = in ? acc[q] : 0.0f;
+            asm("" : "+v"(x));
+            atomicAdd(&hacc[q][sl], rint_i64(x));
+        }
         if (!in) {
 #pragma unroll
             for (int q = 0; q < nq; ++q) {
                 if (acc[q] == 0.0f) continue;
                 if (kDet && q < 10)
-                    det_add_hi(grad64_at(grad, q, id, cap, kSiteMajor), acc[q]);
+                    det_add_x(grad64_at(grad, q, id, cap, kSiteMajor), acc[q]);
                 else
                     atomic_add_f32(q < 10 ? grad_at<kSiteMajor>(grad, q, id, cap) : rdel + id,
                                    acc[q] * fx.post);
@@ -728,9 +731,9 @@ inline FixScale fix_scale(int64_t P) {
     fx.from_fix = std::ldexp(1.0, -(32 + e));
     fx.limit = (float)std::ldexp(1.0, 15 - e);
     fx.to_det = std::ldexp(1.0, 40 + e - kGlobShift);
-    fx.pre = std::ldexp(1.0f, 8 + e);
-    fx.pre_det = std::ldexp(1.0f, 16 + e - kGlobShift);
-    fx.post = std::ldexp(1.0f, -(8 + e));
+    fx.pre = std::ldexp(1.0f, 32 + e);
+    fx.pre_det = std::ldexp(1.0f, 40 + e - kGlobShift);
+    fx.post = std::ldexp(1.0f, -(32 + e));
     return fx;
 }
 

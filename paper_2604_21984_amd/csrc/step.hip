@@ -122,8 +122,9 @@ static sad_status image_pass(const sad_image *img, const sad_train_config *cfg,
                 "training pass: n_inject must be in [0, 16]");
     SAD_REQUIRE(cfg->prop_every >= 0 && cfg->prop_every <= 1024, SAD_ERR_INVALID_ARGUMENT,
                 "training pass: prop_every must be in [0, 1024]");
-    SAD_REQUIRE((cfg->flags & ~SAD_TRAIN_DETERMINISTIC) == 0, SAD_ERR_INVALID_ARGUMENT,
-                "training pass: unknown flags 0x%x", cfg->flags);
+    SAD_REQUIRE((cfg->flags & ~(SAD_TRAIN_DETERMINISTIC | SAD_TRAIN_LOSS_SET)) == 0,
+                SAD_ERR_INVALID_ARGUMENT, "training pass: unknown flags 0x%x", cfg->flags);
+    overwrite_loss = overwrite_loss || (cfg->flags & SAD_TRAIN_LOSS_SET) != 0;
     if (img->n_slots == 0) {  // no sites: empty lists, colour 0, nothing to update
         launch_propagate(img, rec, topk_in, topk_out, 1, 0, 0, 0, nullptr, st);
         if (grad_img)

@@ -84,7 +84,7 @@ def test_host_validation_of_state_forms_and_flags(lib):
                                    C.c_uint32(0), None, None) == 1
     # training pass: unknown training flags
     cfg = S.train_config(4, 0, params)
-    cfg.flags = 2
+    cfg.flags = 4
     assert lib.sad_train_image_pass(C.byref(ok), C.byref(cfg), p, p, p, q, p, None, None, p,
                                     None) == 1
     assert b"unknown flags" in lib.sad_last_error()
@@ -94,3 +94,4 @@ def test_host_validation_of_state_forms_and_flags(lib):
     assert b"8-byte aligned" in lib.sad_last_error()
     assert S.train_config(4, 0, params, deterministic=True).flags == S.TRAIN_DETERMINISTIC
     assert S.train_config(4, 0, params).flags == 0
+    assert S.train_config(4, 0, params, loss_set=True).flags == S.TRAIN_LOSS_SET == 2

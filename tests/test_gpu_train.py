@@ -170,6 +170,12 @@ def test_fused_autograd_pass_matches_oracle(mods):
     assert abs(loss.item() - L) <= 1e-5 * L
     assert grad_close(sites.grad.cpu().numpy() / 3.0, ref, ab) <= 1.0
     assert float(gacc.abs().max()) == 0.0
+    # with SAD_TRAIN_LOSS_SET the pass stores L: a stale value in the state does not leak
+    cfg2 = S.train_config(J, seed, S.adam_params([0.0] * 10), loss_set=True)
+    S.state_loss(state).fill_(123.0)
+    loss2 = A.SADTrainPass.apply(sites.detach(), target, img, cfg2, rec, topk_in, topk_out,
+                                 gacc, state, False)
+    assert abs(loss2.item() - L) <= 1e-5 * L
 
 
 def test_fused_autograd_trainer_graph_matches_eager(mods):
