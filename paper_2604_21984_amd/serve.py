@@ -47,6 +47,7 @@ class Request:
     error: str = None
     nbytes: int = 0
     ready: object = None         # backend marker: the request's inputs are written
+    stream: object = None        # backend marker: the stream they are written on
     Ho: int = 0                  # output grid of a RESCALE request
     Wo: int = 0
 
@@ -98,12 +99,16 @@ class _OnStream:
     def __enter__(self):
         st = self.st
         self.prev = self.C._cuda_getCurrentStream(st.device_index)
+        if self.prev[0] == st.stream_id:
+            self.prev = None           # already current
+            return
         self.C._cuda_setStream(stream_id=st.stream_id, device_index=st.device_index,
                                device_type=st.device_type)
 
     def __exit__(self, *exc):
-        sid, di, dt = self.prev
-        self.C._cuda_setStream(stream_id=sid, device_index=di, device_type=dt)
+        if self.prev is not None:
+            sid, di, dt = self.prev
+            self.C._cuda_setStream(stream_id=sid, device_index=di, device_type=dt)
 
 
 class GpuBackend:
@@ -112,9 +117,14 @@ class GpuBackend:
     A request's inputs (the query points) may still be being written on the stream that
     was current when it was submitted: submit() records an event there, and every launch
     makes its stream wait for the events of its requests before reading their inputs.
-    Events are pooled: a stream's wait holds the event's state at the time of the wait,
-    so a readiness event is reused as soon as its waits are queued, and a completion
-    event once its launch has been seen to finish."""
+    Events are pooled: a request's readiness event and a launch's completion event go
+    back to the pool once the launch has been seen to finish (a readiness event is
+    kept until then, so that a launch retried request by request waits again).  A
+    direct launch (one request while nothing else is in flight, the scheduler's choice)
+    runs on the stream the request's inputs were written on, which needs no wait: with
+    no other launch to overlap, a pool stream would only add the wait's cost."""
+
+    direct_launch = True   # the launch methods take direct=
 
     def __init__(self, device=None, n_streams=4):
         import torch
@@ -148,13 +158,22 @@ class GpuBackend:
         ev = self._event()
         ev.record(caller)
         req.ready = ev
+        req.stream = caller
+
+    def _lane(self, reqs, direct):
+        """The stream a launch runs on, its requests' inputs ordered before it: with
+        direct, the one request's own submitting stream (stream order suffices); else
+        the next pool stream, made to wait for every request's readiness event."""
+        if direct and len(reqs) == 1 and reqs[0].stream is not None:
+            return reqs[0].stream
+        st = self._stream()
+        self._wait_inputs(st, reqs)
+        return st
 
     def _wait_inputs(self, st, reqs):
         for r in reqs:
-            if r.ready is not None:
+            if r.ready is not None:   # kept until the launch is done: a retry waits again
                 st.wait_event(r.ready)
-                self._events.append(r.ready)
-                r.ready = None
             if r.xy is not None:
                 r.xy.record_stream(st)   # the allocator keeps xy until st is done with it
 
@@ -175,14 +194,13 @@ class GpuBackend:
             self._images[key] = img
         return img
 
-    def launch_queries(self, reqs, sets):
+    def launch_queries(self, reqs, sets, direct=False):
         torch, S = self.torch, self.S
         K = sets[reqs[0].set_id].K
         n = len(reqs)
         if n == 1:  # one request: sad_query_points, with no job table to upload
             r, rs = reqs[0], sets[reqs[0].set_id]
-            st = self._stream()
-            self._wait_inputs(st, reqs)
+            st = self._lane(reqs, direct)
             with self._on(st):
                 out = torch.empty((r.M, 3), dtype=torch.float32, device=self.device)
                 S.query_points(self._image(rs), rs.rec, rs.topk, r.xy, out)
@@ -209,10 +227,9 @@ class GpuBackend:
             ev.record(st)
         return {"event": ev, "reqs": reqs, "outs": outs, "keep": (host, jobs)}
 
-    def launch_render(self, req, rset):
+    def launch_render(self, req, rset, direct=False):
         torch, S = self.torch, self.S
-        st = self._stream()
-        self._wait_inputs(st, [req])
+        st = self._lane([req], direct)
         with self._on(st):
             out = torch.empty((3, rset.H, rset.W), dtype=torch.float32, device=self.device)
             S.render_fwd(self._image(rset), rset.rec, rset.topk, out)
@@ -220,12 +237,11 @@ class GpuBackend:
             ev.record(st)
         return {"event": ev, "reqs": [req], "outs": [out], "keep": ()}
 
-    def launch_rescale(self, req, rset, seed=0):
+    def launch_rescale(self, req, rset, seed=0, direct=False):
         """A render of rset at req.Ho x req.Wo: refresh on that grid (JFA prepass and
         RESCALE_PASSES passes, J = 4), then render from the refreshed lists."""
         torch, S = self.torch, self.S
-        st = self._stream()
-        self._wait_inputs(st, [req])
+        st = self._lane([req], direct)
         Ho, Wo, K = req.Ho, req.Wo, rset.K
         with self._on(st):
             img = self._image(rset)
@@ -243,9 +259,13 @@ class GpuBackend:
         return h["event"].query()
 
     def results(self, h):
-        """The (request, output) pairs of a finished launch; its event goes back to the
+        """The (request, output) pairs of a finished launch; its events go back to the
         pool (call once, after done(h))."""
         self._events.append(h.pop("event"))
+        for r in h["reqs"]:
+            if r.ready is not None:
+                self._events.append(r.ready)
+                r.ready = None
         return list(zip(h["reqs"], h["outs"]))
 
 
@@ -318,18 +338,25 @@ class Server:
             self.peak_reserved = max(self.peak_reserved, self.reserved)
             self.admitted.append(r)
 
+    def _direct(self):
+        """Keyword arguments of a launch: a backend that can launch a lone request on
+        its submitting stream is told to when nothing else is in flight."""
+        if getattr(self.backend, "direct_launch", False):
+            return {"direct": not self.inflight}
+        return {}
+
     def _launch(self):
         while self.admitted and len(self.inflight) < self.max_inflight:
             head = self.admitted[0]
             if head.kind == RENDER:
                 self.admitted.popleft()
-                self._start([head], lambda rs=self.sets[head.set_id], r=head:
-                             self.backend.launch_render(r, rs))
+                self._start([head], lambda rs=self.sets[head.set_id], r=head, kw=self._direct():
+                             self.backend.launch_render(r, rs, **kw))
                 continue
             if head.kind == RESCALE:
                 self.admitted.popleft()
-                self._start([head], lambda rs=self.sets[head.set_id], r=head:
-                             self.backend.launch_rescale(r, rs))
+                self._start([head], lambda rs=self.sets[head.set_id], r=head, kw=self._direct():
+                             self.backend.launch_rescale(r, rs, **kw))
                 continue
             # gather admitted point queries with the head's K, up to the point budget
             K = self.sets[head.set_id].K
@@ -343,7 +370,8 @@ class Server:
                 else:
                     keep.append(r)
             self.admitted = keep
-            self._start(batch, lambda b=batch: self.backend.launch_queries(b, self.sets))
+            self._start(batch, lambda b=batch, kw=self._direct():
+                        self.backend.launch_queries(b, self.sets, **kw))
 
     def _start(self, reqs, fn):
         t = self.backend.now()

@@ -140,6 +140,36 @@ def test_inputs_written_on_the_submitting_stream(sets):
         assert torch.equal(r.result, ref), r.rid
 
 
+def test_direct_launch_runs_on_the_submitting_stream(sets):
+    """A lone request (nothing else in flight) is launched on the stream it was submitted
+    from, behind the kernels that write its inputs there, also when the scheduler's own
+    current stream is another one; a request that arrives while it runs goes to a pool
+    stream and waits for its inputs."""
+    from paper_2604_21984_amd import serve as V
+    from paper_2604_21984_amd import _lib as S
+    rsets, _ = sets
+    srv = V.Server(V.GpuBackend(), rsets, mem_budget=64 << 20, max_inflight=4)
+    side = torch.cuda.Stream()
+    rs = rsets[0]
+    scale = torch.tensor([rs.W - 1.0, rs.H - 1.0], device=DEV)
+    torch.manual_seed(5)
+    reqs = []
+    with torch.cuda.stream(side):
+        for rid in range(2):
+            torch.cuda._sleep(int(2e6))
+            xy = torch.rand((300, 2), device=DEV) * scale
+            reqs.append(V.Request(rid, rs.set_id, V.QUERY, xy=xy, M=300))
+            srv.submit(reqs[-1])
+            srv.step()                       # the first launches alone, the second not
+    srv.drain(timeout=30.0)
+    assert [n for _, n, _ in srv.launches] == [1, 1]
+    torch.cuda.synchronize()
+    for r in reqs:
+        assert r.error is None, r.error
+        assert r.stream.stream_id == side.stream_id
+        assert torch.equal(r.result, _alone(S, rs, r.xy)), r.rid
+
+
 def test_renders_at_a_new_resolution(sets):
     """RESCALE requests (a render at another resolution: full refresh on the new grid,
     then the render) mixed with queries: each output equals sad_refresh + sad_render_grid
