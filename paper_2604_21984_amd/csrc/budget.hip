@@ -132,11 +132,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(K <= 8 ? 4 
             }
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                if (!b.ok[k]) continue;
+                const float w = b.e[k] * invS;
+                // every statistic of an entry is a multiple of its weight (the removal
+                // delta of a non-reference entry too): weight 0 adds exactly 0
+                if (!b.ok[k] || w == 0.0f) continue;
                 const uint32_t id = b.id[k];
                 const float4 q0 = rec[4 * (size_t)id];
                 const float4 q2 = rec[4 * (size_t)id + 2];
-                const float w = b.e[k] * invS;
                 const float om = w * err;
                 const float dx = X - q0.x, dy = Y - q0.y;
                 float p0, p1, p2;

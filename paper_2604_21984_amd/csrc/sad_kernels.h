@@ -581,9 +581,12 @@ __device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const 
     float ls[K], ws[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-        ids[k] = b.ok[k] ? b.id[k] : SAD_INVALID_ID;
-        ls[k] = b.l[k];
         ws[k] = b.e[k] * invS;
+        // every term of an entry is a multiple of its weight (the removal delta of a
+        // non-reference entry too): an entry whose weight is 0 adds exactly 0, so it
+        // takes no table slot and no atomics
+        ids[k] = (b.ok[k] && ws[k] != 0.0f) ? b.id[k] : SAD_INVALID_ID;
+        ls[k] = b.l[k];
     }
 #pragma unroll 1
     for (int k = 0; k < K; ++k) {
