@@ -143,3 +143,41 @@ def test_deterministic_batch_equals_per_image_bitwise(mods):
     assert torch.equal(runs[0].sites, runs[1].sites)
     assert torch.equal(runs[0].sites, runs[2].sites)
     assert (runs[0].grad == 0).all()
+
+
+def test_deterministic_batch_full_size_equals_per_image(mods):
+    """The batched-encode workload at its full size (64 images of 256^2 to 1024^2 pixels,
+    26.2 Mpx, 0.05 sites per pixel, K = 8): in the deterministic mode every image of the
+    batch, in the launch the benchmark times (one workgroup per 16 x 16 tile) and in the
+    persistent form with contiguous runs of tiles, equals its per-image encoder bit for
+    bit after four iterations (the per-image encoder is checked against the oracle at
+    768 x 512 in test_gpu_train_oracle)."""
+    from concurrent.futures import ThreadPoolExecutor
+    S, B, E, T = mods
+    shapes = synth.batch_shapes(0)
+    print(f"full-size batch: {len(shapes)} images, "
+          f"{sum(h * w for h, w, _ in shapes)} px", flush=True)
+    with ThreadPoolExecutor(8) as ex:
+        imgs = list(ex.map(lambda a: synth.image_encode(100 + a[0], a[1][0], a[1][1],
+                                                        n_polygons=20), enumerate(shapes)))
+    tg = [torch.from_numpy(im).to(DEV) for im in imgs]
+    ns = [n for _, _, n in shapes]
+    cfg = E.EncodeConfig(K=8, n_inject=4, seed=2, deterministic=True)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    runs = [B.BatchEncoder(tg, ns, cfg, grid=0, chunked=0),
+            B.BatchEncoder(tg, ns, cfg, grid=4 * n_cu, chunked=1)]
+    for _ in range(4):
+        for be in runs:
+            be.step()
+    torch.cuda.synchronize()
+    assert torch.equal(runs[0].sites, runs[1].sites)
+    assert torch.equal(runs[0].lists[runs[0].cur], runs[1].lists[runs[1].cur])
+    be = runs[0]
+    for b, (t, n) in enumerate(zip(tg, ns)):
+        enc = E.Encoder(t, n, cfg)
+        for _ in range(4):
+            enc.step()
+        torch.cuda.synchronize()
+        assert torch.equal(be.view_sites(b), enc.sites), b
+        assert torch.equal(be.view_list(be.cur, b), enc.topk), b
+        del enc
