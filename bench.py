@@ -794,6 +794,86 @@ def packed_decode(reps, seed=6):
     return out
 
 
+def variants(reps, seed=8):
+    """The method's variants (App. B.6, Sec. 7), timed:
+    * tau diffusion (sad_tau_diffusion) on the headline workload (768x512, 20 000 sites,
+      K = 8) after 60 iterations, reading the training step's site-major gradient: us
+      per call and its bytes per site (derived record 64 + list at the site's pixel 4K
+      + gradient in and out 8) over the call time;
+    * a one-dimensional encode: a 2^20-sample signal, 2^20 / 16 sites, K = 8, J = 4,
+      200 iterations of pass + render / loss / gradient + Adam + record refresh; us per
+      iteration over the last 100 (event-timed, eager), samples/s, and the loss at
+      the first and last iteration."""
+    import torch
+
+    import synth
+    from paper_2604_21984_amd import _lib as S
+    from paper_2604_21984_amd.encode import EncodeConfig, Encoder
+    out = {}
+    target = torch.from_numpy(synth.image_encode(seed, H, W)).cuda()
+    enc = Encoder(target, N_SITES, EncodeConfig(K=K, n_inject=J, seed=seed))
+    for _ in range(60):
+        enc.step()
+    g_in = torch.randn(enc.img.cap * S.NPARAM, device="cuda") * 1e-4
+    g_out = torch.empty(enc.img.cap, device="cuda")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, n):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(n):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / n
+
+    us = timed(lambda: S.tau_diffusion(enc.img, enc.rec, enc.topk, g_in[2:], S.NPARAM, 0.5,
+                                       g_out, 1), reps)
+    nb = enc.img.n_slots * (64 + 4 * K + 8)
+    out["tau_diffusion_768x512"] = {"n_sites": enc.img.n_slots, "us_per_call": round(us, 2),
+                                    "algorithmic_bytes": nb,
+                                    "gb_s": round(nb / (us * 1e3), 1)}
+    del enc, g_in, g_out
+    M, n = 1 << 20, (1 << 20) // 16
+    sig = torch.from_numpy(synth.signal1d(seed, M)).cuda()
+    sites = torch.from_numpy(synth.sites1d(seed + 1, M, n, log_tau_range=(4.0, 4.0),
+                                           r_range=(1.0, 1.0))).cuda()
+    sg = S.signal(M, K, n)
+    rec1 = torch.empty(4 * n, device="cuda")
+    S.prepare1d(sg, sites, rec1)
+    a = torch.empty(K * M, dtype=torch.int32, device="cuda")
+    b = torch.empty_like(a)
+    S.seed1d(sg, rec1, a, torch.empty(M, dtype=torch.int64, device="cuda"))
+    grad = torch.zeros((4, n), device="cuda")
+    m, v = torch.zeros_like(grad), torch.zeros_like(grad)
+    loss = S.loss_acc("cuda")
+    losses = []
+    lr = [1.0, 0.01, 0.01, 0.1]
+    for t in range(200):
+        if t == 100:
+            torch.cuda.synchronize()
+            e0.record()
+        S.propagate1d(sg, rec1, a, b, S.jump_step(t, 1, M), J, seed, t)
+        a, b = b, a
+        grad.zero_()
+        loss.zero_()
+        S.render1d(sg, rec1, a, sig, None, grad, loss)
+        S.adam1d(sg, sites, grad, m, v, lr, t + 1)
+        S.prepare1d(sg, sites, rec1)
+        if t in (0, 199):
+            losses.append(float(loss[0]))
+    e1.record()
+    torch.cuda.synchronize()
+    us_it = e0.elapsed_time(e1) * 1e3 / 100
+    out["one_dimensional"] = {"samples": M, "n_sites": n, "K": K, "J": J,
+                              "us_per_iteration": round(us_it, 2),
+                              "samples_per_s": round(M / (us_it * 1e-6), 1),
+                              "loss_first": losses[0], "loss_last": losses[1]}
+    return out
+
+
 def render_call(reps, seed=4):
     """The paper's render-call protocol (Sec. 6.6, Tab. render_call / render_breakdown):
     at 512^2, 1024^2 and 2048^2 with 1 bpp of packed records (n = H W / 128 sites), K = 8,
@@ -1141,6 +1221,7 @@ def main():
     if args.render_call_reps > 0:
         extra("render_call", render_call, args.render_call_reps)
         extra("packed_decode", packed_decode, args.render_call_reps)
+        extra("variants", variants, 10 * args.render_call_reps)
 
     if args.cpu_budget > 0:
         sites_np, lists_np = cpu_baseline_inputs(target_np)

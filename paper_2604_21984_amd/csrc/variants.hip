@@ -181,7 +181,20 @@ __global__ __launch_bounds__(256) void k1_render(int M, int n_slots, int64_t cap
                                                  const uint4 *__restrict__ topk,
                                                  const float *__restrict__ target,
                                                  float *__restrict__ out, float *__restrict__ grad,
-                                                 sad_loss_acc *__restrict__ loss) {
+                                                 sad_loss_acc *__restrict__ loss, FixScale fx) {
+    // The 256 samples of a block share few sites: their gradient terms meet in a block
+    // table keyed by site ID (64-bit fixed point in units of 2^-(32 + e), the image
+    // backward's table), flushed with one float atomic per (site, parameter); a term
+    // the table cannot take goes straight to global memory.
+    __shared__ uint32_t hkey[kHashSlots];
+    __shared__ unsigned long long hacc[4][kHashSlots];
+    const bool tab = grad != nullptr;   // the same for the whole launch
+    if (tab) {
+        hkey[threadIdx.x] = SAD_INVALID_ID;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) hacc[q][threadIdx.x] = 0ull;
+        __syncthreads();
+    }
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     float sq = 0.0f;
     if (m < M) {
@@ -236,20 +249,40 @@ __global__ __launch_bounds__(256) void k1_render(int M, int n_slots, int64_t cap
             const float res = c - target[m];
             sq = res * res;
             if (grad) {
-                const float gm = 2.0f * res / (float)M;
+                // dL/dc pre-scaled by 2^(32 + e): every term below arrives in table units
+                const float gm = (2.0f * res / (float)M) * fx.pre;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    if (!ok[k]) continue;
-                    const float4 q = rec[id[k]];
                     const float w = e[k] * inv;
+                    // all four terms are multiples of w: weight 0 adds exactly 0
+                    if (!ok[k] || w == 0.0f) continue;
+                    const float4 q = rec[id[k]];
                     const float gam = w * gm * ((col[k] - cr) - dc);
                     const float dx = X - q.x;
                     const float sg = dx > 0.0f ? 1.0f : (dx < 0.0f ? -1.0f : 0.0f);
-                    atomic_add_f32(grad + id[k], gam * q.z * sg);
-                    atomic_add_f32(grad + cap + id[k], w * gm);
-                    atomic_add_f32(grad + 2 * cap + id[k], gam * l[k]);
-                    atomic_add_f32(grad + 3 * cap + id[k], gam * q.z);
+                    const float t[4] = {gam * q.z * sg, w * gm, gam * l[k], gam * q.z};
+                    const int slot = hash_slot(hkey, id[k]);
+                    const float asum = fabsf(t[0]) + fabsf(t[1]) + fabsf(t[2]) + fabsf(t[3]);
+                    if (slot >= 0 && asum < kHiLimit) {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) atomicAdd(&hacc[c][slot], rint_i64(t[c]));
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            if (t[c] != 0.0f) atomic_add_f32(grad + c * cap + id[k], t[c] * fx.post);
+                    }
                 }
+            }
+        }
+    }
+    if (tab) {
+        __syncthreads();
+        const uint32_t sid = hkey[threadIdx.x];
+        if (sid != SAD_INVALID_ID) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const unsigned long long u = hacc[c][threadIdx.x];
+                if (u) atomic_add_f32(grad + c * cap + sid, from_fixed(u, fx.from_fix));
             }
         }
     }
@@ -426,9 +459,10 @@ extern "C" sad_status sad1d_render(const sad_signal *sg, const float *rec, const
     const uint4 *t4 = reinterpret_cast<const uint4 *>(topk);
     const int ns = sg->n_slots;
     const bool g = grad && ns > 0;
+    const FixScale fx = fix_scale(sg->M);
     SAD_K_SWITCH(sg->K, hipLaunchKernelGGL((k1_render<KK>), dim3(nblk(sg->M)), dim3(256), 0, st,
                                            sg->M, ns, sg->cap, r4, t4, target, out,
-                                           g ? grad : nullptr, loss));
+                                           g ? grad : nullptr, loss, fx));
     if (loss) hipLaunchKernelGGL(k1_loss_fold, dim3(1), dim3(64), 0, st, loss);
     return check_launch("sad1d_render");
 }
