@@ -28,9 +28,9 @@ HBM_PEAK_GBS = 8000.0
 # kernel sources they were taken with: HBM bytes per launch from FETCH_SIZE + WRITE_SIZE
 # scaled by a copy kernel's readings, and the utilisation counters.
 PROFILED = {
-    "76c95d27a6344271": {"traffic_bytes": 45000939, "valu_insts": 21896346,
-                         "counters": {"VALUBusy_pct": 53.1, "LDSBankConflict_pct": 17.1,
-                                      "OccupancyPercent": 47.9, "MemUnitStalled_pct": 0.08}},
+    "bea02ba5634830d3": {"traffic_bytes": 45000739, "valu_insts": 21896442,
+                         "counters": {"VALUBusy_pct": 51.6, "LDSBankConflict_pct": 16.6,
+                                      "OccupancyPercent": 46.4, "MemUnitStalled_pct": 0.08}},
 }
 # Vector-ALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s (one
 # non-packed float32 operation per lane; packed FMA makes the 157.3 TFLOP/s headline).
