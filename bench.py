@@ -561,11 +561,24 @@ def serving(rates, seconds, seed=0):
             specs.append((sid, M, int(rng.integers(0, (1 << 20) - M + 1))))
         return specs
 
+    out["plain_loop_by_rate"] = {}
     for rate in rates:
         times = V.poisson_arrivals(rate, seconds, rng)
         specs = draw(times)
         out["by_rate"][str(rate)] = rounded(served(specs, times))
         print(f"bench: serving at {rate} req/s done", file=sys.stderr, flush=True)
+        if rate != rates[-1]:
+            # the first 10 s of this stream, served again and through the plain loop
+            # (the highest rate gets the fuller comparison below)
+            n10 = sum(1 for t in times if t < 10.0)
+            if n10:
+                a = served(specs[:n10], times[:n10])
+                b = plain_loop(sets, make(specs[:n10]), times[:n10])
+                out["plain_loop_by_rate"][str(rate)] = {
+                    "requests": n10,
+                    "server": {"p50_ms": round(a["p50_ms"], 3), "p99_ms": round(a["p99_ms"], 3)},
+                    "plain_loop": {"p50_ms": round(b["p50_ms"], 3),
+                                   "p99_ms": round(b["p99_ms"], 3)}}
     # the same request stream (the highest rate's) served by a plain loop: each request
     # alone, in arrival order, launched and synchronised before the next; then both
     # with every request arriving at once (capacity)
