@@ -584,8 +584,9 @@ __device__ __forceinline__ void bwd_pixel(const float4 *__restrict__ rec, const 
         ws[k] = b.e[k] * invS;
         // every term of an entry is a multiple of its weight (the removal delta of a
         // non-reference entry too): an entry whose weight is 0 adds exactly 0, so it
-        // takes no table slot and no atomics
-        ids[k] = (b.ok[k] && ws[k] != 0.0f) ? b.id[k] : SAD_INVALID_ID;
+        // takes no table slot and no atomics (up to K = 8: at K = 16 the extra test
+        // costs more in the register-capped kernel than it saves)
+        ids[k] = (b.ok[k] && (K > 8 || ws[k] != 0.0f)) ? b.id[k] : SAD_INVALID_ID;
         ls[k] = b.l[k];
     }
 #pragma unroll 1

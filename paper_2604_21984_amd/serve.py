@@ -139,6 +139,9 @@ class GpuBackend:
         self._images = {}  # (set id, shape, K, slots, scale) -> sad_image descriptor
         self._events = []  # free events
         self._callers = {}  # stream id -> Stream object of a submitting stream
+        # torch's stream-id calls (no per-call device lookups); the public API otherwise
+        self._fast = all(hasattr(torch._C, f) for f in ("_cuda_getCurrentStream",
+                                                        "_cuda_setStream"))
 
     def now(self):
         return time.perf_counter()
@@ -147,14 +150,19 @@ class GpuBackend:
         return self._events.pop() if self._events else self.torch.cuda.Event()
 
     def _on(self, st):
-        return _OnStream(self.torch._C, st)
+        if self._fast:
+            return _OnStream(self.torch._C, st)
+        return self.torch.cuda.stream(st)
 
     def on_submit(self, req):
-        sid, di, dt = self.torch._C._cuda_getCurrentStream(self.dev)
-        caller = self._callers.get(sid)
-        if caller is None:
-            caller = self.torch.cuda.Stream(stream_id=sid, device_index=di, device_type=dt)
-            self._callers[sid] = caller
+        if self._fast:
+            sid, di, dt = self.torch._C._cuda_getCurrentStream(self.dev)
+            caller = self._callers.get(sid)
+            if caller is None:
+                caller = self.torch.cuda.Stream(stream_id=sid, device_index=di, device_type=dt)
+                self._callers[sid] = caller
+        else:
+            caller = self.torch.cuda.current_stream(self.device)
         ev = self._event()
         ev.record(caller)
         req.ready = ev
