@@ -62,6 +62,9 @@ class Autotuner:
             if "prop_every" in self.cache[sig]:
                 enc.set_prop_every(self.cache[sig]["prop_every"])
             return grid, chunked, self.cache[sig]["timings"]
+        if enc.cur != 0:
+            raise RuntimeError("tune after an even number of iterations (the trials record "
+                               "graphs of iteration pairs)")
         n_cu = torch.cuda.get_device_properties(enc.device).multi_processor_count
         orig = enc.snapshot()
         for _ in range(2 * ((max(0, warm) + 1) // 2)):

@@ -147,7 +147,12 @@ class BatchEncoder:
         self.steps += 1
 
     def capture(self):
-        assert self.cur == 0
+        """Record one pair of iterations as a HIP graph (the list field ping-pongs, so the
+        graph starts and ends on the first buffer: capture after an even number of
+        iterations)."""
+        if self.cur != 0:
+            raise RuntimeError("capture after an even number of iterations (the list "
+                               "field must be on its first buffer)")
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
