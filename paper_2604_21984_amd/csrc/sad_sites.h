@@ -152,6 +152,12 @@ __device__ __forceinline__ void adam_site_impl(float *__restrict__ sites,
     const float lo[SAD_NPARAM] = {0.f, 0.f, 2.f, 1.f, 0.f, 0.f, 0.f, -INFINITY, -INFINITY, -2.f};
     const float hi[SAD_NPARAM] = {(float)(W - 1), (float)(H - 1), 20.f, 512.f, 1.f, 1.f, 1.f,
                                   INFINITY, INFINITY, 2.f};
+    // One division per site for each bias correction and the hardware square root and
+    // reciprocal (1 ulp) per parameter: the update differs from the exactly rounded
+    // quotients by a few ulps of the step, far below the parity tolerance, and a site's
+    // chain of dependent instructions (one wave per SIMD at typical site counts) is
+    // much shorter than with ten IEEE divisions and square roots per quotient.
+    const float ic1 = 1.0f / c1, ic2 = 1.0f / c2;
     float th[SAD_NPARAM];
 #pragma unroll
     for (int p = 0; p < SAD_NPARAM; ++p) {
@@ -160,15 +166,17 @@ __device__ __forceinline__ void adam_site_impl(float *__restrict__ sites,
         const float vv = A.b2 * v0[p] + (1.0f - A.b2) * g[p] * g[p];
         m[o] = mm;
         v[o] = vv;
-        const float mh = mm / c1, vh = vv / c2;
-        float x = x0[p] - A.lr[p] * mh / (sqrtf(vh) + A.eps);
+        const float mh = mm * ic1, vh = vv * ic2;
+        const float den = __builtin_amdgcn_sqrtf(vh) + A.eps;
+        float x = x0[p] - A.lr[p] * mh * __builtin_amdgcn_rcpf(den);
         x = fminf(fmaxf(x, lo[p]), hi[p]);
         th[p] = x;
     }
     const float nu = sqrtf(th[7] * th[7] + th[8] * th[8]);
     if (nu > 0.f) {
-        th[7] /= nu;
-        th[8] /= nu;
+        const float inu = 1.0f / nu;
+        th[7] *= inu;
+        th[8] *= inu;
     } else {
         th[7] = 1.f;
         th[8] = 0.f;
