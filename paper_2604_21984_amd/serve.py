@@ -98,8 +98,9 @@ class _OnStream:
 
     def __enter__(self):
         st = self.st
-        self.prev = self.C._cuda_getCurrentStream(st.device_index)
-        if self.prev[0] == st.stream_id:
+        # the current device's current stream: restoring it also restores the device
+        self.prev = self.C._cuda_getCurrentStream(self.C._cuda_getDevice())
+        if self.prev[0] == st.stream_id and self.prev[1] == st.device_index:
             self.prev = None           # already current
             return
         self.C._cuda_setStream(stream_id=st.stream_id, device_index=st.device_index,
@@ -141,7 +142,7 @@ class GpuBackend:
         self._callers = {}  # stream id -> Stream object of a submitting stream
         # torch's stream-id calls (no per-call device lookups); the public API otherwise
         self._fast = all(hasattr(torch._C, f) for f in ("_cuda_getCurrentStream",
-                                                        "_cuda_setStream"))
+                                                        "_cuda_setStream", "_cuda_getDevice"))
 
     def now(self):
         return time.perf_counter()
