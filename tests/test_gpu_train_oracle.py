@@ -179,17 +179,18 @@ def _edge_case(name):
         sites = synth.random_sites(38, H, W, N, anisotropic=True, log_tau_range=(2.0, 4.0),
                                    r_range=(1.0, 3.0))
         return target, sites, H, W, K, N, O.default_scale(H, W)
-    if name == "ragged_k12":
-        H, W, N, K = 33, 47, 150, 12
-        target = synth.image_encode(39, H, W, n_polygons=8, patch=8)
-        sites = synth.random_sites(40, H, W, N, anisotropic=True, log_tau_range=(2.0, 7.0),
+    if name in ("ragged_k12", "ragged_k20", "ragged_k28"):
+        K = int(name[-2:])
+        H, W, N = 33, 47, 150 + 10 * K
+        target = synth.image_encode(39 + K, H, W, n_polygons=8, patch=8)
+        sites = synth.random_sites(40 + K, H, W, N, anisotropic=True, log_tau_range=(2.0, 7.0),
                                    r_range=(1.0, 4.0))
         return target, sites, H, W, K, N, O.default_scale(H, W)
     raise KeyError(name)
 
 
 @pytest.mark.parametrize("name", ["hard_limit", "all_hard", "k_ge_active", "k_eq_n",
-                                  "ragged_k12"])
+                                  "ragged_k12", "ragged_k20", "ragged_k28"])
 def test_fused_pass_edge_cases(S, name):
     """Free-running fused passes (each from the oracle's previous field) over the whole
     schedule and beyond; with K >= the active count the lists end equal to brute force."""
@@ -203,6 +204,24 @@ def test_fused_pass_edge_cases(S, name):
         lists = ref[0]
     if name in ("k_ge_active", "k_eq_n"):
         assert np.array_equal(lists, O.brute_topk(H, W, K, s, sites, N))
+
+
+@pytest.mark.parametrize("K", [4, 12, 16, 32])
+def test_fused_pass_deterministic_small(S, K):
+    """The deterministic fused pass at the other list lengths (each its own kernel
+    instance; K = 16 carries its own register cap) against the oracle, over the first
+    passes of the schedule from the seed pass."""
+    H, W, N, J, seed = 41, 67, 260, 3, 23
+    target = synth.image_encode(60 + K, H, W, n_polygons=9, patch=12)
+    sites = synth.random_sites(61 + K, H, W, N, anisotropic=True, log_tau_range=(2.0, 6.0),
+                               r_range=(1.0, 3.0))
+    s = O.default_scale(H, W)
+    lists = O.seed_lists(H, W, K, s, sites, N)
+    for t in range(5):
+        got = _fused(S, H, W, K, s, sites, N, lists, J, seed, t, target, deterministic=True)
+        ref = _oracle_pass(H, W, K, s, sites, N, lists, J, seed, t, target)
+        _compare(f"fused deterministic K={K} pass {t}", H, W, got, ref, det=True)
+        lists = ref[0]
 
 
 def test_fused_pass_2048_k16(S):
@@ -226,10 +245,12 @@ BATCH_SHAPES = [(64, 80, 300), (96, 50, 250), (130, 77, 520), (33, 47, 60), (16,
                 (70, 200, 700)]
 
 
-@pytest.mark.parametrize("grid,chunked,det,tile_w", [(0, 0, False, 16), (5, 1, False, 16),
-                                                     (0, 0, True, 16), (7, 0, True, 16),
-                                                     (0, 0, False, 32), (5, 1, True, 32)])
-def test_batch_step_matches_oracle_per_image(S, grid, chunked, det, tile_w):
+@pytest.mark.parametrize("grid,chunked,det,tile_w,K", [(0, 0, False, 16, 8), (5, 1, False, 16, 8),
+                                                       (0, 0, True, 16, 8), (7, 0, True, 16, 8),
+                                                       (0, 0, False, 32, 8), (5, 1, True, 32, 8),
+                                                       (0, 0, False, 16, 16), (5, 1, True, 32, 16),
+                                                       (0, 0, True, 16, 4)])
+def test_batch_step_matches_oracle_per_image(S, grid, chunked, det, tile_w, K):
     """sad_batch_train_step, image by image, against the oracle: every image starts from
     its own oracle field at its own pass index; lists, loss and gradient per image."""
     from paper_2604_21984_amd import batch as B
@@ -237,7 +258,7 @@ def test_batch_step_matches_oracle_per_image(S, grid, chunked, det, tile_w):
     J = 4
     targets = [synth.image_encode(50 + i, H, W, n_polygons=15, patch=16)
                for i, (H, W, _) in enumerate(BATCH_SHAPES)]
-    cfg = E.EncodeConfig(K=8, n_inject=J, seed=6, deterministic=det)
+    cfg = E.EncodeConfig(K=K, n_inject=J, seed=6, deterministic=det)
     be = B.BatchEncoder([_t(x) for x in targets], [n for _, _, n in BATCH_SHAPES], cfg,
                         grid=grid, chunked=chunked, tile_w=tile_w)
     be.adam = S.adam_params([0.0] * 10, cfg.beta1, cfg.beta2, cfg.eps)
@@ -249,13 +270,13 @@ def test_batch_step_matches_oracle_per_image(S, grid, chunked, det, tile_w):
         sites = synth.perturb_sites(60 + b, synth.random_sites(70 + b, H, W, N, log_tau=4.0,
                                                                r=1.0), N, H, W)
         t = 3 * b                           # each image at its own pass index
-        F = _fields(H, W, 8, s, sites, N, J, seed, t)
+        F = _fields(H, W, K, s, sites, N, J, seed, t)
         be.view_sites(b).copy_(_t(sites))
         S.prepare_sites(be.img(b), be.view_sites(b), be.view_rec(b))
-        be.view_list(be.cur, b).copy_(_t(rows_to_planar(F[t], H, W, 8)))
+        be.view_list(be.cur, b).copy_(_t(rows_to_planar(F[t], H, W, K)))
         be.state(b).zero_()
         be.state(b)[0] = t
-        refs.append(_oracle_pass(H, W, 8, s, sites, N, F[t], J, seed, t, targets[b]))
+        refs.append(_oracle_pass(H, W, K, s, sites, N, F[t], J, seed, t, targets[b]))
     be.m.zero_()
     be.v.zero_()
     be.grad.zero_()
@@ -265,12 +286,13 @@ def test_batch_step_matches_oracle_per_image(S, grid, chunked, det, tile_w):
     b1 = np.float64(np.float32(1.0) - np.float32(cfg.beta1))
     for b, (H, W, N) in enumerate(BATCH_SHAPES):
         rlists, rcol, rL, rg, rgrad, ab = refs[b]
-        lists = planar_to_rows(be.view_list(be.cur, b).cpu().numpy(), H, W, 8)
+        lists = planar_to_rows(be.view_list(be.cur, b).cpu().numpy(), H, W, K)
         assert np.array_equal(lists, rlists), f"image {b}: lists differ"
         assert abs(losses[b] - rL) <= 1e-5 * rL, (b, losses[b], rL)
         m = be.view_sites(b, be.m).cpu().numpy().astype(np.float64)
         if det:  # the deterministic mode's per-term rounding at this image's own P
             ab = ab + _det_quantum(H, W, rlists, ab.shape[1])[None, :] / 1e-5
         w, plain, rep = grad_check(m / b1, rgrad, ab,
-                                   f"batch grid={grid} chunked={chunked} det={det} tile={tile_w} image {b}")
+                                   f"batch grid={grid} chunked={chunked} det={det} tile={tile_w} "
+                                   f"K={K} image {b}")
         assert w <= 1.0, f"image {b}: gradient mismatch ratio {w}\n{rep}"
