@@ -333,3 +333,41 @@ def test_large_image_k16_parity(S):
                             abs_sum=True)
     w, rep = grad_report(gg, gref, ab)
     assert w <= 1.0, rep
+
+
+def test_queries_and_render_at_the_largest_serving_set(S):
+    """The largest resident set of the serving workload (4096 x 4096, 0.05 sites per
+    pixel: 838 861 sites, K = 8), its lists from a full refresh (JFA prepass and 16
+    passes): 4096 random point queries (sad_query_points) and the render (sad_render_fwd)
+    at 4096 sampled pixels against the oracle's queries at the same points, one by one."""
+    H = W = 4096
+    K, N = 8, int(round(0.05 * H * W))
+    s = O.default_scale(H, W)
+    print(f"largest serving set: {H}x{W}, {N} sites", flush=True)
+    sites = synth.perturb_sites(12, synth.random_sites(11, H, W, N, log_tau=5.5, r=1.0),
+                                N, H, W)
+    img = S.image(H, W, K, N, N, s)
+    sd = _t(sites)
+    rec = torch.empty(N * S.REC_FLOATS, dtype=torch.float32, device=DEV)
+    S.prepare_sites(img, sd, rec)
+    a = torch.empty((K // 4, H, W, 4), dtype=torch.int32, device=DEV)
+    b = torch.empty_like(a)
+    scratch = torch.empty(H * W, dtype=torch.int64, device=DEV)
+    S.refresh(img, H, W, rec, a, b, scratch, 16, 4, 3, jfa=True)
+    del b, scratch
+    rng = np.random.default_rng(13)
+    xy = np.stack([rng.uniform(0, W - 1, 4096), rng.uniform(0, H - 1, 4096)], 1).astype(np.float32)
+    q = torch.empty((len(xy), 3), dtype=torch.float32, device=DEV)
+    S.query_points(img, rec, a, _t(xy), q)
+    out = torch.empty((3, H, W), dtype=torch.float32, device=DEV)
+    S.render_fwd(img, rec, a, out)
+    pi, pj = rng.integers(0, H, 4096), rng.integers(0, W, 4096)
+    rendered = out[:, torch.from_numpy(pi).to(DEV), torch.from_numpy(pj).to(DEV)].T.cpu().numpy()
+    torch.cuda.synchronize()
+    rows = planar_to_rows(a.cpu().numpy(), H, W, K)
+    del a, out
+    ref_q = O.query(H, W, K, s, sites, N, rows, xy)
+    assert np.abs(q.cpu().numpy() - ref_q).max() <= 1e-5
+    centres = np.stack([pj, pi], 1).astype(np.float32)
+    ref_r = O.query(H, W, K, s, sites, N, rows, centres)
+    assert np.abs(rendered - ref_r).max() <= 1e-5
