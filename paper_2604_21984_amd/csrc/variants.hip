@@ -183,9 +183,11 @@ __global__ __launch_bounds__(256) void k1_render(int M, int n_slots, int64_t cap
                                                  float *__restrict__ out, float *__restrict__ grad,
                                                  sad_loss_acc *__restrict__ loss, FixScale fx) {
     // The 256 samples of a block share few sites: their gradient terms meet in a block
-    // table keyed by site ID (64-bit fixed point in units of 2^-(32 + e), the image
-    // backward's table), flushed with one float atomic per (site, parameter); a term
-    // the table cannot take goes straight to global memory.
+    // table keyed by site ID (64-bit fixed point in units of 2^-(40 + e), 2^e ~ M / 2:
+    // finer than the image table's unit, since a 1-D site's gradient is a sum of few
+    // small terms; a term below 2^51 units converts exactly and 256 of them stay below
+    // 2^59), flushed with one float atomic per (site, parameter); a term the table
+    // cannot take goes straight to global memory.
     __shared__ uint32_t hkey[kHashSlots];
     __shared__ unsigned long long hacc[4][kHashSlots];
     const bool tab = grad != nullptr;   // the same for the whole launch
@@ -249,7 +251,7 @@ __global__ __launch_bounds__(256) void k1_render(int M, int n_slots, int64_t cap
             const float res = c - target[m];
             sq = res * res;
             if (grad) {
-                // dL/dc pre-scaled by 2^(32 + e): every term below arrives in table units
+                // dL/dc pre-scaled by 2^(40 + e): every term below arrives in table units
                 const float gm = (2.0f * res / (float)M) * fx.pre;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
@@ -263,7 +265,7 @@ __global__ __launch_bounds__(256) void k1_render(int M, int n_slots, int64_t cap
                     const float t[4] = {gam * q.z * sg, w * gm, gam * l[k], gam * q.z};
                     const int slot = hash_slot(hkey, id[k]);
                     const float asum = fabsf(t[0]) + fabsf(t[1]) + fabsf(t[2]) + fabsf(t[3]);
-                    if (slot >= 0 && asum < kHiLimit) {
+                    if (slot >= 0 && asum < 0x1p51f) {
 #pragma unroll
                         for (int c = 0; c < 4; ++c) atomicAdd(&hacc[c][slot], rint_i64(t[c]));
                     } else {
@@ -459,7 +461,11 @@ extern "C" sad_status sad1d_render(const sad_signal *sg, const float *rec, const
     const uint4 *t4 = reinterpret_cast<const uint4 *>(topk);
     const int ns = sg->n_slots;
     const bool g = grad && ns > 0;
-    const FixScale fx = fix_scale(sg->M);
+    FixScale fx = fix_scale(sg->M);   // the 1-D table's finer unit 2^-(40 + e)
+    const int e = fix_exponent(sg->M);
+    fx.pre = std::ldexp(1.0f, 40 + e);
+    fx.post = std::ldexp(1.0f, -(40 + e));
+    fx.from_fix = std::ldexp(1.0, -(40 + e));
     SAD_K_SWITCH(sg->K, hipLaunchKernelGGL((k1_render<KK>), dim3(nblk(sg->M)), dim3(256), 0, st,
                                            sg->M, ns, sg->cap, r4, t4, target, out,
                                            g ? grad : nullptr, loss, fx));

@@ -91,7 +91,7 @@ def _rows1(f, M, K):
 
 
 @pytest.mark.parametrize("M,n,K,J", [(300, 40, 4, 2), (5000, 600, 8, 4), (777, 900, 16, 3),
-                                     (64, 3, 8, 1)])
+                                     (64, 3, 8, 1), (1 << 20, 1 << 16, 8, 4)])
 def test_1d_seed_and_propagation_lockstep_bit_exact(S, M, n, K, J):
     sites = synth.sites1d(5 + K, M, n, cap=n + 3)
     sites[0, 1] = -1.0
@@ -116,8 +116,12 @@ def test_1d_seed_and_propagation_lockstep_bit_exact(S, M, n, K, J):
         assert np.array_equal(cur, O.brute_topk1d(M, K, s, sites, n))
 
 
-@pytest.mark.parametrize("M,n,K", [(400, 50, 4), (6000, 700, 8), (999, 300, 16)])
+@pytest.mark.parametrize("M,n,K", [(400, 50, 4), (6000, 700, 8), (999, 300, 16),
+                                   (777, 900, 16), (1 << 20, 1 << 16, 8)])
 def test_1d_render_loss_gradients(S, M, n, K):
+    """Colours, loss and gradients against the oracle; (777, 900, 16) holds more sites
+    per block than the block table's 256 slots (terms overflow to global atomics), and
+    (2^20, 2^16, 8) is the size the benchmark times."""
     sites = synth.sites1d(11 + K, M, n)
     sites[0, 3] = -1.0
     s = O.scale1d(M)
