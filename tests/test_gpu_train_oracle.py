@@ -224,12 +224,14 @@ def test_fused_pass_deterministic_small(S, K):
         lists = ref[0]
 
 
-def test_fused_pass_2048_k16(S):
-    """2048x2048, N = 100 000 (oracle initialisation, moved), K = 16, J = 4: the fused
+@pytest.mark.parametrize("N", [100_000, 400_000])
+def test_fused_pass_2048_k16(S, N):
+    """2048x2048, N = 100 000 and 400 000 (the start and the capacity of the large
+    budget-controlled encode; oracle initialisation, moved), K = 16, J = 4: the fused
     pass at pass 2 from the oracle's field after the seed pass and two passes, whole
     field (the K = 16 kernel carries its own register cap)."""
     H = W = 2048
-    N, K, J, seed = 100_000, 16, 4, 9
+    K, J, seed = 16, 4, 9
     target = synth.image_large(0, H, W)
     lt0 = float(np.clip(math.log(2 * max(H, W) / math.sqrt(H * W / N)), 2, 20))
     sites, _ = O.init_sites(target, N, 0.3, 3, lt0, 1.0, N)
@@ -238,7 +240,7 @@ def test_fused_pass_2048_k16(S):
     F = _fields(H, W, K, s, sites, N, J, seed, 2)
     got = _fused(S, H, W, K, s, sites, N, F[2], J, seed, 2, target)
     ref = _oracle_pass(H, W, K, s, sites, N, F[2], J, seed, 2, target)
-    _compare("fused K=16 2048x2048 pass 2", H, W, got, ref)
+    _compare(f"fused K=16 2048x2048 N={N} pass 2", H, W, got, ref)
 
 
 BATCH_SHAPES = [(64, 80, 300), (96, 50, 250), (130, 77, 520), (33, 47, 60), (16, 16, 12),
