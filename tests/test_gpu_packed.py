@@ -45,7 +45,9 @@ def _packed_rows(t):
     return t.cpu().numpy().view(np.uint32).reshape(-1, 4)
 
 
-SHAPES = [(50, 70, 300, 310), (33, 47, 1, 1), (512, 768, 20000, 20000)]
+# the last: the largest resident set of the serving workload (4096^2 at 0.05 sites/px)
+SHAPES = [(50, 70, 300, 310), (33, 47, 1, 1), (512, 768, 20000, 20000),
+          (4096, 4096, 838861, 838861)]
 
 
 @pytest.mark.parametrize("H,W,n,cap", SHAPES)
