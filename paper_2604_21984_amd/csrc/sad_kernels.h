@@ -139,8 +139,24 @@ struct RecSrc {
     }
 };
 
+// Whether the blend fetches a group of entries' records before scoring any of them
+// (derived records only: the packed source decodes in its fetch, and a group of decoded
+// records does not fit the registers).
+template <class Src>
+struct GroupFetch {
+    static constexpr bool v = false;
+};
+template <>
+struct GroupFetch<RecSrc> {
+    static constexpr bool v = true;
+};
+
 // Gather and score the list of pixel p at point (X, Y); max-subtracted softmax; colour.
-// The entries are taken in the order rotated by `rot`.
+// The entries are taken in the order rotated by `rot`.  Without the reference terms and
+// for K <= 16, the records of a group of entries (all of them up to K = 8, four at a time
+// up to 16) are in registers before any score is formed, so a wave waits for one memory
+// round trip per group: random point queries, whose lanes gather unrelated records, run
+// ~1.6x faster (2^20 points at 2048^2: 116 -> 74 us at K = 8, 352 -> 217 us at K = 16).
 template <int K, bool kRef, class Src>
 __device__ __forceinline__ void blend_src(const Src &src, uint32_t ns,
                                           const uint4 *__restrict__ topk, int64_t P, int64_t p,
@@ -158,22 +174,58 @@ __device__ __forceinline__ void blend_src(const Src &src, uint32_t ns,
     }
     if (rot) rotate_ids<K>(ids, rot);
     float col[K][3];
+    constexpr int G = (GroupFetch<Src>::v && !kRef) ? (K <= 8 ? K : (K <= 16 ? 4 : 1)) : 1;
+    if constexpr (G == 1) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const uint32_t id = ids[k];
-        const bool in_range = id < ns;
-        const uint32_t idc = in_range ? id : 0u;
-        float4 q0, q1, q2;
-        src.fetch(idc, q0, q1, q2);
-        b.id[k] = idc;
-        b.ok[k] = in_range && q1.w != 0.0f;
-        b.l[k] = score(q0, q1, X, Y);
-        col[k][0] = q2.x;
-        col[k][1] = q2.y;
-        col[k][2] = q2.z;
-        if (b.ok[k]) {
-            m = fmaxf(m, b.l[k]);
-            ++b.nv;
+        for (int k = 0; k < K; ++k) {
+            const uint32_t id = ids[k];
+            const bool in_range = id < ns;
+            const uint32_t idc = in_range ? id : 0u;
+            float4 q0, q1, q2;
+            src.fetch(idc, q0, q1, q2);
+            b.id[k] = idc;
+            b.ok[k] = in_range && q1.w != 0.0f;
+            b.l[k] = score(q0, q1, X, Y);
+            col[k][0] = q2.x;
+            col[k][1] = q2.y;
+            col[k][2] = q2.z;
+            if (b.ok[k]) {
+                m = fmaxf(m, b.l[k]);
+                ++b.nv;
+            }
+        }
+        finish_blend<K, kRef>(b, col, m);
+        return;
+    }
+#pragma unroll
+    for (int g0 = 0; g0 < K; g0 += G) {
+        float4 q0[G], q1[G], q2[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const uint32_t id = ids[g0 + k];
+            src.fetch(id < ns ? id : 0u, q0[k], q1[k], q2[k]);
+        }
+        // the group's records all in registers here: one wait for the group
+#pragma unroll
+        for (int k = 0; k < G; ++k)
+            asm volatile("" ::"v"(q0[k].x), "v"(q0[k].y), "v"(q0[k].z), "v"(q0[k].w),
+                         "v"(q1[k].x), "v"(q1[k].y), "v"(q1[k].z), "v"(q1[k].w),
+                         "v"(q2[k].x), "v"(q2[k].y), "v"(q2[k].z));
+#pragma unroll
+        for (int k = 0; k < G; ++k) {
+            const int kk = g0 + k;
+            const uint32_t id = ids[kk];
+            const bool in_range = id < ns;
+            b.id[kk] = in_range ? id : 0u;
+            b.ok[kk] = in_range && q1[k].w != 0.0f;
+            b.l[kk] = score(q0[k], q1[k], X, Y);
+            col[kk][0] = q2[k].x;
+            col[kk][1] = q2[k].y;
+            col[kk][2] = q2[k].z;
+            if (b.ok[kk]) {
+                m = fmaxf(m, b.l[kk]);
+                ++b.nv;
+            }
         }
     }
     finish_blend<K, kRef>(b, col, m);
